@@ -1,0 +1,185 @@
+"""Vertex-patch additive Schwarz preconditioner with LOR patch V-cycles.
+
+eq. as: B = sum_{j=0}^J R_j Q_j.  j = 0 is the coarse space V_0 (Q1 on the
+original mesh T_p); j >= 1 are the vertex patches (eq. patch) carrying the
+LOR space with homogeneous Dirichlet conditions on the patch boundary, each
+solved approximately by one element-structured V-cycle (Section 3.3) with
+MDF-ordered ILU(0) smoothing (Section 3.4).  eq. dg-as extends it to DG.
+
+Readings (the paper is silent or uses a component that is not available):
+* one patch per mesh vertex, boundary vertices included; the patch unknowns
+  at level k are the level-k grid points strictly inside the union of the
+  elements around the vertex and not on the domain boundary;
+* patch matrices are principal sub-matrices of the global level matrices;
+* V-cycle: one IC(0) pre-smoothing step from zero, residual, restriction,
+  recursion, prolongation, one IC(0) post-smoothing step; the coarsest patch
+  level (at most one unknown) is solved exactly;
+* the coarse operator is the Galerkin product A_0 = P_0^T K_h P_0 with P_0
+  the Q1 interpolation of the element vertices, and it is solved exactly
+  (the paper uses one AMG V-cycle here);
+* the patch corrections are summed without weights (eq. as);
+* DG (eq. dg-as): V_p taken as the Dirichlet-conforming space injected by
+  copying node values (E), R_B is point Jacobi with diag(A_DG) on the nodes
+  with some local index in {0, p}.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from . import lor as _lor
+from . import mdf as _mdf
+from . import mesh as _mesh
+from . import highorder as _ho
+
+
+def patch_ranges(mesh, s: int, v):
+    """Per-direction inclusive [lo, hi] level-grid ranges of the patch of vertex v."""
+    out = []
+    for i in range(mesh.dim):
+        n = mesh.n[i]
+        lo = (v[i] - 1) * s + 1 if v[i] > 0 else 1
+        hi = (v[i] + 1) * s - 1 if v[i] < n else n * s - 1
+        out.append((lo, hi))
+    return out
+
+
+def vertices(mesh):
+    """Vertex multi-indices in lexicographic order (x fastest)."""
+    shape = [m + 1 for m in mesh.n]
+    for flat in range(int(np.prod(shape))):
+        v, r = [], flat
+        for i in range(mesh.dim):
+            v.append(r % shape[i])
+            r //= shape[i]
+        yield tuple(v)
+
+
+class Patch:
+    """All levels of one vertex patch: graphs, MDF factors, transfers."""
+
+    def __init__(self, H: _lor.LORHierarchy, v, exact_local: bool = False):
+        mesh = H.mesh
+        dim = mesh.dim
+        self.v = v
+        self.levels = []
+        for k in range(H.nlevels):
+            rng = patch_ranges(mesh, H.sizes[k], v)
+            shape = [hi - lo + 1 for lo, hi in rng]
+            if min(shape) <= 0:
+                shape = [0] * dim
+            idx = np.indices(shape).reshape(dim, -1, order="F") if min(shape) > 0 else np.zeros((dim, 0), int)
+            gl = [idx[i] + rng[i][0] for i in range(dim)]
+            flat = _mesh.lex_index(gl, H.shapes[k]) if idx.shape[1] else np.zeros(0, np.int64)
+            g = _mdf.PatchGraph(shape, H.stencils[k][flat]) if idx.shape[1] else None
+            self.levels.append(dict(range=rng, shape=shape, flat=flat, graph=g))
+        self.exact_local = exact_local
+        nl = H.nlevels
+        for k in range(nl):
+            lv = self.levels[k]
+            g = lv["graph"]
+            if g is None:
+                continue
+            lv["A"] = g.dense()
+            if k == nl - 1 or exact_local:
+                lv["Ainv"] = np.linalg.inv(lv["A"])
+            else:
+                lv["order"], lv["L"], lv["D"] = _mdf.mdf_factor(g)
+        for k in range(nl - 1):
+            f, c = self.levels[k], self.levels[k + 1]
+            if f["graph"] is None or c["graph"] is None:
+                f["P"] = None
+                continue
+            mats = []
+            for i in range(dim):
+                P1 = _lor.interp_1d(mesh, H.p, k, i)
+                (flo, fhi), (clo, chi) = f["range"][i], c["range"][i]
+                mats.append(P1[flo:fhi + 1, clo:chi + 1])
+            f["P"] = _lor.kron_x_fastest(mats)
+
+    def smooth(self, k, r):
+        lv = self.levels[k]
+        return _mdf.ic0_solve(lv["graph"], lv["order"], lv["L"], lv["D"], r)
+
+    def vcycle(self, k, b):
+        lv = self.levels[k]
+        if lv["graph"] is None:
+            return np.zeros(0)
+        if "Ainv" in lv:
+            return lv["Ainv"] @ b
+        A = lv["A"]
+        x = self.smooth(k, b)
+        if lv.get("P") is not None:
+            r = b - A @ x
+            xc = self.vcycle(k + 1, lv["P"].T @ r)
+            x = x + lv["P"] @ xc
+        r = b - A @ x
+        return x + self.smooth(k, r)
+
+    def solve(self, r_patch):
+        return self.vcycle(0, r_patch)
+
+
+class CoarseSpace:
+    """V_0: Q1 on T_p, P_0 = vertex interpolation, A_0 = P_0^T K_h P_0, exact solve."""
+
+    def __init__(self, H: _lor.LORHierarchy, Kh: sp.csr_matrix):
+        mesh = H.mesh
+        dim = mesh.dim
+        mats = [_lor.coarse_interp_1d(mesh, H.p, i) for i in range(dim)]
+        P = _lor.kron_x_fastest(mats)
+        fnum = _mesh.interior_numbering(H.shapes[0])
+        cnum = _mesh.interior_numbering([m + 1 for m in mesh.n])
+        P = P[np.flatnonzero(fnum >= 0)][:, np.flatnonzero(cnum >= 0)]
+        self.P = sp.csr_matrix(P)
+        self.A0 = (self.P.T @ Kh @ self.P).toarray()
+        self.n = self.A0.shape[0]
+        self.chol = sla.cho_factor(self.A0) if self.n else None
+
+    def apply(self, r):
+        if self.n == 0:
+            return np.zeros_like(r)
+        return self.P @ sla.cho_solve(self.chol, self.P.T @ r)
+
+
+class SchwarzLOR:
+    """z = B r for the conforming problem on the Dirichlet unknowns."""
+
+    def __init__(self, mesh, p: int, exact_local: bool = False, coarse: bool = True):
+        self.H = _lor.LORHierarchy(mesh, p)
+        self.Kh = self.H.matrix(0)
+        self.fnum = _mesh.interior_numbering(self.H.shapes[0])
+        self.coarse = CoarseSpace(self.H, self.Kh) if coarse else None
+        self.patches = [Patch(self.H, v, exact_local) for v in vertices(mesh)]
+
+    def apply(self, r: np.ndarray, with_coarse: bool = True, with_patches: bool = True) -> np.ndarray:
+        z = np.zeros_like(r)
+        if with_coarse and self.coarse is not None:
+            z += self.coarse.apply(r)
+        if with_patches:
+            for P in self.patches:
+                lv = P.levels[0]
+                if lv["graph"] is None:
+                    continue
+                u = self.fnum[lv["flat"]]
+                z[u] += P.solve(r[u])
+        return z
+
+    def as_matrix(self, **kw) -> np.ndarray:
+        n = self.Kh.shape[0]
+        return np.column_stack([self.apply(np.eye(n)[:, i], **kw) for i in range(n)])
+
+
+class SchwarzDG:
+    """z = B_DG r = Pi_B^T D_B^-1 Pi_B r + E B E^T r  (eq. dg-as)."""
+
+    def __init__(self, mesh, p: int, A_dg: sp.csr_matrix, **kw):
+        self.B = SchwarzLOR(mesh, p, **kw)
+        self.E = _ho.cg_to_dg(mesh, p)
+        self.mask = _ho.dg_boundary_mask(mesh, p)
+        self.diag = A_dg.diagonal()
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        z = np.where(self.mask, r / self.diag, 0.0)
+        return z + self.E @ self.B.apply(self.E.T @ r)

@@ -1,0 +1,65 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module holds no arithmetic of the method itself: it only produces the
+problem data that the paper's experiments are shaped like (Section 4):
+structured quad/hex meshes of the unit square/cube with optionally perturbed
+interior vertices, the manufactured solution u = prod_i sin(pi x_i) with its
+forcing f = -Laplace(u), and Gaussian right-hand sides.
+
+It imports nothing from the rest of the package, so the CPU oracle and the GPU
+path can both be fed from it without depending on each other.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def structured_vertices(dim: int, n, perturb: float = 0.0, seed=None) -> np.ndarray:
+    """Vertex coordinates of an n^dim block of quads/hexes on [0,1]^dim.
+
+    Returns an array of shape (prod(n_i+1), dim), float64, vertices ordered
+    lexicographically with x fastest.  When ``perturb`` > 0, every vertex not
+    on the boundary is moved by h_i * U(-perturb, perturb) in each coordinate
+    i, drawn from ``numpy.random.default_rng(seed)`` in vertex order, one
+    coordinate after the other (h_i = 1/n_i).  ``perturb`` = 0.1 is the
+    "interior vertices randomly perturbed by at most 10% of h" recipe.
+    """
+    if dim not in (2, 3):
+        raise ValueError("dim must be 2 or 3")
+    n = [int(n)] * dim if np.isscalar(n) else [int(v) for v in n]
+    if len(n) != dim or min(n) < 1:
+        raise ValueError("bad element counts")
+    axes = [np.linspace(0.0, 1.0, ni + 1) for ni in n]
+    grids = np.meshgrid(*axes, indexing="ij")
+    # lexicographic with x fastest: flatten in Fortran order over (x, y, z)
+    xyz = np.stack([g.reshape(-1, order="F") for g in grids], axis=1).copy()
+    if perturb > 0.0:
+        rng = np.random.default_rng(seed)
+        shape = [ni + 1 for ni in n]
+        idx = np.indices(shape).reshape(dim, -1, order="F").T
+        interior = np.all((idx > 0) & (idx < np.array(n)), axis=1)
+        h = 1.0 / np.array(n, dtype=np.float64)
+        disp = rng.uniform(-perturb, perturb, size=(int(interior.sum()), dim))
+        xyz[interior] += disp * h
+    return xyz
+
+
+def manufactured_u(x: np.ndarray) -> np.ndarray:
+    """u(x) = prod_i sin(pi x_i), which vanishes on the boundary of [0,1]^d."""
+    return np.prod(np.sin(np.pi * x), axis=1)
+
+
+def manufactured_f(x: np.ndarray) -> np.ndarray:
+    """f = -Laplace(u) = d * pi^2 * prod_i sin(pi x_i)."""
+    d = x.shape[1]
+    return d * np.pi ** 2 * np.prod(np.sin(np.pi * x), axis=1)
+
+
+def gaussian_rhs(n: int, seed: int) -> np.ndarray:
+    """i.i.d. N(0,1) right-hand side of length n (float64)."""
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+def uniform_vector(n: int, seed: int) -> np.ndarray:
+    """i.i.d. U(-1,1) vector of length n (float64), used as operator input."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, n)

@@ -1,0 +1,107 @@
+"""Pins of the vertex-patch additive Schwarz preconditioner (eq. as, Section 3.2),
+its patch V-cycles (Section 3.3) and the coarse space."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import highorder as HO, lor, mesh as M, schwarz as S
+from paper_1908_07071_amd import inputs
+
+
+def _mesh(dim, n, pert=0.1, seed=5):
+    return M.make_mesh(dim, n, inputs.structured_vertices(dim, n, pert, seed=seed))
+
+
+def test_patch_counts_closed_form():
+    """Per direction a patch has 2s-1 unknowns (interior vertex) or s-1
+    (boundary vertex); at 16^3 elements and p = 6 the level-0 patches hold
+    5,359,375 rows in total and every element lies in 2^d patches."""
+    mesh = M.make_mesh(3, 16, inputs.structured_vertices(3, 16))
+    s = lor.level_sizes(6)
+    tot = []
+    for k in range(len(s)):
+        per_dir = sum(hi - lo + 1 for lo, hi in (S.patch_ranges(mesh, s[k], (v, 0, 0))[0:1][0] for v in range(17)))
+        tot.append(per_dir ** 3)
+    assert tot[0] == 5_359_375
+    assert tot == [5_359_375, 493_039, 103_823, 3_375]
+    m = M.make_mesh(2, 3, inputs.structured_vertices(2, 3))
+    count = np.zeros((3, 3), int)
+    for v in S.vertices(m):
+        for ex in range(3):
+            for ey in range(3):
+                if v[0] in (ex, ex + 1) and v[1] in (ey, ey + 1):
+                    count[ex, ey] += 1
+    assert np.all(count == 4)
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, 3, 4), (3, 2, 3)])
+def test_every_unknown_covered(dim, n, p):
+    B = S.SchwarzLOR(_mesh(dim, n), p, coarse=False)
+    cover = np.zeros(B.Kh.shape[0], int)
+    for P in B.patches:
+        if P.levels[0]["graph"] is not None:
+            cover[B.fnum[P.levels[0]["flat"]]] += 1
+    assert cover.min() >= 1 and cover.max() <= 2 ** dim
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, 3, 4), (3, 2, 3)])
+def test_vcycle_symmetric_positive(dim, n, p):
+    B = S.SchwarzLOR(_mesh(dim, n), p)
+    rng = np.random.default_rng(0)
+    for P in B.patches:
+        lv = P.levels[0]
+        if lv["graph"] is None:
+            continue
+        m = lv["graph"].n
+        x, y = rng.standard_normal(m), rng.standard_normal(m)
+        a, b = x @ P.solve(y), y @ P.solve(x)
+        assert abs(a - b) <= 1e-12 * (abs(a) + abs(b) + 1e-300)
+        assert x @ P.solve(x) > 0
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, 3, 3), (3, 2, 2)])
+def test_overlap_bound(dim, n, p):
+    """Finite overlap (Section 3.2): lambda_max(B K_h) <= 2^d + 1 with exact
+    local solves, and B is symmetric."""
+    B = S.SchwarzLOR(_mesh(dim, n), p, exact_local=True)
+    Bm = B.as_matrix()
+    assert np.abs(Bm - Bm.T).max() <= 1e-12 * np.abs(Bm).max()
+    Kh = B.Kh.toarray()
+    ev = np.real(sla.eigvals(Bm @ Kh))
+    assert ev.max() <= 2 ** dim + 1 + 1e-10
+    assert ev.min() > 0
+
+
+def test_coarse_operator_closed_form():
+    """On an affine mesh the nested Galerkin A_0 = P_0^T K_h P_0 is the exact Q1
+    stiffness on T_p: sum_j (x) (K1D_H in slot j, M1D_H elsewhere)."""
+    dim, n, p = 2, 4, 3
+    mesh = M.make_mesh(dim, n, inputs.structured_vertices(dim, n))
+    H = lor.LORHierarchy(mesh, p)
+    C = S.CoarseSpace(H, H.matrix(0))
+    h = 1.0 / n
+    K1 = (np.diag(2 * np.ones(n - 1)) - np.diag(np.ones(n - 2), 1) - np.diag(np.ones(n - 2), -1)) / h
+    M1 = (np.diag(4 * np.ones(n - 1)) + np.diag(np.ones(n - 2), 1) + np.diag(np.ones(n - 2), -1)) * h / 6
+    ref = np.kron(M1, K1) + np.kron(K1, M1)
+    assert np.abs(C.A0 - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def _kappa(dim, n, p):
+    mesh = _mesh(dim, n)
+    Kp = HO.cg_stiffness(mesh, p).toarray()
+    Bm = S.SchwarzLOR(mesh, p).as_matrix()
+    ev = np.sort(np.real(sla.eigvals(Bm @ Kp)))
+    return ev[-1] / ev[0], ev
+
+
+@pytest.mark.slow
+def test_kappa_bounded_in_h_and_p():
+    """Cor. as: kappa(B A_p) bounded independently of h and p (compared at the
+    larger sizes; small n and p are pre-asymptotic)."""
+    k_n2, _ = _kappa(2, 2, 4)
+    k_n4, ev = _kappa(2, 4, 4)
+    assert ev[0] > 0
+    assert k_n4 / k_n2 <= 1.25
+    k_p6, _ = _kappa(2, 2, 6)
+    assert k_p6 / k_n2 <= 1.35
+    assert k_n4 < 25 and k_p6 < 25
