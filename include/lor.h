@@ -1,0 +1,198 @@
+/*
+ * lor.h -- C ABI of the MI355X LOR-Schwarz preconditioned conjugate gradient
+ * library (Pazner, "Efficient low-order refined preconditioners for high-order
+ * matrix-free continuous and discontinuous Galerkin methods").
+ *
+ * The library solves the high-order Poisson problem of Section 2,
+ *     -div(grad u) = f in Omega,  u = 0 on the boundary        (eq. poisson)
+ * discretized with continuous Galerkin (eq. fem / eq. system), symmetric
+ * interior penalty DG (eq. ip) or BR2 DG (eq. br2) on Gauss-Lobatto (GLL)
+ * tensor-product elements, by conjugate gradients preconditioned with the
+ * overlapping vertex-patch additive Schwarz method of eq. as (eq. dg-as for
+ * DG), whose patch solvers are element-structured multigrid V-cycles on the
+ * low-order refined operator with MDF-ordered ILU(0) smoothing
+ * (Sections 3.1-3.4).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * - Every function returns an int status: LOR_OK (0) or a negative LOR_E*
+ *   code.  No function throws or aborts across the ABI.  lor_error_string()
+ *   gives a static description.
+ * - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *   memory of the current device (for example torch tensors' data_ptr()).
+ *   The caller owns every buffer it passes; the library never frees them.
+ * - "stream" is a hipStream_t passed as void*; NULL means the default stream.
+ *   Work is enqueued on that stream; functions that return host results
+ *   synchronise it.  A handle must be used by one stream at a time.
+ * - Floating-point vectors are float64.
+ *   CG vectors are "L-vectors": the GLL grid nodes of the whole mesh that are
+ *   not on the Dirichlet boundary, in lexicographic order with x fastest
+ *   (the grid has n_i*p+1 points in direction i).  With LOR_BC_NEUMANN every
+ *   grid node is an unknown.
+ *   DG vectors are "E-vectors": element-major (elements lexicographic, x
+ *   fastest), (p+1)^d nodes per element (lexicographic, x fastest).
+ */
+#ifndef LOR_H
+#define LOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LOR_OK          0
+#define LOR_EINVAL     -1  /* bad argument, NaN/Inf in an input              */
+#define LOR_EJACOBIAN  -2  /* element map with det J <= 0 at a GLL node      */
+#define LOR_EPIVOT     -3  /* IC(0) pivot <= 0 or not finite                  */
+#define LOR_EBREAKDOWN -4  /* p^T A p <= 0 or r^T z <= 0 in CG               */
+#define LOR_ENOCONV    -5  /* maxit reached; x and info hold the last iterate */
+#define LOR_EHIP       -6  /* HIP runtime error                               */
+#define LOR_ENOMEM     -7  /* workspace missing or too small                  */
+#define LOR_ESTATE     -8  /* call not valid in the handle's current state    */
+
+typedef struct lor_handle lor_handle_t;   /* opaque, owned by the library */
+
+typedef enum { LOR_CG = 0, LOR_IP = 1, LOR_BR2 = 2 } lor_method_t;
+typedef enum { LOR_BC_DIRICHLET = 0, LOR_BC_NEUMANN = 1 } lor_bc_t;
+
+/* Structured block of quads (dim 2) or hexes (dim 3) covering a domain; each
+ * element is the image of [0,1]^d under the Q1 map of its 2^d vertices
+ * (Section 2).  vertex_xyz: HOST, (n0+1)(n1+1)(n2+1) x dim float64, vertices
+ * lexicographic with x fastest; copied during lor_setup. */
+typedef struct {
+  int dim;                  /* 2 or 3 */
+  int n[3];                 /* elements per direction (n[2] ignored in 2D) */
+  const double *vertex_xyz; /* host */
+  int bc;                   /* lor_bc_t; Neumann only supports lor_apply_A */
+} lor_mesh_t;
+
+#define LOR_PREC_FP64   0   /* every step in float64 */
+#define LOR_PREC_MIXED  1   /* preconditioner applied in float32 */
+
+#define LOR_ORD_MDF     0   /* minimum discarded fill (Section 3.4) */
+#define LOR_ORD_NATURAL 1   /* patch-local lexicographic */
+
+typedef struct {
+  int precision;     /* LOR_PREC_*                                          */
+  int ordering;      /* LOR_ORD_*                                           */
+  int flexible;      /* 0: PCG, 1: flexible CG FCG(1); forced on for MIXED  */
+  int nthreads;      /* host threads for the ordering pass; 0 = all cores   */
+  int reserved[8];   /* must be zero                                        */
+} lor_options_t;
+
+typedef struct {
+  int    iters;        /* CG iterations performed                          */
+  int    status;       /* LOR_OK, LOR_ENOCONV or LOR_EBREAKDOWN            */
+  double rel_res;      /* ||r_k||_2 / ||b||_2 of the recursive residual    */
+  double rel_res_true; /* ||b - A x||_2 / ||b||_2 recomputed at exit       */
+  double t_solve;      /* seconds, measured with HIP events                */
+} lor_solve_info_t;
+
+/* Fill *opt with the defaults (FP64, MDF, PCG, all cores). */
+int lor_default_options(lor_options_t *opt);
+
+const char *lor_error_string(int code);
+
+/* Detail of the last LOR_EHIP failure on the calling thread (which HIP call
+ * and its error string); empty if none.  Static thread-local storage. */
+const char *lor_last_error_detail(void);
+
+/* Set up the discretization and the preconditioner (Sections 2 and 3).
+ * p: polynomial degree, 1 <= p <= 14.  method: lor_method_t.
+ * penalty: eta, ignored for CG; IP uses sigma = eta p^2 / h_e on each face
+ *   (eq. ip, h_e = min |K|/|e| over the elements at the face); BR2 uses eta
+ *   as the factor of the lifting term (eq. br2).
+ * opt: NULL for defaults.  stream: used for the device part of the set-up.
+ * Allocates the device data the handle needs (geometric factors, LOR
+ * stencils, patch factors, coarse inverse) and builds everything.
+ * Errors: LOR_EINVAL (bad sizes, NaN vertex), LOR_EJACOBIAN, LOR_EPIVOT,
+ * LOR_EHIP.  On error *out is NULL and nothing is leaked. */
+int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty,
+              const lor_options_t *opt, void *stream, lor_handle_t **out);
+
+/* Number of unknowns: the L-vector length for CG, n_el (p+1)^d for DG. */
+int lor_ndofs(const lor_handle_t *h, int64_t *n);
+
+/* Bytes of device memory the handle holds. */
+int lor_device_bytes(const lor_handle_t *h, size_t *bytes);
+
+/* Coordinates of the unknowns, HOST output of ndofs x dim float64.  CG: the
+ * GLL grid node evaluated with the map of element min(g_i / p, n_i - 1) in
+ * each direction.  DG: each element's own map at its GLL nodes. */
+int lor_dof_coords(const lor_handle_t *h, double *host_xyz);
+
+/* b = M_p f with the collocated GLL mass (eq. system right-hand side):
+ * b_i = sum over elements containing node i of w_i |J_i| f_i.
+ * f_dev: DEVICE, f at the unknowns (same layout as b); b_dev: DEVICE out. */
+int lor_assemble_rhs(lor_handle_t *h, const double *f_dev, double *b_dev, void *stream);
+
+/* y = A x, matrix-free by sum factorization (Section 2; eq. ip / eq. br2
+ * for DG).  x_dev, y_dev: DEVICE, ndofs float64, must not alias. */
+int lor_apply_A(lor_handle_t *h, const double *x_dev, double *y_dev, void *stream);
+
+/* z = B r: additive Schwarz preconditioner of eq. as (eq. dg-as for DG).
+ * r_dev, z_dev: DEVICE, ndofs float64, must not alias. */
+int lor_apply_P(lor_handle_t *h, const double *r_dev, double *z_dev, void *stream);
+
+/* Solve A x = b by preconditioned (or flexible) CG from x = 0 until
+ * ||r_k||_2 <= rtol ||b||_2 (recursive residual) or maxit iterations.
+ * b_dev: DEVICE in; x_dev: DEVICE out.  info: HOST out, may be NULL.
+ * Returns LOR_OK, LOR_ENOCONV (x holds the last iterate) or
+ * LOR_EBREAKDOWN. */
+int lor_pcg_solve(lor_handle_t *h, const double *b_dev, double *x_dev,
+                  double rtol, int maxit, lor_solve_info_t *info, void *stream);
+
+/* Integer maps for parity checks, HOST output.  If host_out is NULL only
+ * *len is set.  which:
+ *   LOR_MAP_LDOF          L-vector index -> flat GLL grid index
+ *   LOR_MAP_ORDER         MDF orders of every (patch, level) concatenated,
+ *                         patches in vertex order, levels fine to coarse
+ *                         (the coarsest level, solved exactly, has none)
+ *   LOR_MAP_ORDER_OFFSET  start of each (patch, level) in LOR_MAP_ORDER,
+ *                         J*(L-1)+1 entries
+ *   LOR_MAP_SCHEDULE      dependency-level starts of each (patch, level)
+ *                         sweep, concatenated (depth+1 entries each)
+ *   LOR_MAP_SCHEDULE_OFFSET start of each (patch, level) in LOR_MAP_SCHEDULE */
+#define LOR_MAP_LDOF             0
+#define LOR_MAP_ORDER            1
+#define LOR_MAP_ORDER_OFFSET     2
+#define LOR_MAP_SCHEDULE         3
+#define LOR_MAP_SCHEDULE_OFFSET  4
+int lor_export_maps(const lor_handle_t *h, int which, int32_t *host_out, int64_t *len);
+
+/* Assembled LOR stencils of level k of the global element-structured
+ * hierarchy (Section 3.3), HOST output: (3^d) x npts float64, slot-major;
+ * slot = sum_i (o_i + 1) 3^i for the grid offset o in {-1,0,1}^d, points
+ * lexicographic (x fastest) over the level grid, boundary points included.
+ * If host_out is NULL only *len is set.  Returns LOR_EINVAL for a bad k. */
+int lor_export_stencils(const lor_handle_t *h, int level, double *host_out, int64_t *len);
+
+/* ---- host-only utilities (no device needed): the set-up building blocks,
+ * exposed so that their integer results can be checked bit for bit. ---- */
+
+/* GLL nodes x[0..p] and weights w[0..p] on [0,1] (Section 3.1), correctly
+ * rounded to float64.  HOST outputs of p+1 doubles. 1 <= p <= 14. */
+int lor_gll(int p, double *x, double *w);
+
+/* MDF ordering and IC(0) factor of one patch matrix (Section 3.4).
+ * dim: 2 or 3; m: box extents (dim entries, each >= 1); rows: HOST,
+ * n x 3^dim float64 stencil rows of the box points (n = prod m, x fastest;
+ * slot as in lor_export_stencils; couplings leaving the box are ignored).
+ * natural: 1 = eliminate in index order instead of MDF.
+ * HOST outputs (any may be NULL): order[n] elimination order;
+ * level_ptr[n+1] dependency-level starts of the forward sweep, *depth levels;
+ * L[n x 3^dim] (row i: l_im at earlier neighbours m, l_mi at later ones);
+ * D[n] pivots.  Returns LOR_EPIVOT for a pivot <= 0. */
+int lor_mdf_order(int dim, const int *m, const double *rows, int natural, int32_t *order,
+                  int32_t *level_ptr, int32_t *depth, double *L, double *D);
+
+/* Release every resource of the handle (NULL is accepted). */
+int lor_free(lor_handle_t *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LOR_H */

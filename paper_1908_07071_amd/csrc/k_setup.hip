@@ -1,0 +1,478 @@
+// Set-up kernels: GLL node coordinates, geometric factors of the high-order
+// operator, the low-order refined Q1 stencils of every hierarchy level, the
+// coarse-space restriction / prolongation and the dense coarse inverse.
+//
+// The node coordinates and the LOR stencils are computed in a fixed float64
+// operation order without contraction (this file is built with
+// -ffp-contract=off as well): the MDF orderings are decided by comparisons of
+// values derived from them, and a reference implementation that follows the
+// same order reproduces them bit for bit.
+#include <hip/hip_runtime.h>
+
+#include "lor_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace lor {
+
+namespace {
+
+__device__ inline int64_t lex3(int x, int y, int z, int nx, int ny) {
+  return int64_t(x) + int64_t(nx) * (int64_t(y) + int64_t(ny) * z);
+}
+
+// Q1 map of a structured element at reference point xi, pinned order:
+// phi_c = (l(c_x,xi_0) * l(c_y,xi_1)) * l(c_z,xi_2); X_r = sum_c V_c,r phi_c.
+template <int DIM>
+__device__ void q1_map(const double *verts, const MeshDims &md, const int *e, const double *xi,
+                       double *X) {
+  const int nv0 = md.n[0] + 1, nv1 = md.n[1] + 1;
+  double om[3], phi[8];
+  for (int i = 0; i < DIM; ++i) om[i] = 1.0 - xi[i];
+  for (int c = 0; c < (1 << DIM); ++c) {
+    double f = (c & 1) ? xi[0] : om[0];
+    for (int i = 1; i < DIM; ++i) f = f * (((c >> i) & 1) ? xi[i] : om[i]);
+    phi[c] = f;
+  }
+  for (int r = 0; r < DIM; ++r) {
+    double acc = 0.0;
+    for (int c = 0; c < (1 << DIM); ++c) {
+      const int vx = e[0] + (c & 1), vy = e[1] + ((c >> 1) & 1),
+                vz = DIM == 3 ? e[2] + ((c >> 2) & 1) : 0;
+      const int64_t vi = lex3(vx, vy, vz, nv0, nv1);
+      acc = acc + verts[vi * DIM + r] * phi[c];
+    }
+    X[r] = acc;
+  }
+}
+
+template <int DIM>
+__global__ void k_node_coords(MeshDims md, const double *__restrict__ verts,
+                              const double *__restrict__ gllx, double *__restrict__ coords) {
+  const int64_t np = int64_t(md.ng[0]) * md.ng[1] * md.ng[2];
+  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < np;
+       g += int64_t(gridDim.x) * blockDim.x) {
+    int gi[3] = {int(g % md.ng[0]), int((g / md.ng[0]) % md.ng[1]),
+                 int(g / (int64_t(md.ng[0]) * md.ng[1]))};
+    int e[3];
+    double xi[3];
+    for (int i = 0; i < DIM; ++i) {
+      e[i] = min(gi[i] / md.p, md.n[i] - 1);
+      xi[i] = gllx[gi[i] - e[i] * md.p];
+    }
+    double X[3];
+    q1_map<DIM>(verts, md, e, xi, X);
+    for (int r = 0; r < DIM; ++r) coords[r * np + g] = X[r];
+  }
+}
+
+// Geometric factors G = w |J| J^-1 J^-T (symmetric, d(d+1)/2 values per GLL
+// node, element-major SoA [e][comp][node]) and w |J| for the collocated mass.
+template <int DIM>
+__global__ void k_geom(MeshDims md, const double *__restrict__ verts,
+                       const double *__restrict__ gllx, const double *__restrict__ gllw,
+                       double *__restrict__ G, double *__restrict__ wdet, int *bad) {
+  const int Q = md.p + 1;
+  const int nq = DIM == 3 ? Q * Q * Q : Q * Q;
+  const int64_t nel = int64_t(md.n[0]) * md.n[1] * (DIM == 3 ? md.n[2] : 1);
+  const int ncomp = DIM == 3 ? 6 : 3;
+  const int nv0 = md.n[0] + 1, nv1 = md.n[1] + 1;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < nel * nq;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t e = t / nq;
+    const int q = int(t % nq);
+    const int e3[3] = {int(e % md.n[0]), int((e / md.n[0]) % md.n[1]),
+                       DIM == 3 ? int(e / (int64_t(md.n[0]) * md.n[1])) : 0};
+    const int qi[3] = {q % Q, (q / Q) % Q, q / (Q * Q)};
+    double xi[3], om[3];
+    double w = 1.0;
+    for (int i = 0; i < DIM; ++i) {
+      xi[i] = gllx[qi[i]];
+      om[i] = 1.0 - xi[i];
+      w *= gllw[qi[i]];
+    }
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int c = 0; c < (1 << DIM); ++c) {
+      const int b[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+      const int vx = e3[0] + b[0], vy = e3[1] + b[1], vz = DIM == 3 ? e3[2] + b[2] : 0;
+      const int64_t vi = lex3(vx, vy, vz, nv0, nv1);
+      for (int s = 0; s < DIM; ++s) {
+        double gsd = b[s] ? 1.0 : -1.0;
+        for (int i = 0; i < DIM; ++i)
+          if (i != s) gsd *= b[i] ? xi[i] : om[i];
+        for (int r = 0; r < DIM; ++r) J[r][s] += verts[vi * DIM + r] * gsd;
+      }
+    }
+    double det, A[3][3];
+    if (DIM == 3) {
+      A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+      A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+      A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+      A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+      A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+      A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+      A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+      A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+      A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+    } else {
+      A[0][0] = J[1][1];
+      A[0][1] = -J[0][1];
+      A[1][0] = -J[1][0];
+      A[1][1] = J[0][0];
+      det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    }
+    if (!(det > 0.0)) atomicOr(bad, 1);
+    // G = (w / det) * A A^T, with A = det * J^-1
+    const double f = w / det;
+    double *Ge = G + e * ncomp * nq;
+    int comp = 0;
+    for (int r = 0; r < DIM; ++r)
+      for (int c2 = r; c2 < DIM; ++c2) {
+        double acc = 0.0;
+        for (int s = 0; s < DIM; ++s) acc += A[r][s] * A[c2][s];
+        Ge[comp * nq + q] = f * acc;
+        ++comp;
+      }
+    wdet[e * nq + q] = w * det;
+  }
+}
+
+// LOR stencil of one level of the element-structured hierarchy.  For grid
+// point g the 3^d slots are filled, in the order of the cells S = g - 1 + s
+// (s = s_x + 2 s_y + 4 s_z ascending), with the Q1 stiffness entries
+// K_S[corner of g][corner of g+o].  K_S uses 2^d Gauss points; every
+// intermediate is computed in a fixed order (see the per-line comments).
+struct KeptIdx {
+  int fine[kMaxP + 1];  // level 1D index m -> GLL index kept[m]
+};
+
+template <int DIM>
+__global__ void k_lor_stencil(MeshDims md, int s, KeptIdx kept, const double *__restrict__ fine,
+                              double g0, double g1, double *__restrict__ out) {
+  constexpr int NC = 1 << DIM;
+  constexpr int NS = DIM == 3 ? 27 : 9;
+  const int lng[3] = {md.n[0] * s + 1, md.n[1] * s + 1, DIM == 3 ? md.n[2] * s + 1 : 1};
+  const int64_t npts = int64_t(lng[0]) * lng[1] * lng[2];
+  const int64_t fnp = int64_t(md.ng[0]) * md.ng[1] * md.ng[2];
+  const double gq[2] = {g0, g1};
+  const double wq = DIM == 3 ? 0.125 : 0.25;
+  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < npts;
+       g += int64_t(gridDim.x) * blockDim.x) {
+    const int gi[3] = {int(g % lng[0]), int((g / lng[0]) % lng[1]),
+                       int(g / (int64_t(lng[0]) * lng[1]))};
+    double acc[NS];
+    for (int sl = 0; sl < NS; ++sl) acc[sl] = 0.0;
+    for (int sc = 0; sc < NC; ++sc) {
+      int S[3] = {0, 0, 0};
+      bool ok = true;
+      for (int i = 0; i < DIM; ++i) {
+        S[i] = gi[i] - 1 + ((sc >> i) & 1);
+        if (S[i] < 0 || S[i] >= lng[i] - 1) ok = false;
+      }
+      if (!ok) continue;
+      // corners of the cell: level grid point -> GLL grid point -> coordinates
+      double X[NC][DIM];
+      for (int c = 0; c < NC; ++c) {
+        int64_t fi = 0, stride = 1;
+        for (int i = 0; i < DIM; ++i) {
+          const int G = S[i] + ((c >> i) & 1);
+          const int e = min(G / s, md.n[i] - 1);
+          const int f = e * md.p + kept.fine[G - e * s];
+          fi += int64_t(f) * stride;
+          stride *= md.ng[i];
+        }
+        for (int r = 0; r < DIM; ++r) X[c][r] = fine[r * fnp + fi];
+      }
+      int ca = 0;  // corner of g in S
+      for (int i = 0; i < DIM; ++i) ca |= (gi[i] - S[i]) << i;
+      double K[NC];
+      for (int b = 0; b < NC; ++b) K[b] = 0.0;
+      for (int q = 0; q < NC; ++q) {
+        double lv[3][2];
+        for (int i = 0; i < DIM; ++i) {
+          const double xi = gq[(q >> i) & 1];
+          lv[i][0] = 1.0 - xi;
+          lv[i][1] = xi;
+        }
+        double gr[NC][DIM];
+        for (int c = 0; c < NC; ++c) {
+          const int bt[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+          for (int sd = 0; sd < DIM; ++sd) {
+            // product of l over the other directions, ascending
+            double val = 0.0;
+            bool first = true;
+            for (int t = 0; t < DIM; ++t) {
+              if (t == sd) continue;
+              val = first ? lv[t][bt[t]] : val * lv[t][bt[t]];
+              first = false;
+            }
+            gr[c][sd] = bt[sd] ? val : -val;
+          }
+        }
+        double J[DIM][DIM];
+        for (int r = 0; r < DIM; ++r)
+          for (int sd = 0; sd < DIM; ++sd) {
+            double a = 0.0;
+            for (int c = 0; c < NC; ++c) a = a + X[c][r] * gr[c][sd];
+            J[r][sd] = a;
+          }
+        double A[DIM][DIM], det;
+        if constexpr (DIM == 3) {
+          A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+          A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+          A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+          A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+          A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+          A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+          A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+          A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+          A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+          det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+        } else {
+          A[0][0] = J[1][1];
+          A[0][1] = -J[0][1];
+          A[1][0] = -J[1][0];
+          A[1][1] = J[0][0];
+          det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        }
+        const double coef = wq / det;
+        double u[NC][DIM];
+        for (int c = 0; c < NC; ++c)
+          for (int r = 0; r < DIM; ++r) {
+            double a = A[0][r] * gr[c][0] + A[1][r] * gr[c][1];
+            if constexpr (DIM == 3) a = a + A[2][r] * gr[c][2];
+            u[c][r] = a;
+          }
+        for (int b = 0; b < NC; ++b) {
+          double dot = u[ca][0] * u[b][0] + u[ca][1] * u[b][1];
+          if constexpr (DIM == 3) dot = dot + u[ca][2] * u[b][2];
+          K[b] = K[b] + coef * dot;
+        }
+      }
+      for (int b = 0; b < NC; ++b) {
+        int sl = 0, p3 = 1;
+        for (int i = 0; i < DIM; ++i) {
+          const int o = (S[i] + ((b >> i) & 1)) - gi[i];
+          sl += (o + 1) * p3;
+          p3 *= 3;
+        }
+        acc[sl] = acc[sl] + K[b];
+      }
+    }
+    for (int sl = 0; sl < NS; ++sl) out[sl * npts + g] = acc[sl];
+  }
+}
+
+// ---------------------------------------------------------------- coarse space
+// P_0: Q1 interpolation of element-vertex values at the GLL grid nodes, in
+// reference coordinates; weights 1 - x_a and x_a per direction.  Only the
+// interior vertices are unknowns (Dirichlet).
+
+template <int DIM>
+__global__ void k_coarse_restrict(MeshDims md, const double *__restrict__ gllx,
+                                  const double *__restrict__ r, double *__restrict__ rc) {
+  const int ncx = md.n[0] - 1, ncy = md.n[1] - 1;
+  const int c = blockIdx.x;
+  const int v[3] = {c % ncx + 1, (c / ncx) % ncy + 1, DIM == 3 ? c / (ncx * ncy) + 1 : 0};
+  const int p = md.p, w1 = 2 * p - 1;
+  const int cnt = DIM == 3 ? w1 * w1 * w1 : w1 * w1;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+    const int o[3] = {t % w1, (t / w1) % w1, t / (w1 * w1)};
+    double w = 1.0;
+    int64_t li = 0, stride = 1;
+    for (int i = 0; i < DIM; ++i) {
+      const int g = (v[i] - 1) * p + 1 + o[i];
+      const int a = g - (v[i] - 1) * p;  // 1 .. 2p-1
+      w *= a <= p ? gllx[a] : 1.0 - gllx[a - p];
+      li += int64_t(g - 1) * stride;
+      stride *= md.nu[i];
+    }
+    acc += w * r[li];
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rc[c] = red[0];
+}
+
+template <int DIM>
+__global__ void k_coarse_prolong(MeshDims md, const double *__restrict__ gllx,
+                                 const double *__restrict__ xc, double *__restrict__ z,
+                                 const double *flag) {
+  if (flag && flag[S_DONE] != 0.0) return;
+  const int64_t N = int64_t(md.nu[0]) * md.nu[1] * (DIM == 3 ? md.nu[2] : 1);
+  const int ncx = md.n[0] - 1, ncy = md.n[1] - 1;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int gi[3] = {int(i % md.nu[0]) + 1, int((i / md.nu[0]) % md.nu[1]) + 1,
+                       DIM == 3 ? int(i / (int64_t(md.nu[0]) * md.nu[1])) + 1 : 0};
+    int ev[3];
+    double wl[3], wh[3];
+    for (int d = 0; d < DIM; ++d) {
+      const int e = min(gi[d] / md.p, md.n[d] - 1);
+      const int a = gi[d] - e * md.p;
+      ev[d] = e;
+      wl[d] = 1.0 - gllx[a];
+      wh[d] = gllx[a];
+    }
+    double acc = 0.0;
+    for (int c = 0; c < (1 << DIM); ++c) {
+      double w = 1.0;
+      int vi[3];
+      bool ok = true;
+      for (int d = 0; d < DIM; ++d) {
+        const int b = (c >> d) & 1;
+        vi[d] = ev[d] + b;
+        w *= b ? wh[d] : wl[d];
+        if (vi[d] <= 0 || vi[d] >= md.n[d]) ok = false;
+      }
+      if (!ok) continue;
+      int64_t ci = (vi[0] - 1) + int64_t(ncx) * ((vi[1] - 1) + (DIM == 3 ? int64_t(ncy) * (vi[2] - 1) : 0));
+      acc += w * xc[ci];
+    }
+    z[i] = acc;
+  }
+}
+
+// y = A x for a dense row-major n x n matrix: one wavefront per row.
+__global__ void k_gemv(int n, const double *__restrict__ A, const double *__restrict__ x,
+                       double *__restrict__ y, const double *flag) {
+  if (flag && flag[S_DONE] != 0.0) return;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const double *a = A + int64_t(row) * n;
+  double acc = 0.0;
+  for (int j = lane; j < n; j += 64) acc += a[j] * x[j];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) y[row] = acc;
+}
+
+// In-place Gauss-Jordan inversion of an SPD matrix, step k (no pivoting).
+__global__ void k_gj_save(int n, int k, const double *__restrict__ A, double *rowbuf,
+                          double *colbuf, int *bad) {
+  const double piv = A[int64_t(k) * n + k];
+  if (!(piv > 0.0)) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) atomicOr(bad, 1);
+  }
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    rowbuf[j] = j == k ? 1.0 / piv : A[int64_t(k) * n + j] / piv;
+    colbuf[j] = j == k ? 0.0 : A[int64_t(j) * n + k];
+  }
+}
+
+__global__ void k_gj_update(int n, int k, double *__restrict__ A, const double *__restrict__ rowbuf,
+                            const double *__restrict__ colbuf) {
+  const int64_t tot = int64_t(n) * n;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < tot;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int i = int(t / n), j = int(t % n);
+    if (i == k)
+      A[t] = rowbuf[j];
+    else if (j == k)
+      A[t] = -colbuf[i] * rowbuf[k];
+    else
+      A[t] -= colbuf[i] * rowbuf[j];
+  }
+}
+
+__global__ void k_fill(double *x, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    x[i] = v;
+}
+
+inline int grid_for(int64_t n, int bs) {
+  int64_t g = (n + bs - 1) / bs;
+  return int(g > 65536 ? 65536 : (g < 1 ? 1 : g));
+}
+
+}  // namespace
+
+hipError_t launch_node_coords(const MeshDims &md, const double *verts, const double *gllx,
+                              double *coords, hipStream_t st) {
+  const int64_t np = int64_t(md.ng[0]) * md.ng[1] * md.ng[2];
+  if (md.dim == 3)
+    k_node_coords<3><<<grid_for(np, 256), 256, 0, st>>>(md, verts, gllx, coords);
+  else
+    k_node_coords<2><<<grid_for(np, 256), 256, 0, st>>>(md, verts, gllx, coords);
+  return hipGetLastError();
+}
+
+hipError_t launch_geom_cg(const MeshDims &md, const double *verts, const double *gllx,
+                          const double *gllw, double *G, double *wdet, int *bad, hipStream_t st) {
+  const int Q = md.p + 1;
+  const int64_t nel = int64_t(md.n[0]) * md.n[1] * (md.dim == 3 ? md.n[2] : 1);
+  const int64_t tot = nel * (md.dim == 3 ? Q * Q * Q : Q * Q);
+  if (md.dim == 3)
+    k_geom<3><<<grid_for(tot, 256), 256, 0, st>>>(md, verts, gllx, gllw, G, wdet, bad);
+  else
+    k_geom<2><<<grid_for(tot, 256), 256, 0, st>>>(md, verts, gllx, gllw, G, wdet, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_lor_stencil(const MeshDims &md, int s, const int *kept_fine_idx,
+                              const double *fine_coords, double g0, double g1, double *stencil,
+                              hipStream_t st) {
+  KeptIdx k{};
+  for (int i = 0; i <= s; ++i) k.fine[i] = kept_fine_idx[i];
+  const int64_t npts = int64_t(md.n[0] * s + 1) * (md.n[1] * s + 1) *
+                       (md.dim == 3 ? md.n[2] * s + 1 : 1);
+  if (md.dim == 3)
+    k_lor_stencil<3><<<grid_for(npts, 128), 128, 0, st>>>(md, s, k, fine_coords, g0, g1, stencil);
+  else
+    k_lor_stencil<2><<<grid_for(npts, 128), 128, 0, st>>>(md, s, k, fine_coords, g0, g1, stencil);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_restrict(const MeshDims &md, const double *gllx, const double *r,
+                                  double *rc, hipStream_t st) {
+  const int nc = (md.n[0] - 1) * (md.n[1] - 1) * (md.dim == 3 ? md.n[2] - 1 : 1);
+  if (nc <= 0) return hipSuccess;
+  if (md.dim == 3)
+    k_coarse_restrict<3><<<nc, 256, 0, st>>>(md, gllx, r, rc);
+  else
+    k_coarse_restrict<2><<<nc, 256, 0, st>>>(md, gllx, r, rc);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_prolong(const MeshDims &md, const double *gllx, const double *xc,
+                                 double *z, const double *flag, hipStream_t st) {
+  const int64_t N = int64_t(md.nu[0]) * md.nu[1] * (md.dim == 3 ? md.nu[2] : 1);
+  if (md.dim == 3)
+    k_coarse_prolong<3><<<grid_for(N, 256), 256, 0, st>>>(md, gllx, xc, z, flag);
+  else
+    k_coarse_prolong<2><<<grid_for(N, 256), 256, 0, st>>>(md, gllx, xc, z, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv(int n, const double *A, const double *x, double *y, const double *flag,
+                       hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_gemv<<<(n + 3) / 4, 256, 0, st>>>(n, A, x, y, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_gauss_jordan(int n, double *A, double *rowbuf, double *colbuf, int *bad,
+                               hipStream_t st) {
+  const int64_t tot = int64_t(n) * n;
+  for (int k = 0; k < n; ++k) {
+    k_gj_save<<<grid_for(n, 256), 256, 0, st>>>(n, k, A, rowbuf, colbuf, bad);
+    k_gj_update<<<grid_for(tot, 256), 256, 0, st>>>(n, k, A, rowbuf, colbuf);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_fill<<<grid_for(n, 256), 256, 0, st>>>(x, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace lor

@@ -1,0 +1,210 @@
+// Minimum-discarded-fill ordering and the ILU(0) (= IC(0) for the symmetric
+// LOR patch matrices) factor it produces (Section 3.4, complexity in the
+// computational-cost table: O(n log n) with a min-heap).
+//
+// Reading of the method: the matrix carries the Q1 stencil pattern (two grid
+// points are coupled iff their offsets differ by at most one per direction).
+// Eliminating node i applies a_jl -= a_ji a_il / a_ii to every pair of not yet
+// eliminated neighbours (j, l) of i inside the pattern and drops the rest.
+// The discarded fill of a candidate m is the sum, over pairs of its remaining
+// neighbours j < l that are not coupled, of ((a_mj * a_ml) / a_mm)^2.  The
+// node with the smallest value goes next; exact ties go to the smallest
+// patch-local index.  Every float64 operation below is written in a fixed
+// order (and the file is compiled without contraction) so that an
+// independent implementation following the same order agrees bit for bit.
+#include <cmath>
+#include <queue>
+#include <vector>
+
+#include "lor_internal.h"
+
+namespace lor {
+
+namespace {
+
+struct Stencil {
+  int dim, ns, center;
+  int off[27][3];
+  bool coupled[27][27];
+  int rel[27][27];     // slot of (o_l - o_j), -1 if outside the stencil
+  int mirror[27];
+  explicit Stencil(int d) : dim(d) {
+    ns = d == 3 ? 27 : 9;
+    center = ns / 2;
+    for (int s = 0; s < ns; ++s) {
+      off[s][0] = s % 3 - 1;
+      off[s][1] = (s / 3) % 3 - 1;
+      off[s][2] = d == 3 ? s / 9 - 1 : 0;
+    }
+    for (int a = 0; a < ns; ++a) {
+      int mo[3] = {-off[a][0], -off[a][1], -off[a][2]};
+      mirror[a] = slot(mo);
+      for (int b = 0; b < ns; ++b) {
+        int dlt[3];
+        bool ok = true;
+        for (int t = 0; t < 3; ++t) {
+          dlt[t] = off[b][t] - off[a][t];
+          if (dlt[t] < -1 || dlt[t] > 1) ok = false;
+        }
+        coupled[a][b] = ok;
+        rel[a][b] = ok ? slot(dlt) : -1;
+      }
+    }
+  }
+  int slot(const int *o) const {
+    int s = (o[0] + 1) + 3 * (o[1] + 1);
+    if (dim == 3) s += 9 * (o[2] + 1);
+    return s;
+  }
+};
+
+struct HeapItem {
+  double d;
+  int idx;
+  int ver;
+};
+struct HeapCmp {  // min-heap on (d, idx)
+  bool operator()(const HeapItem &a, const HeapItem &b) const {
+    if (a.d != b.d) return a.d > b.d;
+    if (a.idx != b.idx) return a.idx > b.idx;
+    return a.ver > b.ver;
+  }
+};
+
+}  // namespace
+
+int mdf_factor(int dim, const int *m, std::vector<double> &a, bool natural, MdfResult &out) {
+  const Stencil st(dim);
+  const int ns = st.ns, C = st.center;
+  const int mx = m[0], my = m[1], mz = dim == 3 ? m[2] : 1;
+  const int n = mx * my * mz;
+  std::vector<int> nb(size_t(n) * ns, -1);
+  for (int i = 0; i < n; ++i) {
+    int c[3] = {i % mx, (i / mx) % my, i / (mx * my)};
+    for (int s = 0; s < ns; ++s) {
+      int q[3] = {c[0] + st.off[s][0], c[1] + st.off[s][1], c[2] + st.off[s][2]};
+      if (q[0] >= 0 && q[0] < mx && q[1] >= 0 && q[1] < my && q[2] >= 0 && q[2] < mz)
+        nb[size_t(i) * ns + s] = q[0] + mx * (q[1] + my * q[2]);
+      else
+        a[size_t(i) * ns + s] = 0.0;
+    }
+  }
+  std::vector<char> elim(n, 0);
+  out.L.assign(size_t(n) * ns, 0.0);
+  out.D.assign(n, 0.0);
+  out.order.clear();
+  out.order.reserve(n);
+
+  auto disc = [&](int mm) -> double {
+    int nbr[27], k = 0;
+    const size_t base = size_t(mm) * ns;
+    for (int s = 0; s < ns; ++s) {
+      int j = nb[base + s];
+      if (s != C && j >= 0 && !elim[j]) nbr[k++] = s;
+    }
+    double acc = 0.0;
+    const double amm = a[base + C];
+    for (int x = 0; x < k; ++x)
+      for (int y = x + 1; y < k; ++y) {
+        if (st.coupled[nbr[x]][nbr[y]]) continue;
+        double f = (a[base + nbr[x]] * a[base + nbr[y]]) / amm;
+        acc = acc + f * f;
+      }
+    return acc;
+  };
+
+  // returns the number of uneliminated neighbours written to nbr
+  auto eliminate = [&](int i, int *nbr) -> int {
+    const size_t bi = size_t(i) * ns;
+    const double piv = a[bi + C];
+    if (!(std::isfinite(piv) && piv > 0.0)) return -1;
+    out.D[i] = piv;
+    int k = 0;
+    for (int s = 0; s < ns; ++s) {
+      int j = nb[bi + s];
+      if (s != C && j >= 0 && !elim[j]) nbr[k++] = s;
+    }
+    for (int x = 0; x < k; ++x) {
+      const int sj = nbr[x];
+      const int j = nb[bi + sj];
+      const double lji = a[bi + sj] / piv;
+      out.L[bi + sj] = lji;
+      out.L[size_t(j) * ns + st.mirror[sj]] = lji;
+      for (int y = 0; y < k; ++y) {
+        const int sl = nbr[y];
+        if (!st.coupled[sj][sl]) continue;
+        const double t = (a[bi + sj] * a[bi + sl]) / piv;
+        double &dst = a[size_t(j) * ns + st.rel[sj][sl]];
+        dst = dst - t;
+      }
+    }
+    elim[i] = 1;
+    return k;
+  };
+
+  int nbr[27];
+  if (natural) {
+    for (int i = 0; i < n; ++i) {
+      if (eliminate(i, nbr) < 0) return LOR_EPIVOT;
+      out.order.push_back(i);
+    }
+  } else {
+    std::vector<double> dv(n);
+    std::vector<int> ver(n, 0);
+    std::priority_queue<HeapItem, std::vector<HeapItem>, HeapCmp> heap;
+    for (int i = 0; i < n; ++i) {
+      dv[i] = disc(i);
+      heap.push({dv[i], i, 0});
+    }
+    while (int(out.order.size()) < n) {
+      HeapItem it = heap.top();
+      heap.pop();
+      if (elim[it.idx] || it.ver != ver[it.idx]) continue;
+      const int i = it.idx;
+      out.order.push_back(i);
+      int k = eliminate(i, nbr);
+      if (k < 0) return LOR_EPIVOT;
+      const size_t bi = size_t(i) * ns;
+      for (int x = 0; x < k; ++x) {
+        int j = nb[bi + nbr[x]];
+        dv[j] = disc(j);
+        ++ver[j];
+        heap.push({dv[j], j, ver[j]});
+      }
+    }
+  }
+
+  // dependency levels of the forward sweep, rows grouped by level
+  std::vector<int> pos(n), lev(n, 0);
+  for (int t = 0; t < n; ++t) pos[out.order[t]] = t;
+  out.earlier.assign(n, 0);
+  int depth = 0;
+  for (int t = 0; t < n; ++t) {
+    const int i = out.order[t];
+    int best = 0, mask = 0;
+    for (int s = 0; s < ns; ++s) {
+      int j = nb[size_t(i) * ns + s];
+      if (s == C || j < 0) continue;
+      if (pos[j] < t) {
+        mask |= 1 << s;
+        best = std::max(best, lev[j] + 1);
+      }
+    }
+    lev[i] = best;
+    out.earlier[i] = mask;
+    depth = std::max(depth, best + 1);
+  }
+  std::vector<int> cnt(depth + 1, 0);
+  for (int i = 0; i < n; ++i) cnt[lev[i] + 1]++;
+  for (int d = 0; d < depth; ++d) cnt[d + 1] += cnt[d];
+  out.level_ptr = cnt;
+  out.sched.assign(n, 0);
+  std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+  for (int t = 0; t < n; ++t) {
+    const int i = out.order[t];
+    out.sched[fill[lev[i]]++] = i;
+  }
+  return LOR_OK;
+}
+
+}  // namespace lor

@@ -1,0 +1,237 @@
+"""Thin ctypes binding of ``liblor.so`` (the C ABI in include/lor.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  Device vectors are torch tensors (float64, on the current device);
+their ``data_ptr()`` and torch's current HIP stream are handed to the library.
+Importing this module loads the library and raises if it is not built -- there
+is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblor.so")
+
+LOR_OK, LOR_EINVAL, LOR_EJACOBIAN, LOR_EPIVOT = 0, -1, -2, -3
+LOR_EBREAKDOWN, LOR_ENOCONV, LOR_EHIP, LOR_ENOMEM, LOR_ESTATE = -4, -5, -6, -7, -8
+LOR_CG, LOR_IP, LOR_BR2 = 0, 1, 2
+LOR_BC_DIRICHLET, LOR_BC_NEUMANN = 0, 1
+LOR_PREC_FP64, LOR_PREC_MIXED = 0, 1
+LOR_ORD_MDF, LOR_ORD_NATURAL = 0, 1
+LOR_MAP_LDOF, LOR_MAP_ORDER, LOR_MAP_ORDER_OFFSET = 0, 1, 2
+LOR_MAP_SCHEDULE, LOR_MAP_SCHEDULE_OFFSET = 3, 4
+
+EXPORTED = [
+    "lor_default_options", "lor_error_string", "lor_setup", "lor_ndofs", "lor_device_bytes",
+    "lor_dof_coords", "lor_assemble_rhs", "lor_apply_A", "lor_apply_P", "lor_pcg_solve",
+    "lor_export_maps", "lor_export_stencils", "lor_gll", "lor_mdf_order", "lor_free",
+    "lor_last_error_detail",
+]
+
+
+class LorError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        detail = _lib.lor_last_error_detail().decode() if code == LOR_EHIP else ""
+        super().__init__(f"{where}: {error_string(code)} ({code}) {detail}")
+
+
+class lor_mesh_t(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("vertex_xyz", C.POINTER(C.c_double)),
+                ("bc", C.c_int)]
+
+
+class lor_options_t(C.Structure):
+    _fields_ = [("precision", C.c_int), ("ordering", C.c_int), ("flexible", C.c_int),
+                ("nthreads", C.c_int), ("reserved", C.c_int * 8)]
+
+
+class lor_solve_info_t(C.Structure):
+    _fields_ = [("iters", C.c_int), ("status", C.c_int), ("rel_res", C.c_double),
+                ("rel_res_true", C.c_double), ("t_solve", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1908_07071_amd.build")
+    # Load torch's HIP runtime first: the library's libamdhip64.so.7 dependency
+    # then resolves to that already-loaded runtime, so device memory and streams
+    # created by torch are valid in the library (one runtime per process).
+    import torch  # noqa: F401
+    lib = C.CDLL(LIB_PATH)
+    vp, dp, i32p, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    sig = {
+        "lor_default_options": (C.c_int, [C.POINTER(lor_options_t)]),
+        "lor_error_string": (C.c_char_p, [C.c_int]),
+        "lor_setup": (C.c_int, [C.POINTER(lor_mesh_t), C.c_int, C.c_int, C.c_double,
+                                C.POINTER(lor_options_t), vp, C.POINTER(vp)]),
+        "lor_ndofs": (C.c_int, [vp, i64p]),
+        "lor_device_bytes": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
+        "lor_dof_coords": (C.c_int, [vp, dp]),
+        "lor_assemble_rhs": (C.c_int, [vp, vp, vp, vp]),
+        "lor_apply_A": (C.c_int, [vp, vp, vp, vp]),
+        "lor_apply_P": (C.c_int, [vp, vp, vp, vp]),
+        "lor_pcg_solve": (C.c_int, [vp, vp, vp, C.c_double, C.c_int, C.POINTER(lor_solve_info_t), vp]),
+        "lor_export_maps": (C.c_int, [vp, C.c_int, i32p, i64p]),
+        "lor_export_stencils": (C.c_int, [vp, C.c_int, dp, i64p]),
+        "lor_gll": (C.c_int, [C.c_int, dp, dp]),
+        "lor_mdf_order": (C.c_int, [C.c_int, i32p, dp, C.c_int, i32p, i32p, i32p, dp, dp]),
+        "lor_free": (C.c_int, [vp]),
+        "lor_last_error_detail": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def error_string(code: int) -> str:
+    return _lib.lor_error_string(int(code)).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != LOR_OK:
+        raise LorError(rc, where)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------- host-only
+
+def lor_gll(p: int):
+    x = np.zeros(p + 1)
+    w = np.zeros(p + 1)
+    _check(_lib.lor_gll(int(p), _dptr(x), _dptr(w)), "lor_gll")
+    return x, w
+
+
+def lor_mdf_order(dim: int, shape, rows: np.ndarray, natural: bool = False):
+    """(order, level_ptr, L, D) of one patch matrix given as (n, 3^dim) stencil rows."""
+    m = np.ascontiguousarray(shape, dtype=np.int32)
+    n = int(np.prod(m))
+    ns = 3 ** dim
+    rows = np.ascontiguousarray(rows, dtype=np.float64).reshape(n, ns)
+    order = np.zeros(n, np.int32)
+    lvl = np.zeros(n + 1, np.int32)
+    depth = np.zeros(1, np.int32)
+    L = np.zeros((n, ns))
+    D = np.zeros(n)
+    rc = _lib.lor_mdf_order(int(dim), _iptr(m), _dptr(rows), int(bool(natural)), _iptr(order),
+                            _iptr(lvl), _iptr(depth), _dptr(L), _dptr(D))
+    _check(rc, "lor_mdf_order")
+    return order, lvl[:int(depth[0]) + 1].copy(), L, D
+
+
+# ---------------------------------------------------------------- handles
+
+def lor_default_options():
+    o = lor_options_t()
+    _check(_lib.lor_default_options(C.byref(o)), "lor_default_options")
+    return o
+
+
+def lor_setup(dim: int, n, vertices: np.ndarray, p: int, method: int = LOR_CG, penalty: float = 0.0,
+              options: lor_options_t | None = None, bc: int = LOR_BC_DIRICHLET, stream=None):
+    """Returns an opaque handle (ctypes void pointer)."""
+    n = [int(n)] * dim if np.isscalar(n) else [int(v) for v in n]
+    verts = np.ascontiguousarray(vertices, dtype=np.float64)
+    mesh = lor_mesh_t()
+    mesh.dim = dim
+    for i in range(3):
+        mesh.n[i] = n[i] if i < dim else 1
+    mesh.vertex_xyz = _dptr(verts)
+    mesh.bc = bc
+    h = C.c_void_p()
+    opt = C.byref(options) if options is not None else None
+    rc = _lib.lor_setup(C.byref(mesh), int(p), int(method), float(penalty), opt, _stream(stream), C.byref(h))
+    _check(rc, "lor_setup")
+    return h
+
+
+def lor_ndofs(h) -> int:
+    n = C.c_int64()
+    _check(_lib.lor_ndofs(h, C.byref(n)), "lor_ndofs")
+    return n.value
+
+
+def lor_device_bytes(h) -> int:
+    n = C.c_size_t()
+    _check(_lib.lor_device_bytes(h, C.byref(n)), "lor_device_bytes")
+    return n.value
+
+
+def lor_dof_coords(h, dim: int) -> np.ndarray:
+    out = np.zeros((lor_ndofs(h), dim))
+    _check(_lib.lor_dof_coords(h, _dptr(out)), "lor_dof_coords")
+    return out
+
+
+def lor_assemble_rhs(h, f, b, stream=None):
+    _check(_lib.lor_assemble_rhs(h, _dev(f, "f"), _dev(b, "b"), _stream(stream)), "lor_assemble_rhs")
+
+
+def lor_apply_A(h, x, y, stream=None):
+    _check(_lib.lor_apply_A(h, _dev(x, "x"), _dev(y, "y"), _stream(stream)), "lor_apply_A")
+
+
+def lor_apply_P(h, r, z, stream=None):
+    _check(_lib.lor_apply_P(h, _dev(r, "r"), _dev(z, "z"), _stream(stream)), "lor_apply_P")
+
+
+def lor_pcg_solve(h, b, x, rtol: float = 1e-8, maxit: int = 1000, stream=None, check: bool = True):
+    info = lor_solve_info_t()
+    rc = _lib.lor_pcg_solve(h, _dev(b, "b"), _dev(x, "x"), float(rtol), int(maxit), C.byref(info),
+                            _stream(stream))
+    if check and rc not in (LOR_OK,):
+        raise LorError(rc, "lor_pcg_solve")
+    return info
+
+
+def lor_export_maps(h, which: int) -> np.ndarray:
+    n = C.c_int64()
+    _check(_lib.lor_export_maps(h, int(which), None, C.byref(n)), "lor_export_maps")
+    out = np.zeros(n.value, np.int32)
+    _check(_lib.lor_export_maps(h, int(which), _iptr(out), C.byref(n)), "lor_export_maps")
+    return out
+
+
+def lor_export_stencils(h, level: int) -> np.ndarray:
+    n = C.c_int64()
+    _check(_lib.lor_export_stencils(h, int(level), None, C.byref(n)), "lor_export_stencils")
+    out = np.zeros(n.value)
+    _check(_lib.lor_export_stencils(h, int(level), _dptr(out), C.byref(n)), "lor_export_stencils")
+    return out
+
+
+def lor_free(h):
+    if h is not None and h.value:
+        _check(_lib.lor_free(h), "lor_free")
+        h.value = None

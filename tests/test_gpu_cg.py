@@ -1,0 +1,189 @@
+"""GPU parity of the CG path through the C ABI against the CPU oracle.
+
+Integer results (node maps, MDF orders, schedules) and the LOR stencils are
+compared bit for bit; the operator, preconditioner and solves within the
+float64 tolerances 1e-12 (apply) and the solver tolerance (solves).
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import gll, highorder as HO, krylov, lor as OL, mdf, mesh as M, schwarz as S
+from paper_1908_07071_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # dim, n, p, perturb, seed
+    (2, (3, 3), 3, 0.1, 1),
+    (2, (4, 2), 4, 0.0, 2),
+    (3, (2, 2, 2), 3, 0.1, 3),
+    (3, (3, 2, 2), 2, 0.1, 4),
+    (3, (1, 2, 3), 4, 0.1, 5),
+    (2, (1, 1), 2, 0.0, 6),
+    (3, (2, 2, 2), 1, 0.1, 7),
+]
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "HIP device required"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1908_07071_amd import lor
+    return lor
+
+
+def _case(case):
+    dim, n, p, pert, seed = case
+    V = inputs.structured_vertices(dim, list(n), pert, seed=seed)
+    return dim, list(n), p, V, M.make_mesh(dim, list(n), V)
+
+
+def _ids(c):
+    return f"d{c[0]}-n{'x'.join(map(str, c[1]))}-p{c[2]}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_maps_coords_stencils_orders_bitexact(case, L, torch_dev):
+    dim, n, p, V, mesh = _case(case)
+    print("case", case, flush=True)
+    h = L.lor_setup(dim, n, V, p)
+    try:
+        shape = M.grid_shape(mesh, p)
+        num = M.interior_numbering(shape)
+        assert np.array_equal(L.lor_export_maps(h, L.LOR_MAP_LDOF), np.flatnonzero(num >= 0))
+        x, _ = gll.gll(p)
+        coords = M.global_node_coords(mesh, x, p)
+        assert np.array_equal(L.lor_dof_coords(h, dim), coords[num >= 0])
+        H = OL.LORHierarchy(mesh, p)
+        for k in range(H.nlevels):
+            st = L.lor_export_stencils(h, k).reshape(3 ** dim, -1)
+            assert np.array_equal(st, H.stencils[k].T), f"level {k}"
+        order = L.lor_export_maps(h, L.LOR_MAP_ORDER)
+        ooff = L.lor_export_maps(h, L.LOR_MAP_ORDER_OFFSET)
+        sched = L.lor_export_maps(h, L.LOR_MAP_SCHEDULE)
+        soff = L.lor_export_maps(h, L.LOR_MAP_SCHEDULE_OFFSET)
+        nf = H.nlevels - 1
+        t = 0
+        for j, v in enumerate(S.vertices(mesh)):
+            for k in range(nf):
+                rng = S.patch_ranges(mesh, H.sizes[k], v)
+                shp = [hi - lo + 1 for lo, hi in rng]
+                got = order[ooff[t]:ooff[t + 1]]
+                if min(shp) > 0:
+                    idx = np.indices(shp).reshape(dim, -1, order="F")
+                    flat = M.lex_index([idx[i] + rng[i][0] for i in range(dim)], H.shapes[k])
+                    g = mdf.PatchGraph(shp, H.stencils[k][flat])
+                    o, _, _ = mdf.mdf_factor(g)
+                    assert np.array_equal(got, o), (j, k)
+                    lv = sched[soff[t]:soff[t + 1]]
+                    assert len(lv) - 1 == mdf.dependency_depth(g, o)
+                else:
+                    assert len(got) == 0
+                t += 1
+    finally:
+        L.lor_free(h)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_apply_A_rhs_and_P(case, L, torch_dev):
+    torch = torch_dev
+    dim, n, p, V, mesh = _case(case)
+    print("case", case, flush=True)
+    h = L.lor_setup(dim, n, V, p)
+    try:
+        N = L.lor_ndofs(h)
+        K = HO.cg_stiffness(mesh, p)
+        assert N == K.shape[0]
+        if N == 0:
+            return
+        xin = inputs.uniform_vector(N, 11)
+        x = torch.tensor(xin, device="cuda")
+        y = torch.empty_like(x)
+        L.lor_apply_A(h, x, y)
+        torch.cuda.synchronize()
+        ref = K @ xin
+        err = np.abs(y.cpu().numpy() - ref).max() / np.abs(ref).max()
+        assert err <= 1e-12, err
+        # right-hand side b = M_p f
+        xg, _ = gll.gll(p)
+        coords = M.global_node_coords(mesh, xg, p)
+        fgrid = inputs.manufactured_f(coords)
+        num = M.interior_numbering(M.grid_shape(mesh, p))
+        f = torch.tensor(fgrid[num >= 0], device="cuda")
+        b = torch.empty_like(f)
+        L.lor_assemble_rhs(h, f, b)
+        bref = HO.cg_rhs(mesh, p, fgrid)
+        assert np.abs(b.cpu().numpy() - bref).max() <= 1e-14 * np.abs(bref).max() + 1e-300
+        # preconditioner
+        B = S.SchwarzLOR(mesh, p)
+        z = torch.empty_like(x)
+        L.lor_apply_P(h, x, z)
+        torch.cuda.synchronize()
+        zref = B.apply(xin)
+        err = np.abs(z.cpu().numpy() - zref).max() / np.abs(zref).max()
+        assert err <= 1e-12, err
+    finally:
+        L.lor_free(h)
+
+
+@pytest.mark.parametrize("case", CASES[:5], ids=_ids)
+def test_pcg_solve(case, L, torch_dev):
+    torch = torch_dev
+    dim, n, p, V, mesh = _case(case)
+    print("case", case, flush=True)
+    h = L.lor_setup(dim, n, V, p)
+    try:
+        N = L.lor_ndofs(h)
+        K = HO.cg_stiffness(mesh, p)
+        bin_ = inputs.gaussian_rhs(N, 21)
+        b = torch.tensor(bin_, device="cuda")
+        x = torch.zeros_like(b)
+        info = L.lor_pcg_solve(h, b, x, rtol=1e-10, maxit=500)
+        B = S.SchwarzLOR(mesh, p)
+        _, it, hist = krylov.pcg(K, bin_, B.apply, tol=1e-10)
+        assert abs(info.iters - it) <= 1, (info.iters, it)
+        assert info.rel_res <= 1e-10
+        xs = x.cpu().numpy()
+        assert np.linalg.norm(bin_ - K @ xs) <= 1.05e-10 * np.linalg.norm(bin_)
+        assert abs(info.rel_res_true - np.linalg.norm(bin_ - K @ xs) / np.linalg.norm(bin_)) < 1e-12
+        xd = spla.spsolve(K.tocsc(), bin_)
+        assert np.abs(xs - xd).max() <= 1e-7 * np.abs(xd).max()
+    finally:
+        L.lor_free(h)
+
+
+def test_errors(L, torch_dev):
+    dim, n, p, V, mesh = _case(CASES[2])
+    with pytest.raises(L.LorError) as e:
+        L.lor_setup(dim, n, V, 0)
+    assert e.value.code == L.LOR_EINVAL
+    Vbad = V.copy()
+    Vbad[0, 0] = np.nan
+    with pytest.raises(L.LorError) as e:
+        L.lor_setup(dim, n, Vbad, p)
+    assert e.value.code == L.LOR_EINVAL
+    # an inverted element: swap two vertices of one element
+    Vinv = inputs.structured_vertices(3, 2)
+    Vinv[13] = [0.9, 0.9, 0.9]  # the centre vertex pushed through the far corner element
+    with pytest.raises(L.LorError) as e:
+        L.lor_setup(3, 2, Vinv, 2)
+    assert e.value.code == L.LOR_EJACOBIAN
+    h = L.lor_setup(dim, n, V, p)
+    try:
+        torch = torch_dev
+        N = L.lor_ndofs(h)
+        b = torch.tensor(inputs.gaussian_rhs(N, 1), device="cuda")
+        x = torch.zeros_like(b)
+        info = L.lor_pcg_solve(h, b, x, rtol=1e-14, maxit=2, check=False)
+        assert info.status == L.LOR_ENOCONV and info.iters == 2
+        b[0] = float("nan")
+        info = L.lor_pcg_solve(h, b, x, rtol=1e-8, maxit=10, check=False)
+        assert info.status == L.LOR_EINVAL
+    finally:
+        L.lor_free(h)
