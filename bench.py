@@ -1,0 +1,222 @@
+"""Benchmark: PCG DOFs/s to 1e-8 relative residual on one MI355X.
+
+Workload (default): 3D CG Poisson -Laplace(u) = f on the unit cube, 16^3 hexes
+with interior vertices perturbed by up to 10% of h (seed 1), p = 6 GLL
+elements (N = 857,375 unknowns), f from u = prod sin(pi x_i); float64 PCG
+preconditioned by LOR vertex-patch additive Schwarz (MDF-ILU(0) V-cycles,
+exact coarse solve), x0 = 0, stop at ||r|| <= 1e-8 ||b||.
+
+A step is one full solve from x0 = 0 (inputs resident in HBM); setup is done
+once before the timed region and reported separately.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def patch_algorithmic_bytes(dim, n, p, prec_bytes=8):
+    """Bytes one patch V-cycle launch must move: per (patch, smoothed level)
+    row the 13 strict-lower IC(0) entries and the pivot (14 values), per
+    global level row the 14 unique values of the symmetric Q1 stencil, and
+    the residual gather plus the read-modify-write of the correction (3
+    float64 per fine unknown)."""
+    from paper_1908_07071_amd.lor import lor_gll  # noqa: F401  (library must exist)
+    kept = _kept(p)
+    sizes = [len(k) - 1 for k in kept]
+    c = 14 if dim == 3 else 5
+    rows = 0
+    for k, s in enumerate(sizes[:-1]):
+        per = []
+        for v in range(n + 1):
+            lo = (v - 1) * s + 1 if v > 0 else 1
+            hi = (v + 1) * s - 1 if v < n else n * s - 1
+            per.append(max(hi - lo + 1, 0))
+        rows += sum(per) ** dim
+    glob = sum((n * s - 1) ** dim for s in sizes)
+    N = (n * p - 1) ** dim
+    return prec_bytes * c * (rows + glob) + 8 * 3 * N
+
+
+def apply_algorithmic_bytes(dim, n, p):
+    """Operator launch: x read + y read-modify-write (16 B per unknown) and the
+    6 (3 in 2D) float64 geometric factors per element node."""
+    N = (n * p - 1) ** dim
+    g = 48 if dim == 3 else 24
+    return 16 * N + g * n ** dim * (p + 1) ** dim
+
+
+def _kept(p):
+    levels = [list(range(p + 1))]
+    while len(levels[-1]) > 2:
+        cur = levels[-1]
+        inner = cur[1:-1]
+        levels.append([0] + [inner[k] for k in range(len(inner)) if k % 2 == 1] + [p])
+    return levels
+
+
+def cpu_baseline(dim, p, iters_full, budget_s=25.0):
+    """Time the float64 oracle (setup excluded) on a 2^3-element sample of the
+    same workload and scale to DOFs/s of the full solve."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import gll, highorder as HO, krylov, mesh as M, schwarz as S
+    from paper_1908_07071_amd import inputs
+
+    n = 2
+    V = inputs.structured_vertices(dim, n, 0.1, seed=1)
+    mesh = M.make_mesh(dim, n, V)
+    with threadpool_limits(1):
+        K = HO.cg_stiffness(mesh, p)
+        x, _ = gll.gll(p)
+        b = HO.cg_rhs(mesh, p, inputs.manufactured_f(M.global_node_coords(mesh, x, p)))
+        B = S.SchwarzLOR(mesh, p)
+        t0 = time.perf_counter()
+        k = 0
+        while True:
+            k += 2
+            t0 = time.perf_counter()
+            krylov.pcg(K, b, B.apply, tol=0.0, maxit=k)
+            dt = time.perf_counter() - t0
+            if dt > 3.0 or k >= 8 or dt * 2 > budget_s:
+                break
+    t_iter = dt / k
+    Ns = K.shape[0]
+    value = Ns / (t_iter * iters_full)
+    return {"value": value, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": (f"float64 NumPy/SciPy oracle, 1 thread: {k} PCG iterations on the same "
+                       f"workload at 2^3 elements (N={Ns}), {t_iter * 1e3:.1f} ms/iteration; "
+                       f"DOF/s = N_sample / (t_iter_sample * {iters_full} iterations of the full "
+                       f"solve), i.e. per-iteration cost taken linear in N; setup excluded")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=16)
+    ap.add_argument("--p", type=int, default=6)
+    ap.add_argument("--dim", type=int, default=3)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed",
+                    help="mixed: FP32 patch V-cycles inside FP64 flexible CG")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver is "
+              "single-device, see DESIGN.md for how it would shard", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1908_07071_amd import inputs
+    from paper_1908_07071_amd import lor as L
+
+    dim, n, p = args.dim, args.n, args.p
+    dev = torch.device("cuda:0")
+    V = inputs.structured_vertices(dim, n, 0.1, seed=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    opt = L.lor_default_options()
+    opt.precision = L.LOR_PREC_MIXED if args.precision == "mixed" else L.LOR_PREC_FP64
+    h = L.lor_setup(dim, n, V, p, options=opt)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print(f"[bench] setup done in {setup_s:.1f}s", file=sys.stderr, flush=True)
+    N = L.lor_ndofs(h)
+    coords = L.lor_dof_coords(h, dim)
+    f = torch.tensor(inputs.manufactured_f(coords), device=dev)
+    b = torch.empty_like(f)
+    L.lor_assemble_rhs(h, f, b)
+    x = torch.zeros_like(b)
+
+    for _ in range(args.warmup):
+        info = L.lor_pcg_solve(h, b, x, rtol=args.rtol, maxit=1000)
+    torch.cuda.synchronize()
+    L.lor_timing(h, True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info = L.lor_pcg_solve(h, b, x, rtol=args.rtol, maxit=1000)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    L.lor_timing(h, False)
+    ms_step = 1e3 * t_total / args.steps
+    tA, nA = L.lor_timing_read(h, L.LOR_T_APPLY_A)
+    tP, nP = L.lor_timing_read(h, L.LOR_T_PATCH)
+    tC, nC = L.lor_timing_read(h, L.LOR_T_COARSE)
+    print(f"[bench] {args.steps} solves: {ms_step:.2f} ms/solve, iters={info.iters}, "
+          f"rel_res_true={info.rel_res_true:.2e}", file=sys.stderr, flush=True)
+
+    # operator throughput: 100 back-to-back applies, HIP events
+    xr = torch.tensor(inputs.uniform_vector(N, 3), device=dev)
+    y = torch.empty_like(xr)
+    for _ in range(5):
+        L.lor_apply_A(h, xr, y)
+    L.lor_timing(h, True)
+    for _ in range(100):
+        L.lor_apply_A(h, xr, y)
+    tAop, nAop = L.lor_timing_read(h, L.LOR_T_APPLY_A)
+    L.lor_timing(h, False)
+    t_apply = tAop / nAop * 1e-3
+
+    # dominant kernel of the solve
+    kernels = {
+        "patch_vcycle": (tP / max(nP, 1), patch_algorithmic_bytes(dim, n, p)),
+        "apply_A": (tA / max(nA, 1), apply_algorithmic_bytes(dim, n, p)),
+    }
+    dom = "patch_vcycle" if tP >= tA else "apply_A"
+    avg_ms, abytes = kernels[dom]
+    achieved = abytes / (avg_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": "PCG DOFs/s to 1e-8 rel. residual (FP64); operator GDOF/s",
+        "value": N / (ms_step * 1e-3),
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{dim}D CG Poisson, {n}^{dim} hexes with interior vertices perturbed <=10% h "
+                         f"(seed 1), p={p}, f from u=prod sin(pi x_i); FP64 PCG + LOR vertex-patch "
+                         f"Schwarz (MDF-ILU(0) V-cycles, exact coarse) to {args.rtol:g}"),
+            "N": N, "iters": info.iters, "rel_res_true": info.rel_res_true,
+            "precision": "fp64", "setup_s": round(setup_s, 3),
+        },
+        "operator_gdofs": N / t_apply / 1e9,
+        "operator_ms": t_apply * 1e3,
+        "kernel_ms_per_solve": {
+            "apply_A": tA / args.steps, "patch_vcycle": tP / args.steps, "coarse": tC / args.steps,
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "algorithmic_bytes_per_launch": abytes, "avg_launch_ms": avg_ms,
+        },
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(dim, p, info.iters)
+    L.lor_free(h)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

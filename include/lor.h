@@ -170,6 +170,18 @@ int lor_export_maps(const lor_handle_t *h, int which, int32_t *host_out, int64_t
  * If host_out is NULL only *len is set.  Returns LOR_EINVAL for a bad k. */
 int lor_export_stencils(const lor_handle_t *h, int level, double *host_out, int64_t *len);
 
+/* Per-kernel timing with HIP events recorded on the calling stream around
+ * every launch of the hot kernels (for roofline measurements).
+ * lor_timing(h, 1) clears the record and starts recording, lor_timing(h, 0)
+ * stops.  lor_timing_read returns the summed duration (ms) and the number of
+ * launches of one kernel class since the last reset; it synchronises the
+ * recorded events.  which: */
+#define LOR_T_APPLY_A   0   /* sum-factorized operator kernel            */
+#define LOR_T_PATCH     1   /* patch V-cycle kernel (all patches)        */
+#define LOR_T_COARSE    2   /* coarse restrict + inverse GEMV + prolong  */
+int lor_timing(lor_handle_t *h, int enable);
+int lor_timing_read(const lor_handle_t *h, int which, double *total_ms, int64_t *count);
+
 /* ---- host-only utilities (no device needed): the set-up building blocks,
  * exposed so that their integer results can be checked bit for bit. ---- */
 

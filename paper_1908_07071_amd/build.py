@@ -22,6 +22,7 @@ OBJDIR = os.path.join(HERE, "_build")
 SOURCES = [
     ("basis.cpp", []),
     ("mdf.cpp", ["-ffp-contract=off"]),
+    ("sweep_pack.cpp", []),
     ("lor_api.cpp", []),
     ("k_setup.hip", ["-ffp-contract=off"]),
     ("k_operator.hip", []),

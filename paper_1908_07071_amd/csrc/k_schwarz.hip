@@ -1,15 +1,18 @@
 // Vertex-patch additive Schwarz: one element-structured LOR V-cycle per patch
 // (Sections 3.2-3.4), summed into z (eq. as).
 //
-// One workgroup (a single wavefront) per patch.  The patch vectors of every
-// level live in LDS as zero-padded boxes, so stencil neighbours outside the
-// patch (the patch Dirichlet boundary) read zeros without branches.  The
-// ILU(0) sweeps follow the dependency levels of the MDF order computed at
-// set-up: rows of one level are independent and spread over the lanes; the
-// wavefront synchronises between levels.  Stencils come from the global level
-// operators (patch matrices are their principal sub-matrices), factors from
-// the per-patch blocks.  The corrections of overlapping patches are added
-// with FP64 atomics.
+// One wavefront per patch.  The ILU(0) sweeps in MDF order are a chain of
+// dependency levels of a few rows each, so the kernel is built around latency:
+//  * patch vectors stay in LDS (unpadded boxes); at the finest level only two
+//    (the residual is re-gathered from global memory when needed), so several
+//    patches share a CU;
+//  * the wavefront synchronises with wave-scope fences only (no s_barrier,
+//    no waits on outstanding global loads);
+//  * each triangular sweep is stored in chunks of consecutive dependency
+//    levels, at most one row per lane and chunk, interleaved by lane so that
+//    a chunk arrives in a few coalesced loads; chunk c+1 is loaded into a
+//    second register buffer while the levels of chunk c run.
+// Corrections of overlapping patches are added with FP64 atomics.
 #include <hip/hip_runtime.h>
 
 #include "lor_internal.h"
@@ -18,18 +21,42 @@ namespace lor {
 
 namespace {
 
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <int DIM>
 struct Box {
-  int m[3];    // unknowns per direction
-  int mp[3];   // padded extents (m + 2)
-  int lo[3];   // first level-grid index per direction
-  int n;       // unknowns
-  __device__ int pad(int i) const {
-    const int ix = i % m[0], iy = (i / m[0]) % m[1], iz = DIM == 3 ? i / (m[0] * m[1]) : 0;
-    return (ix + 1) + mp[0] * ((iy + 1) + mp[1] * (DIM == 3 ? iz + 1 : 0));
-  }
-  __device__ int padded_size() const { return mp[0] * mp[1] * (DIM == 3 ? mp[2] : 1); }
+  int m[3];   // unknowns per direction
+  int lo[3];  // first level-grid index per direction
+  int n;      // unknowns
 };
+
+// Box of the patch of vertex v at level k (recomputed instead of stored, so
+// that nothing is indexed dynamically in private memory).
+template <int DIM>
+__device__ __forceinline__ Box<DIM> make_box(const PatchArgs &pa, const int *v, int k) {
+  Box<DIM> b;
+  const int s = pa.s[k];
+  b.n = 1;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d >= DIM) {
+      b.m[d] = 1;
+      b.lo[d] = 0;
+      continue;
+    }
+    const int nn = pa.md.n[d];
+    const int lo = v[d] > 0 ? (v[d] - 1) * s + 1 : 1;
+    const int hi = v[d] < nn ? (v[d] + 1) * s - 1 : nn * s - 1;
+    b.lo[d] = lo;
+    b.m[d] = max(hi - lo + 1, 0);
+    b.n *= b.m[d];
+  }
+  return b;
+}
 
 template <int DIM>
 __device__ inline int64_t level_gidx(const Box<DIM> &bx, int i, const int *lng) {
@@ -39,253 +66,393 @@ __device__ inline int64_t level_gidx(const Box<DIM> &bx, int i, const int *lng) 
          int64_t(lng[0]) * (int64_t(bx.lo[1] + iy) + (DIM == 3 ? int64_t(lng[1]) * (bx.lo[2] + iz) : 0));
 }
 
-template <int DIM>
-__device__ inline int slot_off(int s, const int *mp) {
-  const int ox = s % 3 - 1, oy = (s / 3) % 3 - 1, oz = DIM == 3 ? s / 9 - 1 : 0;
-  return ox + mp[0] * (oy + mp[1] * oz);
+// LDS layout of one patch: level 0 holds X, R; level k > 0 holds X, B, R.
+// which: 0 = X, 1 = B, 2 = R.
+template <int DIM, typename T>
+__device__ __forceinline__ T *lds_vec(T *lds, const PatchArgs &pa, const int *v, int k, int which) {
+  int off = 0;
+  for (int q = 0; q < k; ++q) off += (q == 0 ? 2 : 3) * make_box<DIM>(pa, v, q).n;
+  const int n = make_box<DIM>(pa, v, k).n;
+  if (k == 0) return lds + (which == 0 ? 0 : n);
+  return lds + off + which * n;
 }
 
-// forward sweep  w_i = y_i - sum_{earlier m} l_im w_m   (in place)
-template <int DIM>
-__device__ void sweep_fwd(double *Y, const Box<DIM> &bx, const char *blk, int depth) {
-  constexpr int NS = DIM == 3 ? 27 : 9;
-  const int n = bx.n;
-  const int *idx = reinterpret_cast<const int *>(blk);
-  const int *lvl = idx + n;
-  const int *msk = lvl + n + 1;
-  const double *val = reinterpret_cast<const double *>(blk + factor_vals_offset(n));
-  int off[NS];
-  for (int s = 0; s < NS; ++s) off[s] = slot_off<DIM>(s, bx.mp);
-  for (int d = 0; d < depth; ++d) {
-    for (int t = lvl[d] + threadIdx.x; t < lvl[d + 1]; t += blockDim.x) {
-      const int pi = bx.pad(idx[t]);
-      const int mk = msk[t];
-      double acc = Y[pi];
-      for (int s = 0; s < NS; ++s)
-        if ((mk >> s) & 1) acc -= val[int64_t(s) * n + t] * Y[pi + off[s]];
-      Y[pi] = acc;
+// ---------------------------------------------------------------- sweeps
+// A sweep block (layout at kChunkRows) is consumed chunk by chunk from two
+// register buffers: wait for chunk c, issue the coalesced loads of chunk c+1
+// into the other buffer, then run the dependency levels of chunk c from
+// registers and LDS.  The only wait on global memory is the one before new
+// loads are issued, so the loads of a chunk overlap a whole chunk of levels.
+
+// Word k of a register record (k is a constant after unrolling, so the
+// record stays in registers).
+template <int QM>
+__device__ __forceinline__ uint32_t wget(const uint4 (&R)[QM], int k) {
+  const uint4 q = R[k >> 2];
+  switch (k & 3) {
+    case 0: return q.x;
+    case 1: return q.y;
+    case 2: return q.z;
+    default: return q.w;
+  }
+}
+template <typename T, int QM>
+__device__ __forceinline__ T word_get(const uint4 (&R)[QM], int b);
+template <>
+__device__ __forceinline__ float word_get<float, 10>(const uint4 (&R)[10], int b) {
+  return __uint_as_float(wget(R, b));
+}
+template <>
+__device__ __forceinline__ float word_get<float, 11>(const uint4 (&R)[11], int b) {
+  return __uint_as_float(wget(R, b));
+}
+template <>
+__device__ __forceinline__ double word_get<double, 17>(const uint4 (&R)[17], int b) {
+  return __hiloint2double(int(wget(R, b + 1)), int(wget(R, b)));
+}
+
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+// Loads this lane's record of a chunk (myq quads).  The loads are branch
+// free: quads the lane does not need read a zero quad of the block header, so
+// the data goes straight into the record registers and nothing waits for it
+// until the chunk is used.
+template <typename T, bool FWD, int QM>
+__device__ __forceinline__ void load_chunk(uint4 (&R)[QM], const uint4 *src, int myq, const uint4 *zero) {
+#pragma unroll
+  for (int q = 0; q < QM; ++q) {
+    const uint4 *a = q < myq ? src + (q * 64 + int(threadIdx.x)) : zero;
+    R[q] = *a;
+  }
+}
+
+template <typename T, bool FWD, int QM>
+__device__ __forceinline__ void run_chunk(const uint4 (&R)[QM], T *Y, uint32_t hdr) {
+  constexpr int H = sweep_head_words<T>(FWD), PW = sweep_pair_words<T>(), SZ = int(sizeof(T)) / 4;
+  constexpr int NP = (kMaxCouplings + 1) / 2;
+  const int nsteps = (hdr >> 8) & 0xFF;
+  (void)hdr;
+  const uint32_t d0 = R[0].x;
+  const int mystep = (d0 >> 31) ? int((d0 >> 16) & 0x3F) : -1;
+  const int row = int(d0 & 0xFFFF);
+  for (int s = 0; s < nsteps; ++s) {
+    if (mystep == s) {
+      T acc0 = FWD ? Y[row] : Y[row] * word_get<T, QM>(R, 1);
+      T acc1 = T(0);
+      // all LDS reads are issued before the FMAs, with no branch between them
+      // (padding pairs have zero values and offsets: they read the row itself)
+      constexpr int HALF = (NP + 1) / 2;  // two halves bound the live registers
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        T y[2 * HALF];
+#pragma unroll
+        for (int t = 0; t < HALF; ++t) {
+          const int p = h * HALF + t;
+          if (p < NP) {
+            const uint32_t o = wget(R, H + p * PW + PW - 1);
+            y[2 * t] = Y[row + int(short(o & 0xFFFF))];
+            y[2 * t + 1] = Y[row + int(short(o >> 16))];
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < HALF; ++t) {
+          const int p = h * HALF + t;
+          if (p < NP) {
+            acc0 -= word_get<T, QM>(R, H + p * PW) * y[2 * t];
+            acc1 -= word_get<T, QM>(R, H + p * PW + SZ) * y[2 * t + 1];
+          }
+        }
+      }
+      Y[row] = acc0 + acc1;
     }
-    __syncthreads();
+    wave_sync();
   }
 }
 
-// backward sweep  y_i = w_i / D_i - sum_{later m} l_mi y_m   (in place)
-template <int DIM>
-__device__ void sweep_bwd(double *Y, const Box<DIM> &bx, const char *blk, int depth) {
-  constexpr int NS = DIM == 3 ? 27 : 9;
-  constexpr int C = NS / 2;
-  const int n = bx.n;
-  const int *idx = reinterpret_cast<const int *>(blk);
-  const int *lvl = idx + n;
-  const int *msk = lvl + n + 1;
-  const double *val = reinterpret_cast<const double *>(blk + factor_vals_offset(n));
-  int off[NS];
-  for (int s = 0; s < NS; ++s) off[s] = slot_off<DIM>(s, bx.mp);
-  for (int d = depth - 1; d >= 0; --d) {
-    for (int t = lvl[d] + threadIdx.x; t < lvl[d + 1]; t += blockDim.x) {
-      const int pi = bx.pad(idx[t]);
-      const int mk = msk[t];
-      double acc = Y[pi] * val[int64_t(C) * n + t];
-      for (int s = 0; s < NS; ++s)
-        if (s != C && !((mk >> s) & 1)) acc -= val[int64_t(s) * n + t] * Y[pi + off[s]];
-      Y[pi] = acc;
+// forward:  w_i = y_i - sum_{earlier m} l_im w_m
+// backward: y_i = w_i / D_i - sum_{later m} l_mi y_m       (both in place on Y)
+template <typename T, bool FWD>
+__device__ __forceinline__ void sweep(T *Y, const char *blk) {
+  constexpr int QM = sweep_quads<T>(FWD, kMaxCouplings);
+  const int nch = *reinterpret_cast<const int *>(blk);
+  uint32_t hdr = reinterpret_cast<const uint32_t *>(blk)[1];
+  const int lane = threadIdx.x;
+  auto nextq = [&](uint32_t w0) { return lane == 63 ? 1 : int((w0 >> 22) & 0x1F); };
+  const uint4 *src = reinterpret_cast<const uint4 *>(blk + kSweepHeader);
+  const uint4 *zero = reinterpret_cast<const uint4 *>(blk + kSweepZero);
+  uint4 A[QM], B[QM];
+  load_chunk<T, FWD, QM>(A, src, int(reinterpret_cast<const unsigned char *>(blk)[16 + lane]), zero);
+  src += int(hdr & 0xFF) * 64;
+  for (int c = 0; c < nch; c += 2) {
+    wait_vm();
+    const uint32_t h1 = __builtin_amdgcn_readlane(A[0].x, 63);
+    if (c + 1 < nch) {
+      load_chunk<T, FWD, QM>(B, src, nextq(A[0].x), zero);
+      src += int(h1 & 0xFF) * 64;
     }
-    __syncthreads();
+    run_chunk<T, FWD, QM>(A, Y, hdr);
+    if (c + 1 >= nch) break;
+    wait_vm();
+    const uint32_t h2 = __builtin_amdgcn_readlane(B[0].x, 63);
+    if (c + 2 < nch) {
+      load_chunk<T, FWD, QM>(A, src, nextq(B[0].x), zero);
+      src += int(h2 & 0xFF) * 64;
+    }
+    run_chunk<T, FWD, QM>(B, Y, h1);
+    hdr = h2;
   }
 }
 
-// R = B - A X on one level (A from the global level stencil)
-template <int DIM>
-__device__ void residual(double *R, const double *B, const double *X, const Box<DIM> &bx,
-                         const double *__restrict__ st, int64_t npts, const int *lng) {
+// R = B - A X on one level (A from the global level stencil).  GB: the right
+// side is the global residual (finest level) instead of B in LDS.  Two rows
+// per lane and iteration, with all their global loads issued together.
+template <int DIM, typename T, typename ST, bool GB>
+__device__ __forceinline__ void residual(T *R, const T *B, const T *X, const Box<DIM> &bx,
+                                         const ST *__restrict__ st, int64_t npts, const int *lng,
+                                         const double *__restrict__ rglob, const MeshDims &md) {
   constexpr int NS = DIM == 3 ? 27 : 9;
-  int off[NS];
-  for (int s = 0; s < NS; ++s) off[s] = slot_off<DIM>(s, bx.mp);
-  for (int i = threadIdx.x; i < bx.n; i += blockDim.x) {
-    const int pi = bx.pad(i);
-    const int64_t g = level_gidx<DIM>(bx, i, lng);
-    double acc = B[pi];
-    for (int s = 0; s < NS; ++s) acc -= st[int64_t(s) * npts + g] * X[pi + off[s]];
-    R[pi] = acc;
+  constexpr int RB = 2;
+  const int mx = bx.m[0], my = bx.m[1], mz = bx.m[2];
+  const int ox = md.dirichlet ? 1 : 0;
+  for (int i0 = threadIdx.x; i0 < bx.n; i0 += 64 * RB) {
+    ST a[RB][NS];
+    T acc[RB];
+    int ii[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      ii[r] = min(i0 + 64 * r, bx.n - 1);  // clamped: loads stay valid, store is skipped
+      const int64_t g = level_gidx<DIM>(bx, ii[r], lng);
+      if (GB) {
+        const int gx = int(g % md.ng[0]), gy = int((g / md.ng[0]) % md.ng[1]),
+                  gz = DIM == 3 ? int(g / (int64_t(md.ng[0]) * md.ng[1])) : 0;
+        acc[r] = T(rglob[int64_t(gx - ox) +
+                         int64_t(md.nu[0]) * (int64_t(gy - ox) + (DIM == 3 ? int64_t(md.nu[1]) * (gz - ox) : 0))]);
+      } else {
+        acc[r] = B[ii[r]];
+      }
+      // every patch row is strictly inside the level grid: all 3^d entries exist
+#pragma unroll
+      for (int s = 0; s < NS; ++s) a[r][s] = st[int64_t(s) * npts + g];
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int i = ii[r];
+      const int ix = i % mx, iy = (i / mx) % my, iz = DIM == 3 ? i / (mx * my) : 0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int sx = s % 3 - 1, sy = (s / 3) % 3 - 1, sz = DIM == 3 ? s / 9 - 1 : 0;
+        const int jx = ix + sx, jy = iy + sy, jz = iz + sz;
+        const bool in = jx >= 0 && jx < mx && jy >= 0 && jy < my && (DIM == 2 || (jz >= 0 && jz < mz));
+        const T xv = X[in ? jx + mx * (jy + my * jz) : i];
+        acc[r] -= in ? T(a[r][s]) * xv : T(0);
+      }
+      if (i0 + 64 * r < bx.n) R[i] = acc[r];
+    }
   }
-  __syncthreads();
+  wave_sync();
 }
 
-template <int DIM>
-__global__ __launch_bounds__(64) void k_patch_vcycle(PatchArgs pa, const double *__restrict__ r,
+template <int DIM, typename T, typename ST, int W>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_patch_vcycle(PatchArgs pa, const double *__restrict__ r,
                                                      double *__restrict__ z, const double *flag) {
   if (flag && flag[S_DONE] != 0.0) return;
-  extern __shared__ double lds[];
+  extern __shared__ __align__(16) char lds_raw[];
+  T *lds = reinterpret_cast<T *>(lds_raw);
   const int j = blockIdx.x;
   const int L = pa.nlev;
   const MeshDims &md = pa.md;
   const int v[3] = {j % pa.nv[0], (j / pa.nv[0]) % pa.nv[1],
                     DIM == 3 ? j / (pa.nv[0] * pa.nv[1]) : 0};
   int typ[3] = {1, 1, 1};
-  Box<DIM> bx[kMaxLevels];
-  for (int k = 0; k < L; ++k) {
-    const int s = pa.s[k];
-    int n = 1;
-    for (int d = 0; d < 3; ++d) {
-      if (d >= DIM) {
-        bx[k].m[d] = 1;
-        bx[k].mp[d] = 1;
-        bx[k].lo[d] = 0;
-        continue;
-      }
-      const int nn = md.n[d];
-      const int lo = v[d] > 0 ? (v[d] - 1) * s + 1 : 1;
-      const int hi = v[d] < nn ? (v[d] + 1) * s - 1 : nn * s - 1;
-      bx[k].lo[d] = lo;
-      bx[k].m[d] = hi - lo + 1;
-      bx[k].mp[d] = bx[k].m[d] + 2;
-      n *= max(bx[k].m[d], 0);
-    }
-    bx[k].n = n;
-  }
   for (int d = 0; d < DIM; ++d) typ[d] = v[d] == 0 ? 0 : (v[d] == md.n[d] ? 2 : 1);
-  if (bx[0].n <= 0) return;
-
-  for (int i = threadIdx.x; i < pa.lds_total; i += blockDim.x) lds[i] = 0.0;
-  __syncthreads();
-  double *X[kMaxLevels], *B[kMaxLevels], *R[kMaxLevels];
-  for (int k = 0; k < L; ++k) {
-    const int ps = bx[k].padded_size();
-    X[k] = lds + pa.lds_offs[k];
-    B[k] = X[k] + ps;
-    R[k] = B[k] + ps;
+  const Box<DIM> b0 = make_box<DIM>(pa, v, 0);
+  if (b0.n <= 0) return;
+  {
+    int tot = 0;
+    for (int k = 0; k < L; ++k) tot += (k == 0 ? 2 : 3) * make_box<DIM>(pa, v, k).n;
+    for (int i = threadIdx.x; i < tot; i += 64) lds[i] = T(0);
   }
-  // gather the residual of the patch unknowns (level 0 = GLL grid)
+  wave_sync();
   const int ox = md.dirichlet ? 1 : 0;
-  for (int i = threadIdx.x; i < bx[0].n; i += blockDim.x) {
-    const int64_t g = level_gidx<DIM>(bx[0], i, md.ng);
+  auto lvec = [&](int i) -> int64_t {
+    const int64_t g = level_gidx<DIM>(b0, i, md.ng);
     const int gx = int(g % md.ng[0]), gy = int((g / md.ng[0]) % md.ng[1]),
               gz = DIM == 3 ? int(g / (int64_t(md.ng[0]) * md.ng[1])) : 0;
-    const int64_t li = int64_t(gx - ox) +
-                       int64_t(md.nu[0]) * (int64_t(gy - ox) + (DIM == 3 ? int64_t(md.nu[1]) * (gz - ox) : 0));
-    B[0][bx[0].pad(i)] = r[li];
+    return int64_t(gx - ox) +
+           int64_t(md.nu[0]) * (int64_t(gy - ox) + (DIM == 3 ? int64_t(md.nu[1]) * (gz - ox) : 0));
+  };
+  // pre-smoothing input: X_0 = r restricted to the patch
+  {
+    T *X0 = lds_vec<DIM, T>(lds, pa, v, 0, 0);
+    // batched: 8 loads in flight per lane (clamped index, predicated store)
+    for (int i0 = threadIdx.x; i0 < b0.n; i0 += 64 * 8) {
+      T t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = T(r[lvec(min(i0 + 64 * q, b0.n - 1))]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (i0 + 64 * q < b0.n) X0[i0 + 64 * q] = t[q];
+    }
   }
-  __syncthreads();
+  wave_sync();
 
-  const int nf = L - 1;  // levels with smoothing
+  const int nf = L - 1;
   const int64_t fbase = int64_t(j) * (nf > 0 ? nf : 1);
+  const ST *const *stn = reinterpret_cast<const ST *const *>(pa.stencil);
   // ---------------- down
   for (int k = 0; k < nf; ++k) {
-    if (bx[k].n <= 0) break;
-    const char *blk = pa.fac + pa.fac_off[fbase + k];
-    const int depth = pa.depth[fbase + k];
-    for (int i = threadIdx.x; i < bx[k].n; i += blockDim.x) {
-      const int pi = bx[k].pad(i);
-      X[k][pi] = B[k][pi];
+    const Box<DIM> fb = make_box<DIM>(pa, v, k);
+    if (fb.n <= 0) break;
+    T *Xk = lds_vec<DIM, T>(lds, pa, v, k, 0);
+    T *Bk = k > 0 ? lds_vec<DIM, T>(lds, pa, v, k, 1) : nullptr;
+    T *Rk = lds_vec<DIM, T>(lds, pa, v, k, 2);
+    const char *bf = pa.fac + pa.fac_off[2 * (fbase + k)];
+    const char *bb = pa.fac + pa.fac_off[2 * (fbase + k) + 1];
+    if (k > 0) {
+      for (int i = threadIdx.x; i < fb.n; i += 64) Xk[i] = Bk[i];
+      wave_sync();
     }
-    __syncthreads();
-    sweep_fwd<DIM>(X[k], bx[k], blk, depth);
-    sweep_bwd<DIM>(X[k], bx[k], blk, depth);
-    residual<DIM>(R[k], B[k], X[k], bx[k], pa.stencil[k], pa.npts[k], pa.lng[k]);
-    // restriction B_{k+1} = P^T R_k
-    if (bx[k + 1].n > 0) {
-      const XferTab *tb[3];
-      for (int d = 0; d < DIM; ++d) tb[d] = &pa.xfer[k * 3 + typ[d]];
-      const Box<DIM> &cb = bx[k + 1];
-      const Box<DIM> &fb = bx[k];
-      for (int i = threadIdx.x; i < cb.n; i += blockDim.x) {
+    sweep<T, true>(Xk, bf);
+    sweep<T, false>(Xk, bb);
+    if (k == 0)
+      residual<DIM, T, ST, true>(Rk, Bk, Xk, fb, stn[k], pa.npts[k], pa.lng[k], r, md);
+    else
+      residual<DIM, T, ST, false>(Rk, Bk, Xk, fb, stn[k], pa.npts[k], pa.lng[k], r, md);
+    const Box<DIM> cb = make_box<DIM>(pa, v, k + 1);
+    if (cb.n > 0) {
+      T *Bc = lds_vec<DIM, T>(lds, pa, v, k + 1, 1);
+      const XferTab *tb0 = &pa.xfer[k * 3 + typ[0]];
+      const XferTab *tb1 = &pa.xfer[k * 3 + typ[1]];
+      const XferTab *tb2 = &pa.xfer[k * 3 + typ[DIM - 1]];
+      for (int i = threadIdx.x; i < cb.n; i += 64) {
         const int ci[3] = {i % cb.m[0], (i / cb.m[0]) % cb.m[1], DIM == 3 ? i / (cb.m[0] * cb.m[1]) : 0};
-        double acc = 0.0;
-        const int nz = DIM == 3 ? tb[2]->rcnt[ci[2]] : 1;
-        for (int cz = 0; cz < nz; ++cz) {
-          const int fz = DIM == 3 ? tb[2]->rf[ci[2]][cz] : 0;
-          const double wz = DIM == 3 ? tb[2]->rw[ci[2]][cz] : 1.0;
-          for (int cy = 0; cy < tb[1]->rcnt[ci[1]]; ++cy) {
-            const int fy = tb[1]->rf[ci[1]][cy];
-            const double wy = tb[1]->rw[ci[1]][cy] * wz;
-            for (int cx = 0; cx < tb[0]->rcnt[ci[0]]; ++cx) {
-              const int fx = tb[0]->rf[ci[0]][cx];
-              acc += tb[0]->rw[ci[0]][cx] * wy * R[k][fx + fb.mp[0] * (fy + fb.mp[1] * fz)];
-            }
-          }
+        // fixed 3 x 3 (x 3) gather, absent entries have weight 0 and index 0:
+        // every table load and LDS read is issued up front
+        int fx[3], fy[3], fz[3];
+        T wx[3], wy[3], wz[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          fx[a] = tb0->rf[ci[0]][a];
+          wx[a] = T(tb0->rw[ci[0]][a]);
+          fy[a] = tb1->rf[ci[1]][a];
+          wy[a] = T(tb1->rw[ci[1]][a]);
+          fz[a] = DIM == 3 ? tb2->rf[ci[2]][a] : 0;
+          wz[a] = DIM == 3 ? T(tb2->rw[ci[2]][a]) : T(a == 0 ? 1 : 0);
         }
-        B[k + 1][cb.pad(i)] = acc;
+        T acc = T(0);
+#pragma unroll
+        for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c)
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+              acc += wx[a] * wy[b] * wz[c] * Rk[fx[a] + fb.m[0] * (fy[b] + fb.m[1] * fz[c])];
+        Bc[i] = acc;
       }
-      __syncthreads();
+      wave_sync();
     }
   }
   // ---------------- coarsest level: exact (at most one unknown)
   {
     const int kc = L - 1;
-    if (bx[kc].n == 1 && threadIdx.x == 0) {
-      const int64_t g = level_gidx<DIM>(bx[kc], 0, pa.lng[kc]);
+    const Box<DIM> bc = make_box<DIM>(pa, v, kc);
+    if (bc.n == 1 && threadIdx.x == 0) {
+      const int64_t g = level_gidx<DIM>(bc, 0, pa.lng[kc]);
       constexpr int C = DIM == 3 ? 13 : 4;
-      const int pi = bx[kc].pad(0);
-      X[kc][pi] = B[kc][pi] / pa.stencil[kc][int64_t(C) * pa.npts[kc] + g];
+      T *Xc = lds_vec<DIM, T>(lds, pa, v, kc, 0);
+      const T rhs = kc == 0 ? Xc[0] : lds_vec<DIM, T>(lds, pa, v, kc, 1)[0];
+      Xc[0] = rhs / T(stn[kc][int64_t(C) * pa.npts[kc] + g]);
     }
-    __syncthreads();
+    wave_sync();
   }
   // ---------------- up
   for (int k = nf - 1; k >= 0; --k) {
-    if (bx[k].n <= 0) continue;
-    const char *blk = pa.fac + pa.fac_off[fbase + k];
-    const int depth = pa.depth[fbase + k];
-    if (bx[k + 1].n > 0) {
-      const XferTab *tb[3];
-      for (int d = 0; d < DIM; ++d) tb[d] = &pa.xfer[k * 3 + typ[d]];
-      const Box<DIM> &cb = bx[k + 1];
-      const Box<DIM> &fb = bx[k];
-      for (int i = threadIdx.x; i < fb.n; i += blockDim.x) {
+    const Box<DIM> fb = make_box<DIM>(pa, v, k);
+    if (fb.n <= 0) continue;
+    T *Xk = lds_vec<DIM, T>(lds, pa, v, k, 0);
+    T *Bk = k > 0 ? lds_vec<DIM, T>(lds, pa, v, k, 1) : nullptr;
+    T *Rk = lds_vec<DIM, T>(lds, pa, v, k, 2);
+    const char *bf = pa.fac + pa.fac_off[2 * (fbase + k)];
+    const char *bb = pa.fac + pa.fac_off[2 * (fbase + k) + 1];
+    const Box<DIM> cb = make_box<DIM>(pa, v, k + 1);
+    if (cb.n > 0) {
+      const T *Xc = lds_vec<DIM, T>(lds, pa, v, k + 1, 0);
+      const XferTab *tb0 = &pa.xfer[k * 3 + typ[0]];
+      const XferTab *tb1 = &pa.xfer[k * 3 + typ[1]];
+      const XferTab *tb2 = &pa.xfer[k * 3 + typ[DIM - 1]];
+      for (int i = threadIdx.x; i < fb.n; i += 64) {
         const int fi[3] = {i % fb.m[0], (i / fb.m[0]) % fb.m[1], DIM == 3 ? i / (fb.m[0] * fb.m[1]) : 0};
-        double acc = 0.0;
-        for (int bz = 0; bz < (DIM == 3 ? 2 : 1); ++bz) {
-          const int cz = DIM == 3 ? tb[2]->pc[fi[2]][bz] : 0;
-          const double wz = DIM == 3 ? tb[2]->pw[fi[2]][bz] : 1.0;
-          for (int by = 0; by < 2; ++by) {
-            const int cy = tb[1]->pc[fi[1]][by];
-            const double wy = tb[1]->pw[fi[1]][by] * wz;
-            for (int bxx = 0; bxx < 2; ++bxx) {
-              const int cx = tb[0]->pc[fi[0]][bxx];
-              acc += tb[0]->pw[fi[0]][bxx] * wy * X[k + 1][cx + cb.mp[0] * (cy + cb.mp[1] * cz)];
-            }
-          }
+        // fixed 2 x 2 (x 2) gather; sources on the patch boundary get weight 0
+        int cx[2], cy[2], cz[2];
+        T wx[2], wy[2], wz[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          cx[a] = tb0->pc[fi[0]][a];
+          wx[a] = T(tb0->pw[fi[0]][a]);
+          cy[a] = tb1->pc[fi[1]][a];
+          wy[a] = T(tb1->pw[fi[1]][a]);
+          cz[a] = DIM == 3 ? tb2->pc[fi[2]][a] : 0;
+          wz[a] = DIM == 3 ? T(tb2->pw[fi[2]][a]) : T(a == 0 ? 1 : 0);
+          const bool okx = cx[a] >= 0 && cx[a] < cb.m[0];
+          const bool oky = cy[a] >= 0 && cy[a] < cb.m[1];
+          const bool okz = DIM == 2 || (cz[a] >= 0 && cz[a] < cb.m[2]);
+          wx[a] = okx ? wx[a] : T(0);
+          cx[a] = okx ? cx[a] : 0;
+          wy[a] = oky ? wy[a] : T(0);
+          cy[a] = oky ? cy[a] : 0;
+          wz[a] = okz ? wz[a] : T(0);
+          cz[a] = okz ? cz[a] : 0;
         }
-        X[k][fb.pad(i)] += acc;
+        T acc = T(0);
+#pragma unroll
+        for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+              acc += wx[a] * wy[b] * wz[c] * Xc[cx[a] + cb.m[0] * (cy[b] + cb.m[1] * cz[c])];
+        Xk[i] += acc;
       }
-      __syncthreads();
+      wave_sync();
     }
-    residual<DIM>(R[k], B[k], X[k], bx[k], pa.stencil[k], pa.npts[k], pa.lng[k]);
-    sweep_fwd<DIM>(R[k], bx[k], blk, depth);
-    sweep_bwd<DIM>(R[k], bx[k], blk, depth);
-    for (int i = threadIdx.x; i < bx[k].n; i += blockDim.x) {
-      const int pi = bx[k].pad(i);
-      X[k][pi] += R[k][pi];
-    }
-    __syncthreads();
+    if (k == 0)
+      residual<DIM, T, ST, true>(Rk, Bk, Xk, fb, stn[k], pa.npts[k], pa.lng[k], r, md);
+    else
+      residual<DIM, T, ST, false>(Rk, Bk, Xk, fb, stn[k], pa.npts[k], pa.lng[k], r, md);
+    sweep<T, true>(Rk, bf);
+    sweep<T, false>(Rk, bb);
+    for (int i = threadIdx.x; i < fb.n; i += 64) Xk[i] += Rk[i];
+    wave_sync();
   }
   // scatter-add the correction
-  for (int i = threadIdx.x; i < bx[0].n; i += blockDim.x) {
-    const int64_t g = level_gidx<DIM>(bx[0], i, md.ng);
-    const int gx = int(g % md.ng[0]), gy = int((g / md.ng[0]) % md.ng[1]),
-              gz = DIM == 3 ? int(g / (int64_t(md.ng[0]) * md.ng[1])) : 0;
-    const int64_t li = int64_t(gx - ox) +
-                       int64_t(md.nu[0]) * (int64_t(gy - ox) + (DIM == 3 ? int64_t(md.nu[1]) * (gz - ox) : 0));
-    unsafeAtomicAdd(z + li, X[0][bx[0].pad(i)]);
+  {
+    const T *X0 = lds_vec<DIM, T>(lds, pa, v, 0, 0);
+    for (int i = threadIdx.x; i < b0.n; i += 64) unsafeAtomicAdd(z + lvec(i), double(X0[i]));
   }
+}
+
+template <int DIM, typename T, typename ST>
+hipError_t launch_t(const PatchArgs &pa, int npatch, const double *r, double *z, const double *flag,
+                    hipStream_t st) {
+  constexpr int W = DIM == 3 ? 26 : 8;
+  const size_t lds = size_t(pa.lds_total) * sizeof(T);
+  auto kern = k_patch_vcycle<DIM, T, ST, W>;
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (e != hipSuccess) return e;
+  kern<<<npatch, 64, lds, st>>>(pa, r, z, flag);
+  return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r, double *z,
                                const double *flag, hipStream_t st) {
-  const size_t lds = size_t(pa.lds_total) * sizeof(double);
-  if (pa.md.dim == 3) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_patch_vcycle<3>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return e;
-    k_patch_vcycle<3><<<npatch, 64, lds, st>>>(pa, r, z, flag);
-  } else {
-    hipError_t e = hipFuncSetAttribute((const void *)k_patch_vcycle<2>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return e;
-    k_patch_vcycle<2><<<npatch, 64, lds, st>>>(pa, r, z, flag);
+  if (pa.fp32) {
+    if (pa.md.dim == 3) return launch_t<3, float, float>(pa, npatch, r, z, flag, st);
+    return launch_t<2, float, float>(pa, npatch, r, z, flag, st);
   }
-  return hipGetLastError();
+  if (pa.md.dim == 3) return launch_t<3, double, double>(pa, npatch, r, z, flag, st);
+  return launch_t<2, double, double>(pa, npatch, r, z, flag, st);
 }
 
 }  // namespace lor

@@ -388,6 +388,12 @@ __global__ void k_fill(double *x, int64_t n, double v) {
     x[i] = v;
 }
 
+__global__ void k_to_float(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    d[i] = float(s[i]);
+}
+
 inline int grid_for(int64_t n, int bs) {
   int64_t g = (n + bs - 1) / bs;
   return int(g > 65536 ? 65536 : (g < 1 ? 1 : g));
@@ -466,6 +472,12 @@ hipError_t launch_gauss_jordan(int n, double *A, double *rowbuf, double *colbuf,
     k_gj_save<<<grid_for(n, 256), 256, 0, st>>>(n, k, A, rowbuf, colbuf, bad);
     k_gj_update<<<grid_for(tot, 256), 256, 0, st>>>(n, k, A, rowbuf, colbuf);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_to_float<<<grid_for(n, 256), 256, 0, st>>>(src, dst, n);
   return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ struct lor_handle {
   int64_t npts[kMaxLevels] = {};
   char *d_fac = nullptr;
   int64_t *d_fac_off = nullptr;
-  int *d_depth = nullptr;
+  int64_t fac_bytes = 0;
   XferTab *d_xfer = nullptr;
   double *d_A0inv = nullptr, *d_rc = nullptr, *d_xc = nullptr;
   double *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr, *d_rold = nullptr;
@@ -47,6 +47,19 @@ struct lor_handle {
   std::vector<int32_t> order_all, order_off, sched_all, sched_off;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool has_prec = false;
+  // per-kernel event timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tspans[3];
+  hipEvent_t next_event() {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
+  }
 
   template <class T>
   hipError_t alloc(T **ptr, size_t count) {
@@ -64,6 +77,7 @@ struct lor_handle {
     if (h_scal) (void)hipHostFree(h_scal);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
 };
 
@@ -127,12 +141,12 @@ XferTab build_xfer(const lor_handle &h, int k, int type) {
       w[1] = (x[a] - xl) / (xh - xl);
     }
     for (int b = 0; b < 2; ++b) {
-      t.pc[f][b] = cidx[b] - clo + 1;  // padded coarse index (halo = patch boundary)
+      t.pc[f][b] = cidx[b] - clo;  // may be -1 or mc: on the patch boundary
       t.pw[f][b] = w[b];
       const int cl = cidx[b] - clo;
       if (w[b] != 0.0 && cl >= 0 && cl < t.mc) {
         const int c = t.rcnt[cl]++;
-        t.rf[cl][c] = f + 1;
+        t.rf[cl][c] = f;
         t.rw[cl][c] = w[b];
       }
     }
@@ -262,23 +276,13 @@ int build_coarse(lor_handle &h, const std::vector<double> &st0, hipStream_t st) 
 
 int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hipStream_t st) {
   const int dim = h.dim, NS = nslots(dim), L = h.L, nf = L - 1;
+  const bool mixed = h.opt.precision == LOR_PREC_MIXED;
   const int nv[3] = {h.n[0] + 1, h.n[1] + 1, dim == 3 ? h.n[2] + 1 : 1};
   h.J = nv[0] * nv[1] * nv[2];
   const int nfl = std::max(nf, 1);
-  std::vector<int64_t> off(size_t(h.J) * nfl, -1);
-  std::vector<int> depth(size_t(h.J) * nfl, 0);
-  int64_t total = 0;
-  for (int j = 0; j < h.J; ++j)
-    for (int k = 0; k < nf; ++k) {
-      PatchBox b = patch_box(h, j, k);
-      if (b.n <= 0) continue;
-      off[size_t(j) * nfl + k] = total;
-      total += factor_block_bytes(b.n, NS);
-    }
-  std::vector<char> pool(std::max<int64_t>(total, 16), 0);
   h.order_off.assign(size_t(h.J) * nf + 1, 0);
   h.sched_off.assign(size_t(h.J) * nf + 1, 0);
-  // offsets into the concatenated orders / schedules (known sizes up front)
+  // offsets into the concatenated orders (known sizes up front)
   {
     int32_t acc = 0;
     for (int j = 0; j < h.J; ++j)
@@ -290,6 +294,7 @@ int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hi
     h.order_all.assign(acc, 0);
   }
   std::vector<std::vector<int>> lvls(size_t(h.J) * nfl);
+  std::vector<std::vector<char>> blocks(size_t(h.J) * nfl * 2);  // forward, backward
   std::atomic<int> next{0};
   std::atomic<int> err{LOR_OK};
   const int ntask = h.J * nf;
@@ -317,22 +322,13 @@ int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hi
         err.store(rc);
         break;
       }
-      const int n = b.n;
-      char *blk = pool.data() + off[size_t(j) * nfl + k];
-      int32_t *idx = reinterpret_cast<int32_t *>(blk);
-      int32_t *lvl = idx + n;
-      int32_t *msk = lvl + n + 1;
-      double *val = reinterpret_cast<double *>(blk + factor_vals_offset(n));
-      const int C = NS / 2;
-      for (int t = 0; t < n; ++t) {
-        const int i = res.sched[t];
-        idx[t] = i;
-        msk[t] = res.earlier[i];
-        for (int s = 0; s < NS; ++s)
-          val[int64_t(s) * n + t] = s == C ? 1.0 / res.D[i] : res.L[size_t(i) * NS + s];
+      if (mixed) {
+        blocks[2 * (size_t(j) * nfl + k)] = pack_sweep<float>(res, dim, b.m, true);
+        blocks[2 * (size_t(j) * nfl + k) + 1] = pack_sweep<float>(res, dim, b.m, false);
+      } else {
+        blocks[2 * (size_t(j) * nfl + k)] = pack_sweep<double>(res, dim, b.m, true);
+        blocks[2 * (size_t(j) * nfl + k) + 1] = pack_sweep<double>(res, dim, b.m, false);
       }
-      for (size_t d = 0; d < res.level_ptr.size(); ++d) lvl[d] = res.level_ptr[d];
-      depth[size_t(j) * nfl + k] = int(res.level_ptr.size()) - 1;
       std::copy(res.order.begin(), res.order.end(), h.order_all.begin() + h.order_off[size_t(j) * nf + k]);
       lvls[size_t(j) * nfl + k] = res.level_ptr;
     }
@@ -353,12 +349,21 @@ int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hi
     h.sched_all.reserve(acc);
     for (int t = 0; t < ntask; ++t) h.sched_all.insert(h.sched_all.end(), lvls[t].begin(), lvls[t].end());
   }
-  HIPCHK(h.alloc(&h.d_fac, pool.size()));
+  std::vector<int64_t> off(blocks.size(), -1);
+  int64_t total = 0;
+  for (size_t t = 0; t < blocks.size(); ++t) {
+    if (blocks[t].empty()) continue;
+    off[t] = total;
+    total += align16(int64_t(blocks[t].size()));
+  }
+  h.fac_bytes = total;
+  HIPCHK(h.alloc(&h.d_fac, size_t(std::max<int64_t>(total, 16))));
   HIPCHK(h.alloc(&h.d_fac_off, off.size()));
-  HIPCHK(h.alloc(&h.d_depth, depth.size()));
-  HIPCHK(hipMemcpyAsync(h.d_fac, pool.data(), pool.size(), hipMemcpyHostToDevice, st));
+  for (size_t t = 0; t < blocks.size(); ++t)
+    if (!blocks[t].empty())
+      HIPCHK(hipMemcpyAsync(h.d_fac + off[t], blocks[t].data(), blocks[t].size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(h.d_fac_off, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(h.d_depth, depth.data(), depth.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));  // host blocks are freed on return
   // transfer tables
   std::vector<XferTab> xt(size_t(std::max(nf, 1)) * 3);
   for (int k = 0; k < nf; ++k)
@@ -373,27 +378,31 @@ int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hi
   for (int k = 0; k < L; ++k) {
     const int s = int(h.kept[k].size()) - 1;
     pa.s[k] = s;
-    pa.stencil[k] = h.d_stencil[k];
+    if (mixed) {
+      float *f32 = nullptr;
+      HIPCHK(h.alloc(&f32, size_t(NS) * h.npts[k]));
+      HIPCHK(launch_to_float(h.d_stencil[k], f32, int64_t(NS) * h.npts[k], st));
+      pa.stencil[k] = reinterpret_cast<const double *>(f32);  // read as float by the kernel
+    } else {
+      pa.stencil[k] = h.d_stencil[k];
+    }
     pa.npts[k] = h.npts[k];
     for (int d = 0; d < 3; ++d) pa.lng[k][d] = d < dim ? h.n[d] * s + 1 : 1;
   }
   pa.xfer = h.d_xfer;
   pa.fac = h.d_fac;
   pa.fac_off = h.d_fac_off;
-  pa.depth = h.d_depth;
+  // LDS of the largest patch: level 0 X, R; coarser levels X, B, R
   int tot = 0;
   for (int k = 0; k < L; ++k) {
     const int s = pa.s[k];
     int ps = 1;
-    for (int d = 0; d < dim; ++d) {
-      const int mmax = h.n[d] >= 2 ? 2 * s - 1 : s - 1;
-      ps *= std::max(mmax, 0) + 2;
-    }
-    pa.lds_offs[k] = tot;
-    tot += 3 * ps;
+    for (int d = 0; d < dim; ++d) ps *= std::max(h.n[d] >= 2 ? 2 * s - 1 : s - 1, 0);
+    tot += (k == 0 ? 2 : 3) * ps;
   }
   pa.lds_total = tot;
-  if (size_t(tot) * sizeof(double) > 160 * 1024) return LOR_EINVAL;
+  pa.fp32 = mixed ? 1 : 0;
+  if (size_t(tot) * (mixed ? sizeof(float) : sizeof(double)) > 160 * 1024) return LOR_EINVAL;
   return LOR_OK;
 }
 
@@ -480,20 +489,39 @@ int setup_impl(lor_handle &h, hipStream_t st) {
   return LOR_OK;
 }
 
+// Records an event pair around a launch when timing is on.
+struct Span {
+  lor_handle *h;
+  int which;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  Span(lor_handle *hh, int w, hipStream_t s) : h(hh), which(w), st(s) {
+    if (h->timing && (a = h->next_event())) (void)hipEventRecord(a, st);
+  }
+  ~Span() {
+    if (!a) return;
+    hipEvent_t b = h->next_event();
+    if (b && hipEventRecord(b, st) == hipSuccess) h->tspans[which].push_back({a, b});
+  }
+};
+
 int apply_P_impl(lor_handle *h, const double *r, double *z, const double *flag, hipStream_t st) {
   if (h->nc > 0) {
+    Span sp(h, LOR_T_COARSE, st);
     HIPCHK(launch_coarse_restrict(h->md, h->d_gllx, r, h->d_rc, st));
     HIPCHK(launch_gemv(h->nc, h->d_A0inv, h->d_rc, h->d_xc, flag, st));
     HIPCHK(launch_coarse_prolong(h->md, h->d_gllx, h->d_xc, z, flag, st));
   } else {
     HIPCHK(hipMemsetAsync(z, 0, h->ndofs * sizeof(double), st));
   }
+  Span sp(h, LOR_T_PATCH, st);
   HIPCHK(launch_patch_vcycle(h->pa, h->J, r, z, flag, st));
   return LOR_OK;
 }
 
 int apply_A_impl(lor_handle *h, const double *x, double *y, double *partials, const double *flag,
                  hipStream_t st) {
+  Span sp(h, LOR_T_APPLY_A, st);
   HIPCHK(launch_apply_cg(h->md, h->d_G, h->d_D, x, y, partials, flag, st));
   return LOR_OK;
 }
@@ -730,6 +758,31 @@ int lor_export_stencils(const lor_handle_t *h, int level, double *out, int64_t *
   *len = n;
   if (out && hipMemcpy(out, h->d_stencil[level], n * 8, hipMemcpyDeviceToHost) != hipSuccess)
     return LOR_EHIP;
+  return LOR_OK;
+}
+
+int lor_timing(lor_handle_t *h, int enable) {
+  if (!h) return LOR_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return LOR_EHIP;
+  if (enable) {  // a new record; disabling keeps the record for lor_timing_read
+    for (auto &v : h->tspans) v.clear();
+    h->ev_used = 0;
+  }
+  h->timing = enable != 0;
+  return LOR_OK;
+}
+
+int lor_timing_read(const lor_handle_t *h, int which, double *total_ms, int64_t *count) {
+  if (!h || which < 0 || which > 2 || !total_ms || !count) return LOR_EINVAL;
+  double tot = 0.0;
+  for (const auto &sp : h->tspans[which]) {
+    if (hipEventSynchronize(sp.second) != hipSuccess) return LOR_EHIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, sp.first, sp.second) != hipSuccess) return LOR_EHIP;
+    tot += ms;
+  }
+  *total_ms = tot;
+  *count = int64_t(h->tspans[which].size());
   return LOR_OK;
 }
 

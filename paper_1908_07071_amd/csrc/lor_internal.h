@@ -16,15 +16,15 @@ constexpr int kMaxLevels = 6;      // 1 + ceil(log2(16)) = 5, one spare
 constexpr int kMaxQ = kMaxP + 1;   // GLL points per direction
 
 // 1D transfer between two consecutive levels of one patch direction.
-// "fine" is level k, "coarse" level k+1; indices are into the zero-padded
-// patch boxes (local index + 1), so a coarse node on the patch boundary
-// reads the zero halo.
+// "fine" is level k, "coarse" level k+1; indices are patch-local along the
+// direction.  A prolongation source outside [0, mc) lies on the patch
+// boundary (zero) and is skipped.
 struct XferTab {
   int mf, mc;                 // unknowns per direction on the fine / coarse level
-  int pc[2 * kMaxP][2];       // prolongation: padded coarse indices of fine f
+  int pc[2 * kMaxP][2];       // prolongation: coarse indices of fine f
   double pw[2 * kMaxP][2];    //               and their weights
   int rcnt[2 * kMaxP];        // restriction: number of fine nodes of coarse c
-  int rf[2 * kMaxP][4];       //              padded fine indices
+  int rf[2 * kMaxP][4];       //              fine indices
   double rw[2 * kMaxP][4];    //              weights (same as pw, transposed)
 };
 
@@ -49,23 +49,46 @@ struct PatchArgs {
   int lng[kMaxLevels][3];            // level grid points per direction
   const XferTab *xfer;               // [nlev-1][3] by (fine level, direction type)
   const char *fac;                   // factor pool
-  const int64_t *fac_off;            // [J][nlev-1] byte offset of each block (-1: none)
-  const int *depth;                  // [J][nlev-1] sweep depth
-  int lds_offs[kMaxLevels];          // offsets (in doubles) of X_k in LDS; B_k, R_k follow
-  int lds_total;                     // doubles of LDS per patch
+  const int64_t *fac_off;            // [J][nlev-1][2] byte offsets of the forward and
+                                     // backward sweep blocks (-1: none)
+  int lds_total;                     // LDS values per patch (largest patch)
+  int fp32;                          // 1: stencils, factors and patch vectors in float
 };
 
-// One (patch, level) factor block: int32 idx[n], lvl[n+1], mask[n]; then,
-// 8-byte aligned, double val[27][n] (slot-major; center slot holds 1/D).
-__host__ __device__ inline int64_t factor_block_bytes(int64_t n, int nslots) {
-  int64_t ib = 4 * (3 * n + 1);
-  ib = (ib + 15) & ~int64_t(15);
-  return ib + 8 * int64_t(nslots) * n;
+// Sweep block: the data of one ILU(0) triangular sweep (forward or backward)
+// of one (patch, level), laid out for a 64-lane wavefront.
+//   header (kSweepHeader B): int32 nchunks, uint32 hdr0 (header of chunk 0),
+//   8 B pad, uint8 q0[64] (quads lane l loads from chunk 0), 16 zero bytes.
+//   chunks: a chunk is a run of consecutive dependency levels ("steps")
+//   holding at most 63 rows in total, so that every lane owns at most one
+//   row of the chunk.  It is stored as Q quads (16 B) per lane, interleaved
+//   by lane: quad q of lane l at byte 16 * (q * 64 + l) from the chunk start,
+//   so that one coalesced 1 KiB load brings every lane its own quad.
+//   Lane record (uint32 words): word 0 = row (bits 0-15) | step (16-21) |
+//   quads of this lane's record in the next chunk (22-26) | valid (bit 31)
+//   (lanes without a row only carry the next size); for the backward sweep
+//   then 1 / D as T; then the
+//   couplings in pairs: T v0, T v1, uint32 (int16 off0 | int16 off1 << 16),
+//   where off is the LDS offset of the neighbour from the row (padding pairs
+//   are zero).  Lane 63 carries the header of the next chunk instead:
+//   Q (bits 0-7) | nsteps (8-15) | W (16-23), W = couplings per record.
+constexpr int kChunkRows = 63;
+constexpr int kSweepHeader = 96;
+constexpr int kSweepZero = 80;   // 16 zero bytes inside the header
+constexpr int kMaxCouplings = 26;
+template <typename T>
+__host__ __device__ constexpr int sweep_head_words(bool fwd) {
+  return fwd ? 1 : 1 + int(sizeof(T)) / 4;
 }
-__host__ __device__ inline int64_t factor_vals_offset(int64_t n) {
-  int64_t ib = 4 * (3 * n + 1);
-  return (ib + 15) & ~int64_t(15);
+template <typename T>
+__host__ __device__ constexpr int sweep_pair_words() {
+  return 2 * int(sizeof(T)) / 4 + 1;
 }
+template <typename T>
+__host__ __device__ constexpr int sweep_quads(bool fwd, int w) {
+  return (sweep_head_words<T>(fwd) + ((w + 1) / 2) * sweep_pair_words<T>() + 3) / 4;
+}
+__host__ __device__ inline int64_t align16(int64_t b) { return (b + 15) & ~int64_t(15); }
 
 // ---------------------------------------------------------------- host side
 void gll_nodes_weights(int p, std::vector<double> &x, std::vector<double> &w);
@@ -84,6 +107,9 @@ struct MdfResult {
 // rows: n x nslots values (row-major), box shape m[0..dim-1].
 // Returns LOR_OK or LOR_EPIVOT.
 int mdf_factor(int dim, const int *m, std::vector<double> &rows, bool natural, MdfResult &out);
+// Sweep block of one direction (layout at kChunkRows).
+template <typename T>
+std::vector<char> pack_sweep(const MdfResult &res, int dim, const int *m, bool fwd);
 
 // ----------------------------------------------------- device launch wrappers
 // "flag" (nullable) points at the Krylov scalar array: kernels return at once
@@ -112,6 +138,7 @@ hipError_t launch_gauss_jordan(int n, double *A, double *rowbuf, double *colbuf,
 hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r, double *z,
                                const double *flag, hipStream_t st);
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t st);
+hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st);
 
 // Krylov helpers.  Scalars live in a small device array.
 enum Scal { S_RHO = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_TOL2, S_DONE, S_ITERS, S_FAIL,

@@ -29,8 +29,9 @@ EXPORTED = [
     "lor_default_options", "lor_error_string", "lor_setup", "lor_ndofs", "lor_device_bytes",
     "lor_dof_coords", "lor_assemble_rhs", "lor_apply_A", "lor_apply_P", "lor_pcg_solve",
     "lor_export_maps", "lor_export_stencils", "lor_gll", "lor_mdf_order", "lor_free",
-    "lor_last_error_detail",
+    "lor_last_error_detail", "lor_timing", "lor_timing_read",
 ]
+LOR_T_APPLY_A, LOR_T_PATCH, LOR_T_COARSE = 0, 1, 2
 
 
 class LorError(RuntimeError):
@@ -82,6 +83,8 @@ def _load():
         "lor_mdf_order": (C.c_int, [C.c_int, i32p, dp, C.c_int, i32p, i32p, i32p, dp, dp]),
         "lor_free": (C.c_int, [vp]),
         "lor_last_error_detail": (C.c_char_p, []),
+        "lor_timing": (C.c_int, [vp, C.c_int]),
+        "lor_timing_read": (C.c_int, [vp, C.c_int, dp, i64p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -235,3 +238,15 @@ def lor_free(h):
     if h is not None and h.value:
         _check(_lib.lor_free(h), "lor_free")
         h.value = None
+
+
+def lor_timing(h, enable: bool):
+    _check(_lib.lor_timing(h, int(bool(enable))), "lor_timing")
+
+
+def lor_timing_read(h, which: int):
+    """(total milliseconds, launches) of one kernel class since the last reset."""
+    t = C.c_double()
+    n = C.c_int64()
+    _check(_lib.lor_timing_read(h, int(which), C.byref(t), C.byref(n)), "lor_timing_read")
+    return t.value, n.value

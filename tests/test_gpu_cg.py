@@ -187,3 +187,36 @@ def test_errors(L, torch_dev):
         assert info.status == L.LOR_EINVAL
     finally:
         L.lor_free(h)
+
+
+@pytest.mark.parametrize("case", CASES[:5], ids=_ids)
+def test_mixed_precision_preconditioner_and_fcg(case, L, torch_dev):
+    """FP32 preconditioner (patch V-cycles in float): B r within float rounding
+    of the float64 oracle; flexible CG still reaches the float64 tolerance."""
+    torch = torch_dev
+    dim, n, p, V, mesh = _case(case)
+    print("case", case, flush=True)
+    opt = L.lor_default_options()
+    opt.precision = L.LOR_PREC_MIXED
+    h = L.lor_setup(dim, n, V, p, options=opt)
+    try:
+        N = L.lor_ndofs(h)
+        K = HO.cg_stiffness(mesh, p)
+        B = S.SchwarzLOR(mesh, p)
+        rin = inputs.gaussian_rhs(N, 31)
+        r = torch.tensor(rin, device="cuda")
+        z = torch.empty_like(r)
+        L.lor_apply_P(h, r, z)
+        torch.cuda.synchronize()
+        zref = B.apply(rin)
+        err = np.linalg.norm(z.cpu().numpy() - zref) / np.linalg.norm(zref)
+        assert err <= 2e-5, err
+        x = torch.zeros_like(r)
+        info = L.lor_pcg_solve(h, r, x, rtol=1e-10, maxit=500)
+        _, it, _ = krylov.pcg(K, rin, B.apply, tol=1e-10, flexible=True)
+        # the float preconditioner may cost a few iterations at this tolerance
+        assert it - 1 <= info.iters <= 1.15 * it + 2, (info.iters, it)
+        xs = x.cpu().numpy()
+        assert np.linalg.norm(rin - K @ xs) <= 1.05e-10 * np.linalg.norm(rin)
+    finally:
+        L.lor_free(h)
