@@ -112,7 +112,19 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed",
                     help="mixed: FP32 patch V-cycles inside FP64 flexible CG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.calib_copy:
+        import torch
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": a.numel() * 8, "calib_copy_bytes_written": b.numel() * 8}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver is "
               "single-device, see DESIGN.md for how it would shard", file=sys.stderr)
@@ -136,6 +148,7 @@ def main():
     setup_s = time.perf_counter() - t0
     print(f"[bench] setup done in {setup_s:.1f}s", file=sys.stderr, flush=True)
     N = L.lor_ndofs(h)
+    dev_bytes = L.lor_device_bytes(h)
     coords = L.lor_dof_coords(h, dim)
     f = torch.tensor(inputs.manufactured_f(coords), device=dev)
     b = torch.empty_like(f)
@@ -178,10 +191,31 @@ def main():
     }
     dom = "patch_vcycle" if tP >= tA else "apply_A"
     avg_ms, abytes = kernels[dom]
+    if dom == "patch_vcycle" and args.precision == "mixed":
+        abytes = patch_algorithmic_bytes(dim, n, p, prec_bytes=4)
     achieved = abytes / (avg_ms * 1e-3) / 1e9
+    L.lor_free(h)
+
+    # the same solve with the float64 preconditioner, for the mixed-vs-FP64 comparison
+    fp64 = None
+    if args.precision == "mixed":
+        h64 = L.lor_setup(dim, n, V, p)
+        x.zero_()
+        info64 = L.lor_pcg_solve(h64, b, x, rtol=args.rtol, maxit=1000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            info64 = L.lor_pcg_solve(h64, b, x, rtol=args.rtol, maxit=1000)
+        torch.cuda.synchronize()
+        ms64 = 1e3 * (time.perf_counter() - t0) / args.steps
+        L.lor_free(h64)
+        fp64 = {"value": N / (ms64 * 1e-3), "ms_per_step": ms64, "iters": info64.iters,
+                "rel_res_true": info64.rel_res_true}
+        print(f"[bench] fp64 preconditioner: {ms64:.2f} ms/solve, iters={info64.iters}",
+              file=sys.stderr, flush=True)
 
     out = {
-        "metric": "PCG DOFs/s to 1e-8 rel. residual (FP64); operator GDOF/s",
+        "metric": "PCG DOFs/s to 1e-8 rel. residual (mixed/learned vs FP64); operator GDOF/s",
         "value": N / (ms_step * 1e-3),
         "unit": "DOF/s",
         "n_gpus": 1,
@@ -191,15 +225,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+f32" if args.precision == "mixed" else "f64",
         "data": "synthetic",
         "config": {
             "workload": (f"{dim}D CG Poisson, {n}^{dim} hexes with interior vertices perturbed <=10% h "
-                         f"(seed 1), p={p}, f from u=prod sin(pi x_i); FP64 PCG + LOR vertex-patch "
-                         f"Schwarz (MDF-ILU(0) V-cycles, exact coarse) to {args.rtol:g}"),
+                         f"(seed 1), p={p}, f from u=prod sin(pi x_i); "
+                         + ("FP64 flexible CG with FP32 " if args.precision == "mixed" else "FP64 PCG with FP64 ")
+                         + f"LOR vertex-patch Schwarz (MDF-ILU(0) V-cycles, exact coarse) to {args.rtol:g}"),
             "N": N, "iters": info.iters, "rel_res_true": info.rel_res_true,
-            "precision": "fp64", "setup_s": round(setup_s, 3),
+            "precision": args.precision, "setup_s": round(setup_s, 3),
+            "device_bytes": dev_bytes,
         },
+        "fp64_preconditioner": fp64,
         "operator_gdofs": N / t_apply / 1e9,
         "operator_ms": t_apply * 1e3,
         "kernel_ms_per_solve": {
@@ -214,7 +251,6 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(dim, p, info.iters)
-    L.lor_free(h)
     print(json.dumps(out))
 
 
