@@ -102,9 +102,14 @@ const char *lor_last_error_detail(void);
 
 /* Set up the discretization and the preconditioner (Sections 2 and 3).
  * p: polynomial degree, 1 <= p <= 14.  method: lor_method_t.
- * penalty: eta, ignored for CG; IP uses sigma = eta p^2 / h_e on each face
- *   (eq. ip, h_e = min |K|/|e| over the elements at the face); BR2 uses eta
- *   as the factor of the lifting term (eq. br2).
+ * penalty: eta > 0, ignored for CG; IP uses sigma = eta p^2 / h_e on each
+ *   face (eq. ip, h_e = min |K|/|e| over the elements at the face, volumes
+ *   and areas by GLL quadrature); BR2 uses eta as the factor of the lifting
+ *   term (eq. br2), which with the collocated GLL element mass is a
+ *   node-wise penalty sigma_q = eta c^2 sum_K omega_q / (w|J|)_q^K on the
+ *   face nodes (c = 1/2 inside, 1 on the boundary).  DG boundary conditions
+ *   are imposed weakly through the boundary faces (Dirichlet) or not at all
+ *   (Neumann: no boundary faces).
  * opt: NULL for defaults.  stream: used for the device part of the set-up.
  * Allocates the device data the handle needs (geometric factors, LOR
  * stencils, patch factors, coarse inverse) and builds everything.
@@ -133,8 +138,11 @@ int lor_assemble_rhs(lor_handle_t *h, const double *f_dev, double *b_dev, void *
  * for DG).  x_dev, y_dev: DEVICE, ndofs float64, must not alias. */
 int lor_apply_A(lor_handle_t *h, const double *x_dev, double *y_dev, void *stream);
 
-/* z = B r: additive Schwarz preconditioner of eq. as (eq. dg-as for DG).
- * r_dev, z_dev: DEVICE, ndofs float64, must not alias. */
+/* z = B r: additive Schwarz preconditioner of eq. as.  DG (eq. dg-as):
+ * z = D_B^-1 r on the element-boundary nodes (point Jacobi of A_DG on V_B)
+ * plus E B E^T r with E the injection of the conforming space.
+ * r_dev, z_dev: DEVICE, ndofs float64, must not alias.  LOR_ESTATE for a
+ * Neumann handle (no preconditioner). */
 int lor_apply_P(lor_handle_t *h, const double *r_dev, double *z_dev, void *stream);
 
 /* Solve A x = b by preconditioned (or flexible) CG from x = 0 until
@@ -155,12 +163,18 @@ int lor_pcg_solve(lor_handle_t *h, const double *b_dev, double *x_dev,
  *                         J*(L-1)+1 entries
  *   LOR_MAP_SCHEDULE      dependency-level starts of each (patch, level)
  *                         sweep, concatenated (depth+1 entries each)
- *   LOR_MAP_SCHEDULE_OFFSET start of each (patch, level) in LOR_MAP_SCHEDULE */
+ *   LOR_MAP_SCHEDULE_OFFSET start of each (patch, level) in LOR_MAP_SCHEDULE
+ *   LOR_MAP_E2L           DG only: E-vector node -> conforming L-vector index
+ *                         of the same GLL grid node, -1 on the Dirichlet
+ *                         boundary (the injection E of eq. dg-as)
+ * LOR_MAP_LDOF and the Schwarz maps refer to the conforming L-vector for DG
+ * too (the space the DG preconditioner's Schwarz part works in). */
 #define LOR_MAP_LDOF             0
 #define LOR_MAP_ORDER            1
 #define LOR_MAP_ORDER_OFFSET     2
 #define LOR_MAP_SCHEDULE         3
 #define LOR_MAP_SCHEDULE_OFFSET  4
+#define LOR_MAP_E2L              5
 int lor_export_maps(const lor_handle_t *h, int which, int32_t *host_out, int64_t *len);
 
 /* Assembled LOR stencils of level k of the global element-structured

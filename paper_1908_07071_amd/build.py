@@ -28,6 +28,7 @@ SOURCES = [
     ("k_operator.hip", []),
     ("k_schwarz.hip", []),
     ("k_krylov.hip", []),
+    ("k_dg.hip", []),
 ]
 
 ARCH = "gfx950"

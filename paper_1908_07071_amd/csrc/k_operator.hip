@@ -27,13 +27,47 @@ __device__ inline int xcd_tile(int bid, int nb) {
   return x < rem ? x * (per + 1) + c : rem * (per + 1) + (x - rem) * per + c;
 }
 
-template <int Q>
+// Face records of the DG face kernel: per (face, side) 4 x QF values
+// (V, C a_0, C a_1, C a_2), SoA.  Faces of direction s are a structured grid
+// n + e_s after those of the lower directions; the element is side 1 of the
+// face at its xi_s = 0 end and side 0 at its xi_s = 1 end.
+struct FaceRef {
+  int64_t f0, f1;  // faces at xi_s = 0 and xi_s = p
+};
+
+__device__ inline void elem_faces(const MeshDims &md, int ex, int ey, int ez, FaceRef fr[3]) {
+  const int64_t n0 = md.n[0], n1 = md.n[1], n2 = md.n[2];
+  const int64_t off1 = (n0 + 1) * n1 * n2, off2 = off1 + n0 * (n1 + 1) * n2;
+  fr[0].f0 = ex + (n0 + 1) * (ey + n1 * int64_t(ez));
+  fr[0].f1 = fr[0].f0 + 1;
+  fr[1].f0 = off1 + ex + n0 * (ey + (n1 + 1) * int64_t(ez));
+  fr[1].f1 = fr[1].f0 + n0;
+  fr[2].f0 = off2 + ex + n0 * (ey + n1 * int64_t(ez));
+  fr[2].f1 = fr[2].f0 + n0 * n1;
+}
+
+template <int QF>
+__device__ inline void add_face(const double *__restrict__ fo, int64_t face, int side, int q,
+                                double &v, double &g0, double &g1, double &g2) {
+  const double *r = fo + (face * 2 + side) * 4 * QF;
+  v += r[q];
+  g0 += r[QF + q];
+  g1 += r[2 * QF + q];
+  g2 += r[3 * QF + q];
+}
+
+// DG == true: the same volume term on the E-vector (element-owned rows, plain
+// stores) plus the face records of the IP / BR2 face kernel: flux terms added
+// to the reference flux at face nodes before the transposed contractions,
+// value terms added to the result.
+template <int Q, bool DG>
 __global__ __launch_bounds__(256) void k_apply_cg3(MeshDims md, const double *__restrict__ G,
                                                    const double *__restrict__ Dg,
                                                    const double *__restrict__ x,
                                                    double *__restrict__ y,
                                                    double *__restrict__ partials,
-                                                   const double *flag) {
+                                                   const double *flag,
+                                                   const double *__restrict__ fo) {
   if (flag && flag[S_DONE] != 0.0) return;
   constexpr int Q2 = Q * Q, Q3 = Q2 * Q, EPB = 256 / Q2;
   __shared__ double sD[Q2];
@@ -61,12 +95,20 @@ __global__ __launch_bounds__(256) void k_apply_cg3(MeshDims md, const double *__
   int64_t base = (int64_t(gx - ox) + int64_t(md.nu[0]) * (gy - ox));
   const int64_t sz = int64_t(md.nu[0]) * md.nu[1];
   double u[Q];
+  const int64_t ebase = (active ? e : 0) * Q3 + a + Q * b;
 #pragma unroll
   for (int c = 0; c < Q; ++c) {
-    const int gz = ez * p + c;
-    const bool in = active && inxy && (!dir || (gz > 0 && gz < md.ng[2] - 1));
-    u[c] = in ? x[base + sz * (gz - ox)] : 0.0;
+    if (DG) {
+      u[c] = active ? x[ebase + Q2 * c] : 0.0;
+    } else {
+      const int gz = ez * p + c;
+      const bool in = active && inxy && (!dir || (gz > 0 && gz < md.ng[2] - 1));
+      u[c] = in ? x[base + sz * (gz - ox)] : 0.0;
+    }
   }
+  FaceRef fr[3];
+  if (DG) elem_faces(md, ex, ey, ez, fr);
+  double vt[DG ? Q : 1];
   __syncthreads();
   double uz[Q];
 #pragma unroll
@@ -104,6 +146,21 @@ __global__ __launch_bounds__(256) void k_apply_cg3(MeshDims md, const double *__
     fx[c] = g00 * ux + g01 * uy + g02 * uz[c];
     fy[c] = g01 * ux + g11 * uy + g12 * uz[c];
     fz[c] = g02 * ux + g12 * uy + g22 * uz[c];
+    if (DG) {
+      double v = 0.0, h0 = 0.0, h1 = 0.0, h2 = 0.0;
+      if (active) {
+        if (a == 0) add_face<Q2>(fo, fr[0].f0, 1, b + Q * c, v, h0, h1, h2);
+        if (a == p) add_face<Q2>(fo, fr[0].f1, 0, b + Q * c, v, h0, h1, h2);
+        if (b == 0) add_face<Q2>(fo, fr[1].f0, 1, a + Q * c, v, h0, h1, h2);
+        if (b == p) add_face<Q2>(fo, fr[1].f1, 0, a + Q * c, v, h0, h1, h2);
+        if (c == 0) add_face<Q2>(fo, fr[2].f0, 1, a + Q * b, v, h0, h1, h2);
+        if (c == p) add_face<Q2>(fo, fr[2].f1, 0, a + Q * b, v, h0, h1, h2);
+      }
+      fx[c] += h0;
+      fy[c] += h1;
+      fz[c] += h2;
+      vt[DG ? c : 0] = v;
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -125,6 +182,12 @@ __global__ __launch_bounds__(256) void k_apply_cg3(MeshDims md, const double *__
         acc += sD[k * Q + b] * s1[le][a + Q * (k + Q * c)];
         acc += sD[k * Q + c] * fz[k];
       }
+    }
+    if (DG) {
+      acc += vt[DG ? c : 0];
+      dotp += u[c] * acc;
+      if (active) y[ebase + Q2 * c] = acc;
+      continue;
     }
     dotp += u[c] * acc;
     const int gz = ez * p + c;
@@ -150,13 +213,14 @@ __global__ __launch_bounds__(256) void k_apply_cg3(MeshDims md, const double *__
 }
 
 // 2D: one thread per element node, Q^2 threads per element.
-template <int Q>
+template <int Q, bool DG>
 __global__ __launch_bounds__(256) void k_apply_cg2(MeshDims md, const double *__restrict__ G,
                                                    const double *__restrict__ Dg,
                                                    const double *__restrict__ x,
                                                    double *__restrict__ y,
                                                    double *__restrict__ partials,
-                                                   const double *flag) {
+                                                   const double *flag,
+                                                   const double *__restrict__ fo) {
   if (flag && flag[S_DONE] != 0.0) return;
   constexpr int Q2 = Q * Q, EPB = 256 / Q2;
   __shared__ double sD[Q2];
@@ -175,7 +239,8 @@ __global__ __launch_bounds__(256) void k_apply_cg2(MeshDims md, const double *__
   const int ox = dir ? 1 : 0;
   bool in = active;
   if (dir) in = in && gx > 0 && gx < md.ng[0] - 1 && gy > 0 && gy < md.ng[1] - 1;
-  const int64_t li = int64_t(gx - ox) + int64_t(md.nu[0]) * (gy - ox);
+  const int64_t li = DG ? (active ? e : 0) * Q2 + t : int64_t(gx - ox) + int64_t(md.nu[0]) * (gy - ox);
+  if (DG) in = active;
   const double u = in ? x[li] : 0.0;
   if (le < EPB) su[le][t] = u;
   __syncthreads();
@@ -193,9 +258,19 @@ __global__ __launch_bounds__(256) void k_apply_cg2(MeshDims md, const double *__
     g11 = Ge[2 * Q2 + t];
   }
   __syncthreads();
+  double v = 0.0, h0 = 0.0, h1 = 0.0;
+  if (DG && active) {
+    const int64_t n0 = md.n[0], n1 = md.n[1], off1 = (n0 + 1) * n1;
+    const int64_t fx0 = ex + (n0 + 1) * ey, fy0 = off1 + ex + n0 * ey;
+    double h2 = 0.0;
+    if (a == 0) add_face<Q>(fo, fx0, 1, b, v, h0, h1, h2);
+    if (a == p) add_face<Q>(fo, fx0 + 1, 0, b, v, h0, h1, h2);
+    if (b == 0) add_face<Q>(fo, fy0, 1, a, v, h0, h1, h2);
+    if (b == p) add_face<Q>(fo, fy0 + n0, 0, a, v, h0, h1, h2);
+  }
   if (le < EPB) {
-    sa[le][t] = g00 * ua + g01 * ub;
-    sb[le][t] = g01 * ua + g11 * ub;
+    sa[le][t] = g00 * ua + g01 * ub + h0;
+    sb[le][t] = g01 * ua + g11 * ub + h1;
   }
   __syncthreads();
   double acc = 0;
@@ -204,7 +279,10 @@ __global__ __launch_bounds__(256) void k_apply_cg2(MeshDims md, const double *__
       acc += sD[k * Q + a] * sa[le][k + Q * b];
       acc += sD[k * Q + b] * sb[le][a + Q * k];
     }
-  if (in) {
+  if (DG) {
+    acc += v;
+    if (in) y[li] = acc;
+  } else if (in) {
     const bool interior = a > 0 && a < p && b > 0 && b < p;
     if (interior)
       y[li] = acc;
@@ -267,17 +345,22 @@ inline int grid_for(int64_t n, int bs) {
 
 template <int Q>
 hipError_t apply_q(const MeshDims &md, const double *G, const double *D, const double *x,
-                   double *y, double *partials, const double *flag, hipStream_t st) {
+                   double *y, double *partials, const double *flag, const double *fo,
+                   hipStream_t st) {
   constexpr int Q2 = Q * Q;
   constexpr int EPB = 256 / Q2;
+  const int64_t nel = int64_t(md.n[0]) * md.n[1] * (md.dim == 3 ? md.n[2] : 1);
+  const int nb = int((nel + EPB - 1) / EPB);
   if (md.dim == 3) {
-    const int64_t nel = int64_t(md.n[0]) * md.n[1] * md.n[2];
-    const int nb = int((nel + EPB - 1) / EPB);
-    k_apply_cg3<Q><<<nb, 256, 0, st>>>(md, G, D, x, y, partials, flag);
+    if (fo)
+      k_apply_cg3<Q, true><<<nb, 256, 0, st>>>(md, G, D, x, y, partials, flag, fo);
+    else
+      k_apply_cg3<Q, false><<<nb, 256, 0, st>>>(md, G, D, x, y, partials, flag, nullptr);
   } else {
-    const int64_t nel = int64_t(md.n[0]) * md.n[1];
-    const int nb = int((nel + EPB - 1) / EPB);
-    k_apply_cg2<Q><<<nb, 256, 0, st>>>(md, G, D, x, y, partials, flag);
+    if (fo)
+      k_apply_cg2<Q, true><<<nb, 256, 0, st>>>(md, G, D, x, y, partials, flag, fo);
+    else
+      k_apply_cg2<Q, false><<<nb, 256, 0, st>>>(md, G, D, x, y, partials, flag, nullptr);
   }
   return hipGetLastError();
 }
@@ -292,23 +375,24 @@ int apply_cg_blocks(const MeshDims &md) {
 }
 
 hipError_t launch_apply_cg(const MeshDims &md, const double *G, const double *D, const double *x,
-                           double *y, double *partials, const double *flag, hipStream_t st) {
+                           double *y, double *partials, const double *flag, hipStream_t st,
+                           const double *fo) {
   switch (md.p + 1) {
-    case 2: return apply_q<2>(md, G, D, x, y, partials, flag, st);
-    case 3: return apply_q<3>(md, G, D, x, y, partials, flag, st);
-    case 4: return apply_q<4>(md, G, D, x, y, partials, flag, st);
-    case 5: return apply_q<5>(md, G, D, x, y, partials, flag, st);
-    case 6: return apply_q<6>(md, G, D, x, y, partials, flag, st);
-    case 7: return apply_q<7>(md, G, D, x, y, partials, flag, st);
-    case 8: return apply_q<8>(md, G, D, x, y, partials, flag, st);
-    case 9: return apply_q<9>(md, G, D, x, y, partials, flag, st);
-    case 10: return apply_q<10>(md, G, D, x, y, partials, flag, st);
-    case 11: return apply_q<11>(md, G, D, x, y, partials, flag, st);
-    case 12: return apply_q<12>(md, G, D, x, y, partials, flag, st);
-    case 13: return apply_q<13>(md, G, D, x, y, partials, flag, st);
-    case 14: return apply_q<14>(md, G, D, x, y, partials, flag, st);
-    case 15: return apply_q<15>(md, G, D, x, y, partials, flag, st);
-    case 16: return apply_q<16>(md, G, D, x, y, partials, flag, st);
+    case 2: return apply_q<2>(md, G, D, x, y, partials, flag, fo, st);
+    case 3: return apply_q<3>(md, G, D, x, y, partials, flag, fo, st);
+    case 4: return apply_q<4>(md, G, D, x, y, partials, flag, fo, st);
+    case 5: return apply_q<5>(md, G, D, x, y, partials, flag, fo, st);
+    case 6: return apply_q<6>(md, G, D, x, y, partials, flag, fo, st);
+    case 7: return apply_q<7>(md, G, D, x, y, partials, flag, fo, st);
+    case 8: return apply_q<8>(md, G, D, x, y, partials, flag, fo, st);
+    case 9: return apply_q<9>(md, G, D, x, y, partials, flag, fo, st);
+    case 10: return apply_q<10>(md, G, D, x, y, partials, flag, fo, st);
+    case 11: return apply_q<11>(md, G, D, x, y, partials, flag, fo, st);
+    case 12: return apply_q<12>(md, G, D, x, y, partials, flag, fo, st);
+    case 13: return apply_q<13>(md, G, D, x, y, partials, flag, fo, st);
+    case 14: return apply_q<14>(md, G, D, x, y, partials, flag, fo, st);
+    case 15: return apply_q<15>(md, G, D, x, y, partials, flag, fo, st);
+    case 16: return apply_q<16>(md, G, D, x, y, partials, flag, fo, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -66,6 +66,29 @@ __global__ void k_node_coords(MeshDims md, const double *__restrict__ verts,
   }
 }
 
+// E-vector node coordinates: every element maps its own GLL nodes (same
+// operation order as the grid coordinates above).  Layout [node][dim].
+template <int DIM>
+__global__ void k_dg_coords(MeshDims md, const double *__restrict__ verts,
+                            const double *__restrict__ gllx, double *__restrict__ coords) {
+  const int Q = md.p + 1;
+  const int nq = DIM == 3 ? Q * Q * Q : Q * Q;
+  const int64_t nel = int64_t(md.n[0]) * md.n[1] * md.n[2];
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < nel * nq;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t e = t / nq;
+    const int q = int(t % nq);
+    const int ec[3] = {int(e % md.n[0]), int((e / md.n[0]) % md.n[1]),
+                       int(e / (int64_t(md.n[0]) * md.n[1]))};
+    const int l[3] = {q % Q, (q / Q) % Q, q / (Q * Q)};
+    double xi[3];
+    for (int i = 0; i < DIM; ++i) xi[i] = gllx[l[i]];
+    double X[3];
+    q1_map<DIM>(verts, md, ec, xi, X);
+    for (int r = 0; r < DIM; ++r) coords[t * DIM + r] = X[r];
+  }
+}
+
 // Geometric factors G = w |J| J^-1 J^-T (symmetric, d(d+1)/2 values per GLL
 // node, element-major SoA [e][comp][node]) and w |J| for the collocated mass.
 template <int DIM>
@@ -420,6 +443,17 @@ hipError_t launch_geom_cg(const MeshDims &md, const double *verts, const double 
     k_geom<3><<<grid_for(tot, 256), 256, 0, st>>>(md, verts, gllx, gllw, G, wdet, bad);
   else
     k_geom<2><<<grid_for(tot, 256), 256, 0, st>>>(md, verts, gllx, gllw, G, wdet, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_dg_coords(const MeshDims &md, const double *verts, const double *gllx,
+                            double *coords, hipStream_t st) {
+  const int Q = md.p + 1;
+  const int64_t n = int64_t(md.n[0]) * md.n[1] * md.n[2] * (md.dim == 3 ? Q * Q * Q : Q * Q);
+  if (md.dim == 3)
+    k_dg_coords<3><<<grid_for(n, 256), 256, 0, st>>>(md, verts, gllx, coords);
+  else
+    k_dg_coords<2><<<grid_for(n, 256), 256, 0, st>>>(md, verts, gllx, coords);
   return hipGetLastError();
 }
 

@@ -25,6 +25,8 @@ struct lor_handle {
   std::vector<std::vector<int>> kept;
   int L = 1;
   int64_t ndofs = 0, nfine = 0, nel = 0;
+  int64_t ncg = 0;     // conforming unknowns (the L-vector of the Schwarz preconditioner)
+  int64_t nfaces = 0;  // DG faces
   int J = 0, nc = 0;
   // device memory (owned)
   std::vector<void *> allocs;
@@ -38,6 +40,7 @@ struct lor_handle {
   int64_t fac_bytes = 0;
   XferTab *d_xfer = nullptr;
   double *d_A0inv = nullptr, *d_rc = nullptr, *d_xc = nullptr;
+  double *d_fg = nullptr, *d_fo = nullptr, *d_dinv = nullptr, *d_rL = nullptr, *d_zL = nullptr;
   double *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr, *d_rold = nullptr;
   double *d_tmp = nullptr, *d_scal = nullptr, *d_part = nullptr, *d_part2 = nullptr;
   int npart = 0;
@@ -425,10 +428,9 @@ int setup_impl(lor_handle &h, hipStream_t st) {
   h.nel = int64_t(md.n[0]) * md.n[1] * md.n[2];
   const int Q = p + 1;
   const int nq = dim == 3 ? Q * Q * Q : Q * Q;
-  if (h.method == LOR_CG)
-    h.ndofs = int64_t(md.nu[0]) * md.nu[1] * md.nu[2];
-  else
-    return LOR_EINVAL;  // DG set-up is not built yet
+  const bool dg = h.method != LOR_CG;
+  h.ncg = int64_t(md.nu[0]) * md.nu[1] * md.nu[2];
+  h.ndofs = dg ? h.nel * nq : h.ncg;
   HIPCHK(h.alloc(&h.d_verts, h.verts.size()));
   HIPCHK(h.alloc(&h.d_gllx, Q));
   HIPCHK(h.alloc(&h.d_gllw, Q));
@@ -450,6 +452,19 @@ int setup_impl(lor_handle &h, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (hb) return LOR_EJACOBIAN;
+  if (dg) {
+    // faces: geometry and penalty (eq. ip / eq. br2), face records, diag(A_DG)
+    const int QF = dim == 3 ? Q * Q : Q;
+    h.nfaces = dg_face_count(md);
+    HIPCHK(h.alloc(&h.d_fg, size_t(h.nfaces) * 8 * QF));
+    HIPCHK(h.alloc(&h.d_fo, size_t(h.nfaces) * 8 * QF));
+    HIPCHK(h.alloc(&h.d_dinv, size_t(h.ndofs)));
+    HIPCHK(launch_dg_face_geom(md, h.d_verts, h.d_gllx, h.d_gllw, h.d_wdet, h.method, h.penalty,
+                               h.d_fg, st));
+    HIPCHK(launch_dg_diag(md, h.d_G, h.d_D, h.d_fg, h.d_dinv, st));
+    HIPCHK(h.alloc(&h.d_rL, size_t(h.ncg)));
+    HIPCHK(h.alloc(&h.d_zL, size_t(h.ncg)));
+  }
   // Krylov work vectors
   const int64_t N = h.ndofs;
   HIPCHK(h.alloc(&h.d_r, N));
@@ -505,24 +520,38 @@ struct Span {
   }
 };
 
-int apply_P_impl(lor_handle *h, const double *r, double *z, const double *flag, hipStream_t st) {
+// Conforming Schwarz preconditioner on L-vectors (eq. as).
+int apply_P_cg(lor_handle *h, const double *r, double *z, const double *flag, hipStream_t st) {
   if (h->nc > 0) {
     Span sp(h, LOR_T_COARSE, st);
     HIPCHK(launch_coarse_restrict(h->md, h->d_gllx, r, h->d_rc, st));
     HIPCHK(launch_gemv(h->nc, h->d_A0inv, h->d_rc, h->d_xc, flag, st));
     HIPCHK(launch_coarse_prolong(h->md, h->d_gllx, h->d_xc, z, flag, st));
   } else {
-    HIPCHK(hipMemsetAsync(z, 0, h->ndofs * sizeof(double), st));
+    HIPCHK(launch_fill(z, h->ncg, 0.0, st));
   }
   Span sp(h, LOR_T_PATCH, st);
   HIPCHK(launch_patch_vcycle(h->pa, h->J, r, z, flag, st));
   return LOR_OK;
 }
 
+// CG: eq. as.  DG: eq. dg-as, z = D_B^-1 r on element-boundary nodes plus
+// E B E^T r.
+int apply_P_impl(lor_handle *h, const double *r, double *z, const double *flag, hipStream_t st) {
+  if (h->method == LOR_CG) return apply_P_cg(h, r, z, flag, st);
+  HIPCHK(launch_dg_restrict(h->md, r, h->d_rL, flag, st));
+  int rc = apply_P_cg(h, h->d_rL, h->d_zL, flag, st);
+  if (rc != LOR_OK) return rc;
+  HIPCHK(launch_dg_prolong_jacobi(h->md, r, h->d_dinv, h->d_zL, z, flag, st));
+  return LOR_OK;
+}
+
 int apply_A_impl(lor_handle *h, const double *x, double *y, double *partials, const double *flag,
                  hipStream_t st) {
   Span sp(h, LOR_T_APPLY_A, st);
-  HIPCHK(launch_apply_cg(h->md, h->d_G, h->d_D, x, y, partials, flag, st));
+  if (h->method != LOR_CG) HIPCHK(launch_dg_face(h->md, h->d_D, h->d_fg, x, h->d_fo, flag, st));
+  HIPCHK(launch_apply_cg(h->md, h->d_G, h->d_D, x, y, partials, flag, st,
+                         h->method != LOR_CG ? h->d_fo : nullptr));
   return LOR_OK;
 }
 
@@ -612,6 +641,15 @@ int lor_device_bytes(const lor_handle_t *h, size_t *bytes) {
 int lor_dof_coords(const lor_handle_t *h, double *host_xyz) {
   if (!h || !host_xyz) return LOR_EINVAL;
   const int dim = h->dim;
+  if (h->method != LOR_CG) {
+    double *tmp = nullptr;
+    const size_t nb = size_t(h->ndofs) * dim * sizeof(double);
+    if (hipMalloc(&tmp, nb) != hipSuccess) return LOR_EHIP;
+    hipError_t e = launch_dg_coords(h->md, h->d_verts, h->d_gllx, tmp, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(host_xyz, tmp, nb, hipMemcpyDeviceToHost);
+    (void)hipFree(tmp);
+    return e == hipSuccess ? LOR_OK : LOR_EHIP;
+  }
   std::vector<double> all(size_t(h->nfine) * dim);
   if (hipMemcpy(all.data(), h->d_coords, all.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
     return LOR_EHIP;
@@ -628,6 +666,10 @@ int lor_dof_coords(const lor_handle_t *h, double *host_xyz) {
 
 int lor_assemble_rhs(lor_handle_t *h, const double *f_dev, double *b_dev, void *stream) {
   if (!h || !f_dev || !b_dev) return LOR_EINVAL;
+  if (h->method != LOR_CG) {
+    HIPCHK(launch_dg_rhs(h->d_wdet, f_dev, b_dev, h->ndofs, static_cast<hipStream_t>(stream)));
+    return LOR_OK;
+  }
   HIPCHK(launch_rhs_cg(h->md, h->d_wdet, f_dev, b_dev, static_cast<hipStream_t>(stream)));
   return LOR_OK;
 }
@@ -635,7 +677,7 @@ int lor_assemble_rhs(lor_handle_t *h, const double *f_dev, double *b_dev, void *
 int lor_apply_A(lor_handle_t *h, const double *x_dev, double *y_dev, void *stream) {
   if (!h || !x_dev || !y_dev || x_dev == y_dev) return LOR_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  HIPCHK(hipMemsetAsync(y_dev, 0, h->ndofs * sizeof(double), st));
+  if (h->method == LOR_CG) HIPCHK(hipMemsetAsync(y_dev, 0, h->ndofs * sizeof(double), st));
   return apply_A_impl(h, x_dev, y_dev, nullptr, nullptr, st);
 }
 
@@ -731,11 +773,35 @@ int lor_export_maps(const lor_handle_t *h, int which, int32_t *out, int64_t *len
     case LOR_MAP_LDOF: {
       const MeshDims &md = h->md;
       const int ox = md.dirichlet ? 1 : 0;
-      tmp.resize(h->ndofs);
-      for (int64_t i = 0; i < h->ndofs; ++i) {
+      tmp.resize(h->ncg);
+      for (int64_t i = 0; i < h->ncg; ++i) {
         const int64_t gx = i % md.nu[0] + ox, gy = (i / md.nu[0]) % md.nu[1] + ox,
                       gz = h->dim == 3 ? i / (int64_t(md.nu[0]) * md.nu[1]) + ox : 0;
         tmp[i] = int32_t(gx + int64_t(md.ng[0]) * (gy + int64_t(md.ng[1]) * gz));
+      }
+      src = &tmp;
+      break;
+    }
+    case LOR_MAP_E2L: {
+      if (h->method == LOR_CG) return LOR_EINVAL;
+      const MeshDims &md = h->md;
+      const int Q = md.p + 1, ox = md.dirichlet ? 1 : 0;
+      const int nq = h->dim == 3 ? Q * Q * Q : Q * Q;
+      tmp.resize(h->ndofs);
+      for (int64_t t = 0; t < h->ndofs; ++t) {
+        const int64_t e = t / nq;
+        const int m = int(t % nq);
+        const int l[3] = {m % Q, (m / Q) % Q, m / (Q * Q)};
+        const int64_t ec[3] = {e % md.n[0], (e / md.n[0]) % md.n[1], e / (int64_t(md.n[0]) * md.n[1])};
+        int64_t li = 0, stride = 1;
+        bool in = true;
+        for (int d = 0; d < h->dim; ++d) {
+          const int64_t g = ec[d] * md.p + l[d];
+          if (md.dirichlet && (g == 0 || g == md.ng[d] - 1)) in = false;
+          li += (g - ox) * stride;
+          stride *= md.nu[d];
+        }
+        tmp[t] = in ? int32_t(li) : -1;
       }
       src = &tmp;
       break;

@@ -124,9 +124,30 @@ hipError_t launch_lor_stencil(const MeshDims &md, int s, const int *kept_fine_id
 hipError_t launch_rhs_cg(const MeshDims &md, const double *wdet, const double *f, double *b,
                          hipStream_t st);
 int apply_cg_blocks(const MeshDims &md);
+// fo == nullptr: CG operator on the L-vector; otherwise the DG volume term on
+// the E-vector plus the face records fo written by launch_dg_face.
 hipError_t launch_apply_cg(const MeshDims &md, const double *G, const double *D,
                            const double *x, double *y, double *partials, const double *flag,
-                           hipStream_t st);
+                           hipStream_t st, const double *fo = nullptr);
+
+// DG (faces, penalties, diagonal, E-vector transfers)
+int64_t dg_face_count(const MeshDims &md);
+hipError_t launch_dg_coords(const MeshDims &md, const double *verts, const double *gllx,
+                            double *coords, hipStream_t st);
+hipError_t launch_dg_face_geom(const MeshDims &md, const double *verts, const double *gllx,
+                               const double *gllw, const double *wdet, int method, double eta,
+                               double *fg, hipStream_t st);
+hipError_t launch_dg_face(const MeshDims &md, const double *D, const double *fg, const double *x,
+                          double *fo, const double *flag, hipStream_t st);
+hipError_t launch_dg_diag(const MeshDims &md, const double *G, const double *D, const double *fg,
+                          double *dinv, hipStream_t st);
+hipError_t launch_dg_restrict(const MeshDims &md, const double *rE, double *rL, const double *flag,
+                              hipStream_t st);
+hipError_t launch_dg_prolong_jacobi(const MeshDims &md, const double *rE, const double *dinv,
+                                    const double *zL, double *zE, const double *flag,
+                                    hipStream_t st);
+hipError_t launch_dg_rhs(const double *wdet, const double *f, double *b, int64_t n,
+                         hipStream_t st);
 hipError_t launch_coarse_restrict(const MeshDims &md, const double *gllx, const double *r,
                                   double *rc, hipStream_t st);
 hipError_t launch_coarse_prolong(const MeshDims &md, const double *gllx, const double *xc,

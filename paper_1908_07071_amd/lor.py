@@ -23,7 +23,7 @@ LOR_BC_DIRICHLET, LOR_BC_NEUMANN = 0, 1
 LOR_PREC_FP64, LOR_PREC_MIXED = 0, 1
 LOR_ORD_MDF, LOR_ORD_NATURAL = 0, 1
 LOR_MAP_LDOF, LOR_MAP_ORDER, LOR_MAP_ORDER_OFFSET = 0, 1, 2
-LOR_MAP_SCHEDULE, LOR_MAP_SCHEDULE_OFFSET = 3, 4
+LOR_MAP_SCHEDULE, LOR_MAP_SCHEDULE_OFFSET, LOR_MAP_E2L = 3, 4, 5
 
 EXPORTED = [
     "lor_default_options", "lor_error_string", "lor_setup", "lor_ndofs", "lor_device_bytes",
