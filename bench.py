@@ -55,6 +55,73 @@ def apply_algorithmic_bytes(dim, n, p):
     return 16 * N + g * n ** dim * (p + 1) ** dim
 
 
+def dg_apply_algorithmic_bytes(dim, n, p):
+    """DG operator launch pair: x read and y written (16 B per E-vector node),
+    the float64 geometric factors per node (48 B in 3D, 24 B in 2D) and the
+    face geometry (omega, sigma and J^-1 n on both sides: 64 B per face
+    node).  The face records passed from the face kernel to the element
+    kernel are an intermediate of this design, not counted."""
+    Q = p + 1
+    N = n ** dim * Q ** dim
+    g = 48 if dim == 3 else 24
+    faces = dim * (n + 1) * n ** (dim - 1)
+    return 16 * N + g * N + 64 * faces * Q ** (dim - 1)
+
+
+def dg_measure(L, torch, dim, n, p, rtol, steps, precision):
+    """Interior penalty and BR2 DG solves at the penalties 1.5 (p+1)^2 x
+    {1, 10, 100, 1e4} on a perturbed n^dim mesh (seed 2)."""
+    from paper_1908_07071_amd import inputs
+    V = inputs.structured_vertices(dim, n, 0.1, seed=2)
+    dev = torch.device("cuda:0")
+    out = {"workload": (f"{dim}D IP and BR2 DG Poisson, {n}^{dim} hexes perturbed <=10% h (seed 2), "
+                        f"p={p}, f from u=prod sin(pi x_i), flexible CG to {rtol:g}, preconditioner "
+                        f"{'FP32 Schwarz part' if precision == 'mixed' else 'FP64'}"),
+           "runs": []}
+    for meth, code in (("ip", L.LOR_IP), ("br2", L.LOR_BR2)):
+        for fac in (1, 10, 100, 1e4):
+            eta = 1.5 * (p + 1) ** 2 * fac
+            opt = L.lor_default_options()
+            opt.precision = L.LOR_PREC_MIXED if precision == "mixed" else L.LOR_PREC_FP64
+            h = L.lor_setup(dim, n, V, p, method=code, penalty=eta, options=opt)
+            N = L.lor_ndofs(h)
+            coords = L.lor_dof_coords(h, dim)
+            f = torch.tensor(inputs.manufactured_f(coords), device=dev)
+            b = torch.empty_like(f)
+            L.lor_assemble_rhs(h, f, b)
+            x = torch.zeros_like(b)
+            info = L.lor_pcg_solve(h, b, x, rtol=rtol, maxit=5000, check=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                info = L.lor_pcg_solve(h, b, x, rtol=rtol, maxit=5000, check=False)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / steps
+            run = {"method": meth, "eta": eta, "N": N, "iters": info.iters, "status": info.status,
+                   "rel_res_true": info.rel_res_true, "ms_per_solve": ms, "dofs_per_s": N / (ms * 1e-3)}
+            if fac == 1:
+                xr = torch.tensor(inputs.uniform_vector(N, 3), device=dev)
+                y = torch.empty_like(xr)
+                for _ in range(5):
+                    L.lor_apply_A(h, xr, y)
+                L.lor_timing(h, True)
+                for _ in range(100):
+                    L.lor_apply_A(h, xr, y)
+                tA, nA = L.lor_timing_read(h, L.LOR_T_APPLY_A)
+                L.lor_timing(h, False)
+                t_apply = tA / nA * 1e-3
+                ab = dg_apply_algorithmic_bytes(dim, n, p)
+                run["operator_ms"] = t_apply * 1e3
+                run["operator_gdofs"] = N / t_apply / 1e9
+                run["operator_algorithmic_bytes"] = ab
+                run["operator_hbm_frac"] = ab / t_apply / (HBM_PEAK_GBS * 1e9)
+            L.lor_free(h)
+            print(f"[bench] DG {meth} eta={eta:g}: {ms:.2f} ms/solve, iters={info.iters}, "
+                  f"rel_res_true={info.rel_res_true:.2e}", file=sys.stderr, flush=True)
+            out["runs"].append(run)
+    return out
+
+
 def _kept(p):
     levels = [list(range(p + 1))]
     while len(levels[-1]) > 2:
@@ -112,6 +179,8 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed",
                     help="mixed: FP32 patch V-cycles inside FP64 flexible CG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dg", action="store_true", help="skip the DG (IP/BR2, 12^3, p=6) runs")
+    ap.add_argument("--dg-n", type=int, default=12)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -248,6 +317,8 @@ def main():
             "algorithmic_bytes_per_launch": abytes, "avg_launch_ms": avg_ms,
         },
     }
+    if not args.no_dg:
+        out["dg"] = dg_measure(L, torch, dim, args.dg_n, p, args.rtol, 1, args.precision)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(dim, p, info.iters)

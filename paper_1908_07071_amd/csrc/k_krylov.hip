@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_p_update(double *__restrict__ p, double
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
     p[i] = z[i] + beta * p[i];
-    q[i] = 0.0;
+    if (q) q[i] = 0.0;  // only when the operator accumulates into q
   }
 }
 

@@ -18,6 +18,14 @@ namespace lor {
 
 namespace {
 
+// Workgroup barrier for LDS data only.  __syncthreads() is a release /
+// acquire fence at workgroup scope, which makes every wavefront wait for all
+// of its outstanding global loads as well; the element-loop kernel keeps the
+// next element's loads in flight across its barriers, so it waits for its
+// LDS operations only.  (The memory clobber keeps the compiler from moving
+// LDS accesses across the barrier.)
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // Map block index -> element tile so that each XCD (blocks are dealt to the 8
 // XCDs round robin) works on one contiguous range of elements, which keeps
 // neighbouring elements' shared nodes in the same L2.
@@ -61,7 +69,7 @@ __device__ inline void add_face(const double *__restrict__ fo, int64_t face, int
 // to the reference flux at face nodes before the transposed contractions,
 // value terms added to the result.
 template <int Q, bool DG>
-__global__ __launch_bounds__(256) void k_apply_cg3(MeshDims md, const double *__restrict__ G,
+__global__ __launch_bounds__(256) void k_apply_cg3(MeshDims md, const double *G,
                                                    const double *__restrict__ Dg,
                                                    const double *__restrict__ x,
                                                    double *__restrict__ y,
@@ -70,13 +78,18 @@ __global__ __launch_bounds__(256) void k_apply_cg3(MeshDims md, const double *__
                                                    const double *__restrict__ fo) {
   if (flag && flag[S_DONE] != 0.0) return;
   constexpr int Q2 = Q * Q, Q3 = Q2 * Q, EPB = 256 / Q2;
-  __shared__ double sD[Q2];
-  __shared__ double s0[EPB][Q3];
-  __shared__ double s1[EPB][Q3];
+  __shared__ double sD[Q2];            // D[i][k] = l_k'(x_i)
+  __shared__ double sDT[Q2];           // transposed
+  __shared__ double su[EPB][Q3];       // element values, staged once
+  __shared__ double sf[2][2][EPB][Q2]; // per z-plane fluxes fx, fy (double buffered)
   __shared__ double red[256];
   const int tid = threadIdx.x;
   const int le = tid / Q2, t = tid % Q2, a = t % Q, b = t / Q;
-  if (tid < Q2) sD[tid] = Dg[tid];
+  const int lq = le < EPB ? le : 0;  // threads past the last element slot idle
+  if (tid < Q2) {
+    sD[tid] = Dg[tid];
+    sDT[(tid % Q) * Q + tid / Q] = Dg[tid];
+  }
   const int64_t nel = int64_t(md.n[0]) * md.n[1] * md.n[2];
   const int64_t e = int64_t(xcd_tile(blockIdx.x, gridDim.x)) * EPB + le;
   const bool active = le < EPB && e < nel;
@@ -92,60 +105,64 @@ __global__ __launch_bounds__(256) void k_apply_cg3(MeshDims md, const double *__
   const int ox = dir ? 1 : 0;
   bool inxy = true;
   if (dir) inxy = gx > 0 && gx < md.ng[0] - 1 && gy > 0 && gy < md.ng[1] - 1;
-  int64_t base = (int64_t(gx - ox) + int64_t(md.nu[0]) * (gy - ox));
+  const int64_t base = (int64_t(gx - ox) + int64_t(md.nu[0]) * (gy - ox));
   const int64_t sz = int64_t(md.nu[0]) * md.nu[1];
-  double u[Q];
   const int64_t ebase = (active ? e : 0) * Q3 + a + Q * b;
+  // gather the column (a, b, 0..p) into LDS
 #pragma unroll
   for (int c = 0; c < Q; ++c) {
+    double u;
     if (DG) {
-      u[c] = active ? x[ebase + Q2 * c] : 0.0;
+      u = active ? x[ebase + Q2 * c] : 0.0;
     } else {
       const int gz = ez * p + c;
       const bool in = active && inxy && (!dir || (gz > 0 && gz < md.ng[2] - 1));
-      u[c] = in ? x[base + sz * (gz - ox)] : 0.0;
+      u = in ? x[base + sz * (gz - ox)] : 0.0;
     }
+    if (le < EPB) su[le][a + Q * (b + Q * c)] = u;
   }
   FaceRef fr[3];
   if (DG) elem_faces(md, ex, ey, ez, fr);
-  double vt[DG ? Q : 1];
+  const double *Ge = G + (active ? e : 0) * 6 * Q3 + a + Q * b;
+  double gn[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) gn[i] = active ? Ge[i * Q3] : 0.0;
+  double acc[Q];
+#pragma unroll
+  for (int c = 0; c < Q; ++c) acc[c] = 0.0;
   __syncthreads();
-  double uz[Q];
-#pragma unroll
+  const double *U = su[lq];
+  const double *Da = sD + a * Q, *Db = sD + b * Q, *DaT = sDT + a * Q, *DbT = sDT + b * Q;
+  // One z-plane per iteration (a real loop: per-plane state only): reference
+  // gradient, pointwise G, the transposed xi_1 / xi_2 contractions through a
+  // plane buffer, and the transposed xi_3 contraction into the column
+  // accumulator.  G of the next plane is loaded one iteration ahead.
+#pragma unroll 1
   for (int c = 0; c < Q; ++c) {
-    double acc = 0.0;
+    // keep the loop-invariant D rows in LDS instead of 4Q registers
+    asm volatile("" ::: "memory");
+    const double g00 = gn[0], g01 = gn[1], g02 = gn[2], g11 = gn[3], g12 = gn[4], g22 = gn[5];
+    if (c + 1 < Q) {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) acc += sD[c * Q + k] * u[k];
-    uz[c] = acc;
-    if (le < EPB) s0[le][a + Q * (b + Q * c)] = u[c];
-  }
-  __syncthreads();
-  double fz[Q];
-  const double *Ge = G + (active ? e : 0) * 6 * Q3;
-  double fx[Q], fy[Q];
-#pragma unroll
-  for (int c = 0; c < Q; ++c) {
-    double ux = 0.0, uy = 0.0;
-    if (le < EPB) {
-#pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        ux += sD[a * Q + k] * s0[le][k + Q * (b + Q * c)];
-        uy += sD[b * Q + k] * s0[le][a + Q * (k + Q * c)];
-      }
+      for (int i = 0; i < 6; ++i) gn[i] = active ? Ge[i * Q3 + Q2 * (c + 1)] : 0.0;
     }
-    const int q = a + Q * (b + Q * c);
-    double g00 = 0, g01 = 0, g02 = 0, g11 = 0, g12 = 0, g22 = 0;
-    if (active) {
-      g00 = Ge[0 * Q3 + q];
-      g01 = Ge[1 * Q3 + q];
-      g02 = Ge[2 * Q3 + q];
-      g11 = Ge[3 * Q3 + q];
-      g12 = Ge[4 * Q3 + q];
-      g22 = Ge[5 * Q3 + q];
-    }
-    fx[c] = g00 * ux + g01 * uy + g02 * uz[c];
-    fy[c] = g01 * ux + g11 * uy + g12 * uz[c];
-    fz[c] = g02 * ux + g12 * uy + g22 * uz[c];
+    const double *Dc = Dg + c * Q;  // wave-uniform row
+    // the scheduling fences keep each contraction's LDS reads next to their
+    // FMAs, so that a plane needs few registers and many waves fit a SIMD
+    double ux = 0.0, uy = 0.0, uz = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) ux += Da[k] * U[k + Q * (b + Q * c)];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) uy += Db[k] * U[a + Q * (k + Q * c)];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) uz += Dc[k] * U[a + Q * (b + Q * k)];
+    __builtin_amdgcn_sched_barrier(0);
+    double fx = g00 * ux + g01 * uy + g02 * uz;
+    double fy = g01 * ux + g11 * uy + g12 * uz;
+    double fz = g02 * ux + g12 * uy + g22 * uz;
+    double own = 0.0;  // contributions to node (a, b, c) itself
     if (DG) {
       double v = 0.0, h0 = 0.0, h1 = 0.0, h2 = 0.0;
       if (active) {
@@ -156,49 +173,45 @@ __global__ __launch_bounds__(256) void k_apply_cg3(MeshDims md, const double *__
         if (c == 0) add_face<Q2>(fo, fr[2].f0, 1, a + Q * b, v, h0, h1, h2);
         if (c == p) add_face<Q2>(fo, fr[2].f1, 0, a + Q * b, v, h0, h1, h2);
       }
-      fx[c] += h0;
-      fy[c] += h1;
-      fz[c] += h2;
-      vt[DG ? c : 0] = v;
+      fx += h0;
+      fy += h1;
+      fz += h2;
+      own = v;
     }
-  }
-  __syncthreads();
 #pragma unroll
-  for (int c = 0; c < Q; ++c) {
+    for (int k = 0; k < Q; ++k) acc[k] += Dc[k] * fz;
     if (le < EPB) {
-      s0[le][a + Q * (b + Q * c)] = fx[c];
-      s1[le][a + Q * (b + Q * c)] = fy[c];
+      sf[c & 1][0][le][t] = fx;
+      sf[c & 1][1][le][t] = fy;
     }
+    __syncthreads();
+    const double *FX = sf[c & 1][0][lq], *FY = sf[c & 1][1][lq];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) own += DaT[k] * FX[k + Q * b];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) own += DbT[k] * FY[a + Q * k];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) acc[k] += k == c ? own : 0.0;
   }
-  __syncthreads();
   double dotp = 0.0;
 #pragma unroll
   for (int c = 0; c < Q; ++c) {
-    double acc = 0.0;
-    if (le < EPB) {
-#pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        acc += sD[k * Q + a] * s0[le][k + Q * (b + Q * c)];
-        acc += sD[k * Q + b] * s1[le][a + Q * (k + Q * c)];
-        acc += sD[k * Q + c] * fz[k];
-      }
-    }
+    if (le < EPB) dotp += su[le][a + Q * (b + Q * c)] * acc[c];
     if (DG) {
-      acc += vt[DG ? c : 0];
-      dotp += u[c] * acc;
-      if (active) y[ebase + Q2 * c] = acc;
+      if (active) y[ebase + Q2 * c] = acc[c];
       continue;
     }
-    dotp += u[c] * acc;
     const int gz = ez * p + c;
     const bool in = active && inxy && (!dir || (gz > 0 && gz < md.ng[2] - 1));
     if (in) {
       double *dst = y + base + sz * (gz - ox);
       const bool interior = a > 0 && a < p && b > 0 && b < p && c > 0 && c < p;
       if (interior)
-        *dst = acc;
+        *dst = acc[c];
       else
-        unsafeAtomicAdd(dst, acc);
+        unsafeAtomicAdd(dst, acc[c]);
     }
   }
   if (partials) {
@@ -209,6 +222,167 @@ __global__ __launch_bounds__(256) void k_apply_cg3(MeshDims md, const double *__
       __syncthreads();
     }
     if (tid == 0) partials[blockIdx.x] = red[0];
+  }
+}
+
+// 3D, 5 <= Q <= 8: one element per block of Q wavefronts; wavefront c owns
+// the GLL plane (., ., c) with one node per lane.  The plane index is uniform
+// in a wavefront, so the xi_3 derivative entries D[c][k] and D[k][c] are
+// scalar operands; the rows D[a][.], D[b][.] stay in registers and the
+// transposed rows are read from LDS, which keeps the kernel at about 70
+// registers so that four elements per CU have their loads in flight (the
+// kernel is bound by HBM latency, not by arithmetic).  x and G are loaded
+// with one coalesced access per wavefront and array; the three flux
+// components go through LDS for the transposed contractions.  Same results
+// as the column kernel up to the order of the floating-point sums.
+template <int Q, bool DG>
+__global__ __launch_bounds__(Q * 64) __attribute__((amdgpu_waves_per_eu(7)))
+void k_apply_pw3(MeshDims md, const double *__restrict__ G, const double *__restrict__ Dg,
+                 const double *__restrict__ x, double *__restrict__ y,
+                 double *__restrict__ partials, const double *flag,
+                 const double *__restrict__ fo, double *__restrict__ yE) {
+  if (flag && flag[S_DONE] != 0.0) return;
+  constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
+  static_assert(Q2 <= 64, "one plane per wavefront");
+  __shared__ double su[Q3], sfx[Q3], sfy[Q3], sfz[Q3];
+  __shared__ double sDT[Q2];
+  __shared__ double red[Q];
+  const int lane = threadIdx.x % 64;
+  const int c = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const bool valid = lane < Q2;
+  const int t = valid ? lane : 0;
+  const int a = t % Q, b = t / Q;
+  const int node = t + Q2 * c;
+  const int64_t nel = int64_t(md.n[0]) * md.n[1] * md.n[2];
+  const int64_t e = xcd_tile(blockIdx.x, gridDim.x);
+  const bool active = valid && e < nel;
+  const int p = Q - 1;
+  // streamed data first: G (6 per node) and x
+  const double *Ge = G + (e < nel ? e : 0) * 6 * Q3 + node;
+  double g[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) g[i] = active ? Ge[i * Q3] : 0.0;
+  const int ex = int(e % md.n[0]), ey = int((e / md.n[0]) % md.n[1]),
+            ez = int(e / (int64_t(md.n[0]) * md.n[1]));
+  const int gx = ex * p + a, gy = ey * p + b, gz = ez * p + c;
+  const bool dir = md.dirichlet;
+  const int ox = dir ? 1 : 0;
+  bool in = active;
+  if (!DG && dir)
+    in = in && gx > 0 && gx < md.ng[0] - 1 && gy > 0 && gy < md.ng[1] - 1 && gz > 0 &&
+         gz < md.ng[2] - 1;
+  const int64_t li = DG ? e * Q3 + node
+                        : int64_t(gx - ox) + int64_t(md.nu[0]) * (int64_t(gy - ox) +
+                                                                  int64_t(md.nu[1]) * (gz - ox));
+  const double u = in ? x[li] : 0.0;
+  if (threadIdx.x < Q2) sDT[(threadIdx.x % Q) * Q + threadIdx.x / Q] = Dg[threadIdx.x];
+  double Da[Q], Db[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    Da[k] = Dg[a * Q + k];
+    Db[k] = Dg[b * Q + k];
+  }
+  if (valid) su[node] = u;
+  __syncthreads();
+  double ux = 0.0, uy = 0.0, uz = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    ux += Da[k] * su[k + Q * b + Q2 * c];
+    uy += Db[k] * su[a + Q * k + Q2 * c];
+    uz += Dg[c * Q + k] * su[t + Q2 * k];
+  }
+  double fx = g[0] * ux + g[1] * uy + g[2] * uz;
+  double fy = g[1] * ux + g[3] * uy + g[4] * uz;
+  double fz = g[2] * ux + g[4] * uy + g[5] * uz;
+  double v = 0.0;
+  if (DG && active) {
+    FaceRef fr[3];
+    elem_faces(md, ex, ey, ez, fr);
+    double h0 = 0.0, h1 = 0.0, h2 = 0.0;
+    if (a == 0) add_face<Q2>(fo, fr[0].f0, 1, b + Q * c, v, h0, h1, h2);
+    if (a == p) add_face<Q2>(fo, fr[0].f1, 0, b + Q * c, v, h0, h1, h2);
+    if (b == 0) add_face<Q2>(fo, fr[1].f0, 1, a + Q * c, v, h0, h1, h2);
+    if (b == p) add_face<Q2>(fo, fr[1].f1, 0, a + Q * c, v, h0, h1, h2);
+    if (c == 0) add_face<Q2>(fo, fr[2].f0, 1, a + Q * b, v, h0, h1, h2);
+    if (c == p) add_face<Q2>(fo, fr[2].f1, 0, a + Q * b, v, h0, h1, h2);
+    fx += h0;
+    fy += h1;
+    fz += h2;
+  }
+  if (valid) {
+    sfx[node] = fx;
+    sfy[node] = fy;
+    sfz[node] = fz;
+  }
+  __syncthreads();
+  double acc = v;
+  const double *DaT = sDT + a * Q, *DbT = sDT + b * Q;
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    acc += DaT[k] * sfx[k + Q * b + Q2 * c] + DbT[k] * sfy[a + Q * k + Q2 * c] +
+           Dg[k * Q + c] * sfz[t + Q2 * k];
+  if (DG) {
+    if (active) y[li] = acc;
+  } else if (in) {
+    // element-interior nodes belong to this element only; the others are
+    // summed over their elements by k_skeleton_gather (no atomics)
+    const bool interior = a > 0 && a < p && b > 0 && b < p && c > 0 && c < p;
+    if (interior)
+      y[li] = acc;
+    else
+      yE[e * Q3 + node] = acc;
+  }
+  if (partials) {
+    double d = in ? u * acc : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off);
+    if (lane == 0) red[c] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tot = 0.0;
+      for (int i = 0; i < Q; ++i) tot += red[i];
+      partials[blockIdx.x] = tot;
+    }
+  }
+}
+
+// y on the element skeleton (GLL grid nodes with some coordinate on an
+// element interface): the sum over the elements sharing the node of their
+// element-local results yE, added in a fixed element order.  Nodes inside
+// one element were stored by the element kernel.
+template <int Q>
+__global__ void k_skeleton_gather(MeshDims md, const double *__restrict__ yE,
+                                  double *__restrict__ y, const double *flag) {
+  if (flag && flag[S_DONE] != 0.0) return;
+  constexpr int Q3 = Q * Q * Q;
+  const int p = Q - 1;
+  const int ox = md.dirichlet ? 1 : 0;
+  const int64_t N = int64_t(md.nu[0]) * md.nu[1] * md.nu[2];
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int g[3] = {int(i % md.nu[0]) + ox, int((i / md.nu[0]) % md.nu[1]) + ox,
+                      int(i / (int64_t(md.nu[0]) * md.nu[1])) + ox};
+    if (g[0] % p != 0 && g[1] % p != 0 && g[2] % p != 0) continue;
+    double acc = 0.0;
+    for (int cb = 0; cb < 8; ++cb) {
+      int e[3], l[3];
+      bool ok = true;
+      for (int d = 0; d < 3; ++d) {
+        if (((cb >> d) & 1) == 0) {
+          e[d] = g[d] / p;
+          l[d] = g[d] - e[d] * p;
+          if (e[d] >= md.n[d]) ok = false;
+        } else {
+          if (g[d] % p != 0 || g[d] == 0) ok = false;
+          e[d] = g[d] / p - 1;
+          l[d] = p;
+        }
+      }
+      if (!ok) continue;
+      const int64_t ei = e[0] + int64_t(md.n[0]) * (e[1] + int64_t(md.n[1]) * e[2]);
+      acc += yE[ei * Q3 + l[0] + Q * (l[1] + Q * l[2])];
+    }
+    y[i] = acc;
   }
 }
 
@@ -345,12 +519,27 @@ inline int grid_for(int64_t n, int bs) {
 
 template <int Q>
 hipError_t apply_q(const MeshDims &md, const double *G, const double *D, const double *x,
-                   double *y, double *partials, const double *flag, const double *fo,
+                   double *y, double *partials, const double *flag, const double *fo, double *yE,
                    hipStream_t st) {
   constexpr int Q2 = Q * Q;
   constexpr int EPB = 256 / Q2;
   const int64_t nel = int64_t(md.n[0]) * md.n[1] * (md.dim == 3 ? md.n[2] : 1);
   const int nb = int((nel + EPB - 1) / EPB);
+  if constexpr (Q >= 5 && Q <= 8) {
+    if (md.dim == 3) {
+      if (fo) {
+        k_apply_pw3<Q, true><<<int(nel), Q * 64, 0, st>>>(md, G, D, x, y, partials, flag, fo,
+                                                          nullptr);
+      } else {
+        if (!yE) return hipErrorInvalidValue;
+        k_apply_pw3<Q, false><<<int(nel), Q * 64, 0, st>>>(md, G, D, x, y, partials, flag,
+                                                           nullptr, yE);
+        const int64_t N = int64_t(md.nu[0]) * md.nu[1] * md.nu[2];
+        k_skeleton_gather<Q><<<grid_for(N, 256), 256, 0, st>>>(md, yE, y, flag);
+      }
+      return hipGetLastError();
+    }
+  }
   if (md.dim == 3) {
     if (fo)
       k_apply_cg3<Q, true><<<nb, 256, 0, st>>>(md, G, D, x, y, partials, flag, fo);
@@ -367,8 +556,14 @@ hipError_t apply_q(const MeshDims &md, const double *G, const double *D, const d
 
 }  // namespace
 
-int apply_cg_blocks(const MeshDims &md) {
+bool apply_cg_uses_skeleton(const MeshDims &md) {
+  return md.dim == 3 && md.p + 1 >= 5 && md.p + 1 <= 8;
+}
+
+int apply_cg_blocks(const MeshDims &md, bool dg) {
   const int Q = md.p + 1;
+  (void)dg;
+  if (md.dim == 3 && Q >= 5 && Q <= 8) return int(int64_t(md.n[0]) * md.n[1] * md.n[2]);
   const int EPB = 256 / (Q * Q);
   const int64_t nel = int64_t(md.n[0]) * md.n[1] * (md.dim == 3 ? md.n[2] : 1);
   return int((nel + EPB - 1) / EPB);
@@ -376,23 +571,23 @@ int apply_cg_blocks(const MeshDims &md) {
 
 hipError_t launch_apply_cg(const MeshDims &md, const double *G, const double *D, const double *x,
                            double *y, double *partials, const double *flag, hipStream_t st,
-                           const double *fo) {
+                           const double *fo, double *yE) {
   switch (md.p + 1) {
-    case 2: return apply_q<2>(md, G, D, x, y, partials, flag, fo, st);
-    case 3: return apply_q<3>(md, G, D, x, y, partials, flag, fo, st);
-    case 4: return apply_q<4>(md, G, D, x, y, partials, flag, fo, st);
-    case 5: return apply_q<5>(md, G, D, x, y, partials, flag, fo, st);
-    case 6: return apply_q<6>(md, G, D, x, y, partials, flag, fo, st);
-    case 7: return apply_q<7>(md, G, D, x, y, partials, flag, fo, st);
-    case 8: return apply_q<8>(md, G, D, x, y, partials, flag, fo, st);
-    case 9: return apply_q<9>(md, G, D, x, y, partials, flag, fo, st);
-    case 10: return apply_q<10>(md, G, D, x, y, partials, flag, fo, st);
-    case 11: return apply_q<11>(md, G, D, x, y, partials, flag, fo, st);
-    case 12: return apply_q<12>(md, G, D, x, y, partials, flag, fo, st);
-    case 13: return apply_q<13>(md, G, D, x, y, partials, flag, fo, st);
-    case 14: return apply_q<14>(md, G, D, x, y, partials, flag, fo, st);
-    case 15: return apply_q<15>(md, G, D, x, y, partials, flag, fo, st);
-    case 16: return apply_q<16>(md, G, D, x, y, partials, flag, fo, st);
+    case 2: return apply_q<2>(md, G, D, x, y, partials, flag, fo, yE, st);
+    case 3: return apply_q<3>(md, G, D, x, y, partials, flag, fo, yE, st);
+    case 4: return apply_q<4>(md, G, D, x, y, partials, flag, fo, yE, st);
+    case 5: return apply_q<5>(md, G, D, x, y, partials, flag, fo, yE, st);
+    case 6: return apply_q<6>(md, G, D, x, y, partials, flag, fo, yE, st);
+    case 7: return apply_q<7>(md, G, D, x, y, partials, flag, fo, yE, st);
+    case 8: return apply_q<8>(md, G, D, x, y, partials, flag, fo, yE, st);
+    case 9: return apply_q<9>(md, G, D, x, y, partials, flag, fo, yE, st);
+    case 10: return apply_q<10>(md, G, D, x, y, partials, flag, fo, yE, st);
+    case 11: return apply_q<11>(md, G, D, x, y, partials, flag, fo, yE, st);
+    case 12: return apply_q<12>(md, G, D, x, y, partials, flag, fo, yE, st);
+    case 13: return apply_q<13>(md, G, D, x, y, partials, flag, fo, yE, st);
+    case 14: return apply_q<14>(md, G, D, x, y, partials, flag, fo, yE, st);
+    case 15: return apply_q<15>(md, G, D, x, y, partials, flag, fo, yE, st);
+    case 16: return apply_q<16>(md, G, D, x, y, partials, flag, fo, yE, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -40,6 +40,7 @@ struct lor_handle {
   int64_t fac_bytes = 0;
   XferTab *d_xfer = nullptr;
   double *d_A0inv = nullptr, *d_rc = nullptr, *d_xc = nullptr;
+  double *d_yE = nullptr;  // element-boundary partial results of the CG operator
   double *d_fg = nullptr, *d_fo = nullptr, *d_dinv = nullptr, *d_rL = nullptr, *d_zL = nullptr;
   double *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr, *d_rold = nullptr;
   double *d_tmp = nullptr, *d_scal = nullptr, *d_part = nullptr, *d_part2 = nullptr;
@@ -444,6 +445,7 @@ int setup_impl(lor_handle &h, hipStream_t st) {
   const int ncomp = dim == 3 ? 6 : 3;
   HIPCHK(h.alloc(&h.d_G, size_t(h.nel) * ncomp * nq));
   HIPCHK(h.alloc(&h.d_wdet, size_t(h.nel) * nq));
+  if (!dg && apply_cg_uses_skeleton(md)) HIPCHK(h.alloc(&h.d_yE, size_t(h.nel) * nq));
   int *bad;
   HIPCHK(h.alloc(&bad, 1));
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), st));
@@ -474,7 +476,7 @@ int setup_impl(lor_handle &h, hipStream_t st) {
   HIPCHK(h.alloc(&h.d_rold, N));
   HIPCHK(h.alloc(&h.d_tmp, N));
   HIPCHK(h.alloc(&h.d_scal, S_COUNT));
-  h.npart = std::max(kRedBlocks, apply_cg_blocks(md));
+  h.npart = std::max(kRedBlocks, apply_cg_blocks(md, dg));
   HIPCHK(h.alloc(&h.d_part, h.npart));
   HIPCHK(h.alloc(&h.d_part2, h.npart));
   HIPCHK(hipHostMalloc((void **)&h.h_scal, S_COUNT * sizeof(double), 0));
@@ -551,7 +553,7 @@ int apply_A_impl(lor_handle *h, const double *x, double *y, double *partials, co
   Span sp(h, LOR_T_APPLY_A, st);
   if (h->method != LOR_CG) HIPCHK(launch_dg_face(h->md, h->d_D, h->d_fg, x, h->d_fo, flag, st));
   HIPCHK(launch_apply_cg(h->md, h->d_G, h->d_D, x, y, partials, flag, st,
-                         h->method != LOR_CG ? h->d_fo : nullptr));
+                         h->method != LOR_CG ? h->d_fo : nullptr, h->d_yE));
   return LOR_OK;
 }
 
@@ -677,7 +679,8 @@ int lor_assemble_rhs(lor_handle_t *h, const double *f_dev, double *b_dev, void *
 int lor_apply_A(lor_handle_t *h, const double *x_dev, double *y_dev, void *stream) {
   if (!h || !x_dev || !y_dev || x_dev == y_dev) return LOR_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (h->method == LOR_CG) HIPCHK(hipMemsetAsync(y_dev, 0, h->ndofs * sizeof(double), st));
+  if (h->method == LOR_CG && !apply_cg_uses_skeleton(h->md))
+    HIPCHK(hipMemsetAsync(y_dev, 0, h->ndofs * sizeof(double), st));
   return apply_A_impl(h, x_dev, y_dev, nullptr, nullptr, st);
 }
 
@@ -710,7 +713,10 @@ int lor_pcg_solve(lor_handle_t *h, const double *b, double *x, double rtol, int 
   HIPCHK(launch_finalize(s, h->d_part, nbv, FIN_RHO, 0, nullptr, st));
   HIPCHK(launch_copy(h->d_p, h->d_z, N, st));
   HIPCHK(hipMemsetAsync(h->d_q, 0, N * sizeof(double), st));
-  const int nba = apply_cg_blocks(h->md);
+  // the operator writes q completely (DG, or CG through the skeleton gather);
+  // otherwise q is accumulated atomically and must be cleared each iteration
+  const bool zero_q = h->method == LOR_CG && !apply_cg_uses_skeleton(h->md);
+  const int nba = apply_cg_blocks(h->md, h->method != LOR_CG);
   const int chunk = 8;
   int it = 0;
   bool done = false;
@@ -728,7 +734,7 @@ int lor_pcg_solve(lor_handle_t *h, const double *b, double *x, double rtol, int 
       if (fcg) HIPCHK(launch_dot_partials(h->d_z, h->d_rold, N, h->d_part2, s, st));
       HIPCHK(launch_finalize(s, h->d_part, nbv, fcg ? FIN_FCG : FIN_RHO, it + 1,
                              fcg ? h->d_part2 : nullptr, st));
-      HIPCHK(launch_p_update(h->d_p, h->d_q, h->d_z, N, s, st));
+      HIPCHK(launch_p_update(h->d_p, zero_q ? h->d_q : nullptr, h->d_z, N, s, st));
     }
     HIPCHK(hipMemcpyAsync(h->h_scal, s, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -736,7 +742,7 @@ int lor_pcg_solve(lor_handle_t *h, const double *b, double *x, double rtol, int 
   }
   HIPCHK(hipEventRecord(h->ev1, st));
   // true residual ||b - A x|| (stream-ordered, after the timed region)
-  HIPCHK(hipMemsetAsync(h->d_tmp, 0, N * sizeof(double), st));
+  if (zero_q) HIPCHK(hipMemsetAsync(h->d_tmp, 0, N * sizeof(double), st));
   rc = apply_A_impl(h, x, h->d_tmp, nullptr, nullptr, st);
   if (rc != LOR_OK) return rc;
   HIPCHK(launch_sub_dot(b, h->d_tmp, N, h->d_part, st));

@@ -123,12 +123,18 @@ hipError_t launch_lor_stencil(const MeshDims &md, int s, const int *kept_fine_id
                               hipStream_t st);
 hipError_t launch_rhs_cg(const MeshDims &md, const double *wdet, const double *f, double *b,
                          hipStream_t st);
-int apply_cg_blocks(const MeshDims &md);
+// Blocks (= partial sums) of one operator launch.
+int apply_cg_blocks(const MeshDims &md, bool dg);
 // fo == nullptr: CG operator on the L-vector; otherwise the DG volume term on
-// the E-vector plus the face records fo written by launch_dg_face.
+// the E-vector plus the face records fo written by launch_dg_face.  CG with
+// apply_cg_uses_skeleton(md): yE (n_el (p+1)^3 values) receives the
+// element-boundary partial results, which a second kernel sums into y (y is
+// then written completely, no zeroing needed); otherwise y must be zero on
+// entry (shared nodes are accumulated atomically) and yE is unused.
+bool apply_cg_uses_skeleton(const MeshDims &md);
 hipError_t launch_apply_cg(const MeshDims &md, const double *G, const double *D,
                            const double *x, double *y, double *partials, const double *flag,
-                           hipStream_t st, const double *fo = nullptr);
+                           hipStream_t st, const double *fo = nullptr, double *yE = nullptr);
 
 // DG (faces, penalties, diagonal, E-vector transfers)
 int64_t dg_face_count(const MeshDims &md);
