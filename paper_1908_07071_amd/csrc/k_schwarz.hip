@@ -206,14 +206,40 @@ __device__ __forceinline__ void sweep(T *Y, const char *blk) {
 // R = B - A X on one level (A from the global level stencil).  GB: the right
 // side is the global residual (finest level) instead of B in LDS.  Two rows
 // per lane and iteration, with all their global loads issued together.
+// The centre and forward half of a point's symmetric stencil record, with
+// 16-byte loads (the records are 64 B (float) or 128 B (double) aligned).
+template <int DIM, typename ST>
+__device__ __forceinline__ void load_sym_rec(const ST *__restrict__ rec, ST *a) {
+  constexpr int W = sym_width<DIM>(), C = DIM == 3 ? 13 : 4;
+  constexpr int PER = 16 / int(sizeof(ST));  // values per 16-byte load
+  ST v[W];
+#pragma unroll
+  for (int q = 0; q < W / PER; ++q) {
+    if constexpr (sizeof(ST) == 4) {
+      const float4 t = reinterpret_cast<const float4 *>(rec)[q];
+      v[4 * q] = t.x;
+      v[4 * q + 1] = t.y;
+      v[4 * q + 2] = t.z;
+      v[4 * q + 3] = t.w;
+    } else {
+      const double2 t = reinterpret_cast<const double2 *>(rec)[q];
+      v[2 * q] = t.x;
+      v[2 * q + 1] = t.y;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j <= C; ++j) a[C + j] = v[j];
+}
+
 template <int DIM, typename T, typename ST, bool GB>
 __device__ __forceinline__ void residual(T *R, const T *B, const T *X, const Box<DIM> &bx,
                                          const ST *__restrict__ st, int64_t npts, const int *lng,
                                          const double *__restrict__ rglob, const MeshDims &md) {
-  constexpr int NS = DIM == 3 ? 27 : 9;
+  constexpr int NS = DIM == 3 ? 27 : 9, C = NS / 2, W = sym_width<DIM>();
   constexpr int RB = 2;
   const int mx = bx.m[0], my = bx.m[1], mz = bx.m[2];
   const int ox = md.dirichlet ? 1 : 0;
+  (void)npts;
   for (int i0 = threadIdx.x; i0 < bx.n; i0 += 64 * RB) {
     ST a[RB][NS];
     T acc[RB];
@@ -230,9 +256,20 @@ __device__ __forceinline__ void residual(T *R, const T *B, const T *X, const Box
       } else {
         acc[r] = B[ii[r]];
       }
-      // every patch row is strictly inside the level grid: all 3^d entries exist
+      // centre and forward half from the point's own record; the backward
+      // half from the neighbours' records (the point's own record when the
+      // neighbour is outside the patch, where X is zero and the term dropped)
+      load_sym_rec<DIM, ST>(st + g * W, a[r]);
+      const int i = ii[r];
+      const int ix = i % mx, iy = (i / mx) % my, iz = DIM == 3 ? i / (mx * my) : 0;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) a[r][s] = st[int64_t(s) * npts + g];
+      for (int s = 0; s < C; ++s) {
+        const int sx = s % 3 - 1, sy = (s / 3) % 3 - 1, sz = DIM == 3 ? s / 9 - 1 : 0;
+        const int jx = ix + sx, jy = iy + sy, jz = iz + sz;
+        const bool in = jx >= 0 && jx < mx && jy >= 0 && jy < my && (DIM == 2 || (jz >= 0 && jz < mz));
+        const int64_t off = sx + int64_t(lng[0]) * (sy + int64_t(lng[1]) * sz);
+        a[r][s] = st[(in ? g + off : g) * W + (NS - 1 - s - C)];
+      }
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
@@ -361,7 +398,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       constexpr int C = DIM == 3 ? 13 : 4;
       T *Xc = lds_vec<DIM, T>(lds, pa, v, kc, 0);
       const T rhs = kc == 0 ? Xc[0] : lds_vec<DIM, T>(lds, pa, v, kc, 1)[0];
-      Xc[0] = rhs / T(stn[kc][int64_t(C) * pa.npts[kc] + g]);
+      Xc[0] = rhs / T(stn[kc][g * sym_width<DIM>()]);  // centre entry of the record
     }
     wave_sync();
   }

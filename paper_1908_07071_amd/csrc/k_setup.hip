@@ -411,6 +411,14 @@ __global__ void k_fill(double *x, int64_t n, double v) {
     x[i] = v;
 }
 
+template <int DIM, typename ST>
+__global__ void k_sym_stencil(const double *__restrict__ soa, int64_t npts, ST *__restrict__ out) {
+  constexpr int NS = DIM == 3 ? 27 : 9, C = NS / 2, W = sym_width<DIM>();
+  for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < npts;
+       g += int64_t(gridDim.x) * blockDim.x)
+    for (int j = 0; j < W; ++j) out[g * W + j] = j <= C ? ST(soa[int64_t(C + j) * npts + g]) : ST(0);
+}
+
 __global__ void k_to_float(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x)
@@ -512,6 +520,23 @@ hipError_t launch_gauss_jordan(int n, double *A, double *rowbuf, double *colbuf,
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   k_to_float<<<grid_for(n, 256), 256, 0, st>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sym_stencil(const double *soa, int64_t npts, int dim, void *out, bool f32,
+                              hipStream_t st) {
+  const int g = grid_for(npts, 256);
+  if (dim == 3) {
+    if (f32)
+      k_sym_stencil<3, float><<<g, 256, 0, st>>>(soa, npts, static_cast<float *>(out));
+    else
+      k_sym_stencil<3, double><<<g, 256, 0, st>>>(soa, npts, static_cast<double *>(out));
+  } else {
+    if (f32)
+      k_sym_stencil<2, float><<<g, 256, 0, st>>>(soa, npts, static_cast<float *>(out));
+    else
+      k_sym_stencil<2, double><<<g, 256, 0, st>>>(soa, npts, static_cast<double *>(out));
+  }
   return hipGetLastError();
 }
 

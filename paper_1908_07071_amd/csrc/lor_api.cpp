@@ -382,13 +382,17 @@ int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hi
   for (int k = 0; k < L; ++k) {
     const int s = int(h.kept[k].size()) - 1;
     pa.s[k] = s;
+    const int W = dim == 3 ? sym_width<3>() : sym_width<2>();
     if (mixed) {
       float *f32 = nullptr;
-      HIPCHK(h.alloc(&f32, size_t(NS) * h.npts[k]));
-      HIPCHK(launch_to_float(h.d_stencil[k], f32, int64_t(NS) * h.npts[k], st));
+      HIPCHK(h.alloc(&f32, size_t(W) * h.npts[k]));
+      HIPCHK(launch_sym_stencil(h.d_stencil[k], h.npts[k], dim, f32, true, st));
       pa.stencil[k] = reinterpret_cast<const double *>(f32);  // read as float by the kernel
     } else {
-      pa.stencil[k] = h.d_stencil[k];
+      double *f64 = nullptr;
+      HIPCHK(h.alloc(&f64, size_t(W) * h.npts[k]));
+      HIPCHK(launch_sym_stencil(h.d_stencil[k], h.npts[k], dim, f64, false, st));
+      pa.stencil[k] = f64;
     }
     pa.npts[k] = h.npts[k];
     for (int d = 0; d < 3; ++d) pa.lng[k][d] = d < dim ? h.n[d] * s + 1 : 1;

@@ -44,7 +44,8 @@ struct PatchArgs {
   int nlev;                          // levels of the element-structured hierarchy
   int s[kMaxLevels];                 // sub-intervals per element at each level
   int nv[3];                         // vertices per direction (n+1)
-  const double *stencil[kMaxLevels]; // global level stencils, slot-major 3^d x npts
+  const double *stencil[kMaxLevels]; // global level stencils, symmetric point-major records
+                                     // (sym_width), float when fp32
   int64_t npts[kMaxLevels];          // level grid points
   int lng[kMaxLevels][3];            // level grid points per direction
   const XferTab *xfer;               // [nlev-1][3] by (fine level, direction type)
@@ -72,6 +73,17 @@ struct PatchArgs {
 //   where off is the LDS offset of the neighbour from the row (padding pairs
 //   are zero).  Lane 63 carries the header of the next chunk instead:
 //   Q (bits 0-7) | nsteps (8-15) | W (16-23), W = couplings per record.
+// Level stencils as the patch kernel reads them: point-major, symmetric
+// half.  Record of grid point g: values of slots C, C+1, .., 3^d - 1 (the
+// centre and the neighbours after it in slot order; C = (3^d - 1) / 2),
+// zero-padded to kSymW values.  Slot s < C of point g equals slot
+// 3^d - 1 - s of the neighbour g + offset(s) (the LOR matrices are
+// symmetric bit for bit).
+template <int DIM>
+__host__ __device__ constexpr int sym_width() {
+  return DIM == 3 ? 16 : 8;
+}
+
 constexpr int kChunkRows = 63;
 constexpr int kSweepHeader = 96;
 constexpr int kSweepZero = 80;   // 16 zero bytes inside the header
@@ -166,6 +178,10 @@ hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r,
                                const double *flag, hipStream_t st);
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t st);
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st);
+// slot-major float64 stencil (3^dim x npts) -> symmetric point-major records
+// (sym_width values per point) in float (f32) or float64.
+hipError_t launch_sym_stencil(const double *soa, int64_t npts, int dim, void *out, bool f32,
+                              hipStream_t st);
 
 // Krylov helpers.  Scalars live in a small device array.
 enum Scal { S_RHO = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_TOL2, S_DONE, S_ITERS, S_FAIL,
