@@ -131,6 +131,22 @@ def _kept(p):
     return levels
 
 
+def measured_traffic(kernel_key):
+    """HBM bytes per launch of the FP32 patch kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE record (profiles/), or None when the
+    kernel's sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "patch_vcycle_16cube_p6_fp32_traffic.json")
+    if kernel_key != "patch_vcycle" or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return rec["bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
 def cpu_baseline(dim, p, iters_full, budget_s=25.0):
     """Time the float64 oracle (setup excluded) on a 2^3-element sample of the
     same workload and scale to DOFs/s of the full solve."""
@@ -313,7 +329,9 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": (measured_traffic(dom) if (dim, n, p) == (3, 16, 6) and args.precision == "mixed"
+                        else None),
             "algorithmic_bytes_per_launch": abytes, "avg_launch_ms": avg_ms,
         },
     }
