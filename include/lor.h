@@ -153,6 +153,29 @@ int lor_apply_P(lor_handle_t *h, const double *r_dev, double *z_dev, void *strea
 int lor_pcg_solve(lor_handle_t *h, const double *b_dev, double *x_dev,
                   double rtol, int maxit, lor_solve_info_t *info, void *stream);
 
+/* Batched solve of many independent problems and right-hand sides:
+ * pair k = i * nrhs + j solves A_i x_k = b_k with handle hs[i] (i < nprob,
+ * j < nrhs), exactly as lor_pcg_solve would (same kernels in the same
+ * order; the patch corrections, and the operator outside 5 <= p+1 <= 8 in 3D,
+ * are accumulated with float64 atomics, so the last bits of any two solves
+ * may differ).  Every pair gets its own device
+ * workspace; each pair's CG iterations are captured once into a HIP graph
+ * (8 iterations per graph, kernels turn into no-ops after the device-side
+ * convergence flag is set) and the graphs of all pairs are replayed on four
+ * worker streams until every pair has converged or reached maxit, so that
+ * small problems run concurrently and launch costs are paid once per chunk.
+ * A handle must not be used by another call during the batch (it may
+ * appear several times in hs).
+ * b, x: HOST arrays of nprob*nrhs DEVICE pointers (ndofs of the pair's
+ * handle each); stream: the caller's stream, ordered before and after the
+ * batch.  info: HOST array of nprob*nrhs entries (may be NULL); t_solve is
+ * the time of the whole batch.  Returns LOR_OK or the first failing pair's
+ * status (LOR_ENOCONV, LOR_EBREAKDOWN, LOR_EINVAL); LOR_ESTATE for a handle
+ * without preconditioner.  Allocates (and frees) the workspaces. */
+int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const double *const *b_dev,
+                        double *const *x_dev, double rtol, int maxit, lor_solve_info_t *info,
+                        void *stream);
+
 /* Integer maps for parity checks, HOST output.  If host_out is NULL only
  * *len is set.  which:
  *   LOR_MAP_LDOF          L-vector index -> flat GLL grid index

@@ -95,8 +95,11 @@ __global__ void k_copy(double *__restrict__ d, const double *__restrict__ s, int
     d[i] = s[i];
 }
 
+// The iteration count lives on the device (S_ITERS, incremented with each
+// recursive residual), so that a captured chunk of iterations can be replayed;
+// the solve also stops when S_ITERS reaches S_MAXIT.
 __global__ __launch_bounds__(1024) void k_finalize(double *scal, const double *__restrict__ partials,
-                                                   int count, int which, int iter,
+                                                   int count, int which,
                                                    const double *__restrict__ partials2) {
   if (which != FIN_BB && which != FIN_RRTRUE && scal[S_DONE] != 0.0) return;
   __shared__ double red[1024];
@@ -135,28 +138,27 @@ __global__ __launch_bounds__(1024) void k_finalize(double *scal, const double *_
       if (!(s > 0.0)) {
         scal[S_FAIL] = 1.0;
         scal[S_DONE] = 1.0;
-        scal[S_ITERS] = iter - 1;
       } else {
         scal[S_ALPHA] = scal[S_RHO] / s;
       }
       break;
     case FIN_RR:
       scal[S_RR] = s;
-      scal[S_ITERS] = iter;
-      if (s <= scal[S_TOL2] * scal[S_BB]) scal[S_DONE] = 1.0;
+      scal[S_ITERS] += 1.0;
+      if (s <= scal[S_TOL2] * scal[S_BB] || scal[S_ITERS] >= scal[S_MAXIT]) scal[S_DONE] = 1.0;
       if (!isfinite(s)) {
         scal[S_FAIL] = 2.0;
         scal[S_DONE] = 1.0;
       }
       break;
-    case FIN_RHO:   // s = r.z ; iter 0: initial rho
+    case FIN_RHO:   // s = r.z; before the first iteration: the initial rho
     case FIN_FCG: { // s = r.z, s2 = z.rold
       if (!(s > 0.0)) {
         scal[S_FAIL] = 1.0;
         scal[S_DONE] = 1.0;
         break;
       }
-      if (iter > 0) {
+      if (scal[S_ITERS] > 0.0) {
         const double num = which == FIN_FCG ? s - s2 : s;
         scal[S_BETA] = num / scal[S_RHO];
       }
@@ -184,9 +186,9 @@ hipError_t launch_dot_partials(const double *a, const double *b, int64_t n, doub
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(double *scal, const double *partials, int count, int which, int iter,
+hipError_t launch_finalize(double *scal, const double *partials, int count, int which,
                            const double *partials2, hipStream_t st) {
-  k_finalize<<<1, 1024, 0, st>>>(scal, partials, count, which, iter, partials2);
+  k_finalize<<<1, 1024, 0, st>>>(scal, partials, count, which, partials2);
   return hipGetLastError();
 }
 

@@ -468,19 +468,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
 }
 
+// gfx950: 160 KB of LDS per CU, all of it addressable by one workgroup.
+constexpr int kMaxDynLds = 160 * 1024;
+
+template <int DIM, typename T, typename ST>
+hipError_t prepare_t() {
+  constexpr int W = DIM == 3 ? 26 : 8;
+  return hipFuncSetAttribute((const void *)k_patch_vcycle<DIM, T, ST, W>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+}
+
 template <int DIM, typename T, typename ST>
 hipError_t launch_t(const PatchArgs &pa, int npatch, const double *r, double *z, const double *flag,
                     hipStream_t st) {
   constexpr int W = DIM == 3 ? 26 : 8;
   const size_t lds = size_t(pa.lds_total) * sizeof(T);
-  auto kern = k_patch_vcycle<DIM, T, ST, W>;
-  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-  if (e != hipSuccess) return e;
-  kern<<<npatch, 64, lds, st>>>(pa, r, z, flag);
+  if (lds > size_t(kMaxDynLds)) return hipErrorInvalidValue;
+  k_patch_vcycle<DIM, T, ST, W><<<npatch, 64, lds, st>>>(pa, r, z, flag);
   return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t prepare_patch_vcycle(const PatchArgs &pa) {
+  if (pa.md.dim == 3) return pa.fp32 ? prepare_t<3, float, float>() : prepare_t<3, double, double>();
+  return pa.fp32 ? prepare_t<2, float, float>() : prepare_t<2, double, double>();
+}
 
 hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r, double *z,
                                const double *flag, hipStream_t st) {

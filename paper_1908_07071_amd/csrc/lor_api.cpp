@@ -16,6 +16,19 @@
 
 using namespace lor;
 
+// Device workspace of one solve.  The handle holds one; a batched solve holds
+// one per (problem, right-hand side) pair so that the pairs of one problem can
+// run concurrently.
+struct Work {
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *rold = nullptr, *tmp = nullptr;
+  double *scal = nullptr, *part = nullptr, *part2 = nullptr;
+  double *rc = nullptr, *xc = nullptr;  // coarse-space vectors
+  double *yE = nullptr;                 // element-boundary operator results (CG skeleton path)
+  double *fo = nullptr;                 // DG face records
+  double *rL = nullptr, *zL = nullptr;  // DG: conforming vectors of E B E^T
+  double *h_scal = nullptr;             // pinned host copy of scal
+};
+
 struct lor_handle {
   int dim = 3, n[3] = {1, 1, 1}, p = 1, method = LOR_CG, bc = LOR_BC_DIRICHLET;
   double penalty = 0.0;
@@ -39,13 +52,11 @@ struct lor_handle {
   int64_t *d_fac_off = nullptr;
   int64_t fac_bytes = 0;
   XferTab *d_xfer = nullptr;
-  double *d_A0inv = nullptr, *d_rc = nullptr, *d_xc = nullptr;
-  double *d_yE = nullptr;  // element-boundary partial results of the CG operator
-  double *d_fg = nullptr, *d_fo = nullptr, *d_dinv = nullptr, *d_rL = nullptr, *d_zL = nullptr;
-  double *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr, *d_rold = nullptr;
-  double *d_tmp = nullptr, *d_scal = nullptr, *d_part = nullptr, *d_part2 = nullptr;
+  double *d_A0inv = nullptr;
+  double *d_fg = nullptr, *d_dinv = nullptr;
   int npart = 0;
-  double *h_scal = nullptr;  // pinned
+  Work w;                  // workspace of lor_pcg_solve / lor_apply_*
+  bool capturing = false;  // no event timing while a graph is captured
   PatchArgs pa{};
   // host copies for parity export
   std::vector<int32_t> order_all, order_off, sched_all, sched_off;
@@ -78,7 +89,7 @@ struct lor_handle {
   }
   ~lor_handle() {
     for (void *p : allocs) (void)hipFree(p);
-    if (h_scal) (void)hipHostFree(h_scal);
+    if (w.h_scal) (void)hipHostFree(w.h_scal);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
@@ -262,8 +273,6 @@ int build_coarse(lor_handle &h, const std::vector<double> &st0, hipStream_t st) 
   for (unsigned t = 0; t < nth; ++t) pool.emplace_back(work);
   for (auto &th : pool) th.join();
   HIPCHK(h.alloc(&h.d_A0inv, size_t(h.nc) * h.nc));
-  HIPCHK(h.alloc(&h.d_rc, h.nc));
-  HIPCHK(h.alloc(&h.d_xc, h.nc));
   HIPCHK(hipMemcpyAsync(h.d_A0inv, A0.data(), A0.size() * sizeof(double), hipMemcpyHostToDevice, st));
   double *rowbuf, *colbuf;
   int *bad;
@@ -411,6 +420,7 @@ int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hi
   pa.lds_total = tot;
   pa.fp32 = mixed ? 1 : 0;
   if (size_t(tot) * (mixed ? sizeof(float) : sizeof(double)) > 160 * 1024) return LOR_EINVAL;
+  HIPCHK(prepare_patch_vcycle(pa));
   return LOR_OK;
 }
 
@@ -449,7 +459,6 @@ int setup_impl(lor_handle &h, hipStream_t st) {
   const int ncomp = dim == 3 ? 6 : 3;
   HIPCHK(h.alloc(&h.d_G, size_t(h.nel) * ncomp * nq));
   HIPCHK(h.alloc(&h.d_wdet, size_t(h.nel) * nq));
-  if (!dg && apply_cg_uses_skeleton(md)) HIPCHK(h.alloc(&h.d_yE, size_t(h.nel) * nq));
   int *bad;
   HIPCHK(h.alloc(&bad, 1));
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), st));
@@ -463,27 +472,12 @@ int setup_impl(lor_handle &h, hipStream_t st) {
     const int QF = dim == 3 ? Q * Q : Q;
     h.nfaces = dg_face_count(md);
     HIPCHK(h.alloc(&h.d_fg, size_t(h.nfaces) * 8 * QF));
-    HIPCHK(h.alloc(&h.d_fo, size_t(h.nfaces) * 8 * QF));
     HIPCHK(h.alloc(&h.d_dinv, size_t(h.ndofs)));
     HIPCHK(launch_dg_face_geom(md, h.d_verts, h.d_gllx, h.d_gllw, h.d_wdet, h.method, h.penalty,
                                h.d_fg, st));
     HIPCHK(launch_dg_diag(md, h.d_G, h.d_D, h.d_fg, h.d_dinv, st));
-    HIPCHK(h.alloc(&h.d_rL, size_t(h.ncg)));
-    HIPCHK(h.alloc(&h.d_zL, size_t(h.ncg)));
   }
-  // Krylov work vectors
-  const int64_t N = h.ndofs;
-  HIPCHK(h.alloc(&h.d_r, N));
-  HIPCHK(h.alloc(&h.d_z, N));
-  HIPCHK(h.alloc(&h.d_p, N));
-  HIPCHK(h.alloc(&h.d_q, N));
-  HIPCHK(h.alloc(&h.d_rold, N));
-  HIPCHK(h.alloc(&h.d_tmp, N));
-  HIPCHK(h.alloc(&h.d_scal, S_COUNT));
   h.npart = std::max(kRedBlocks, apply_cg_blocks(md, dg));
-  HIPCHK(h.alloc(&h.d_part, h.npart));
-  HIPCHK(h.alloc(&h.d_part2, h.npart));
-  HIPCHK(hipHostMalloc((void **)&h.h_scal, S_COUNT * sizeof(double), 0));
   HIPCHK(hipEventCreate(&h.ev0));
   HIPCHK(hipEventCreate(&h.ev1));
   if (!md.dirichlet) return LOR_OK;  // Neumann: operator only
@@ -510,6 +504,47 @@ int setup_impl(lor_handle &h, hipStream_t st) {
   return LOR_OK;
 }
 
+// Allocates the device workspace of one solve for handle h.  Buffers are
+// appended to `owned` (hipMalloc'ed, freed by the owner) and counted in
+// `bytes`; the pinned scalar copy is returned in w.h_scal.
+int work_alloc(const lor_handle &h, Work &w, std::vector<void *> &owned, size_t &bytes) {
+  auto get = [&](double **ptr, size_t count) -> hipError_t {
+    void *p = nullptr;
+    const size_t b = std::max<size_t>(count * sizeof(double), 16);
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) return e;
+    owned.push_back(p);
+    bytes += b;
+    *ptr = static_cast<double *>(p);
+    return hipSuccess;
+  };
+  const int64_t N = h.ndofs;
+  const int Q = h.p + 1;
+  const int nq = h.dim == 3 ? Q * Q * Q : Q * Q, QF = h.dim == 3 ? Q * Q : Q;
+  const bool dg = h.method != LOR_CG;
+  HIPCHK(get(&w.r, N));
+  HIPCHK(get(&w.z, N));
+  HIPCHK(get(&w.p, N));
+  HIPCHK(get(&w.q, N));
+  HIPCHK(get(&w.rold, N));
+  HIPCHK(get(&w.tmp, N));
+  HIPCHK(get(&w.scal, S_COUNT));
+  HIPCHK(get(&w.part, h.npart));
+  HIPCHK(get(&w.part2, h.npart));
+  if (h.nc > 0) {
+    HIPCHK(get(&w.rc, h.nc));
+    HIPCHK(get(&w.xc, h.nc));
+  }
+  if (!dg && apply_cg_uses_skeleton(h.md)) HIPCHK(get(&w.yE, size_t(h.nel) * nq));
+  if (dg) {
+    HIPCHK(get(&w.fo, size_t(h.nfaces) * 8 * QF));
+    HIPCHK(get(&w.rL, size_t(h.ncg)));
+    HIPCHK(get(&w.zL, size_t(h.ncg)));
+  }
+  HIPCHK(hipHostMalloc((void **)&w.h_scal, S_COUNT * sizeof(double), 0));
+  return LOR_OK;
+}
+
 // Records an event pair around a launch when timing is on.
 struct Span {
   lor_handle *h;
@@ -517,7 +552,7 @@ struct Span {
   hipStream_t st;
   hipEvent_t a = nullptr;
   Span(lor_handle *hh, int w, hipStream_t s) : h(hh), which(w), st(s) {
-    if (h->timing && (a = h->next_event())) (void)hipEventRecord(a, st);
+    if (h->timing && !h->capturing && (a = h->next_event())) (void)hipEventRecord(a, st);
   }
   ~Span() {
     if (!a) return;
@@ -527,12 +562,13 @@ struct Span {
 };
 
 // Conforming Schwarz preconditioner on L-vectors (eq. as).
-int apply_P_cg(lor_handle *h, const double *r, double *z, const double *flag, hipStream_t st) {
+int apply_P_cg(lor_handle *h, Work &w, const double *r, double *z, const double *flag,
+               hipStream_t st) {
   if (h->nc > 0) {
     Span sp(h, LOR_T_COARSE, st);
-    HIPCHK(launch_coarse_restrict(h->md, h->d_gllx, r, h->d_rc, st));
-    HIPCHK(launch_gemv(h->nc, h->d_A0inv, h->d_rc, h->d_xc, flag, st));
-    HIPCHK(launch_coarse_prolong(h->md, h->d_gllx, h->d_xc, z, flag, st));
+    HIPCHK(launch_coarse_restrict(h->md, h->d_gllx, r, w.rc, st));
+    HIPCHK(launch_gemv(h->nc, h->d_A0inv, w.rc, w.xc, flag, st));
+    HIPCHK(launch_coarse_prolong(h->md, h->d_gllx, w.xc, z, flag, st));
   } else {
     HIPCHK(launch_fill(z, h->ncg, 0.0, st));
   }
@@ -543,22 +579,113 @@ int apply_P_cg(lor_handle *h, const double *r, double *z, const double *flag, hi
 
 // CG: eq. as.  DG: eq. dg-as, z = D_B^-1 r on element-boundary nodes plus
 // E B E^T r.
-int apply_P_impl(lor_handle *h, const double *r, double *z, const double *flag, hipStream_t st) {
-  if (h->method == LOR_CG) return apply_P_cg(h, r, z, flag, st);
-  HIPCHK(launch_dg_restrict(h->md, r, h->d_rL, flag, st));
-  int rc = apply_P_cg(h, h->d_rL, h->d_zL, flag, st);
+int apply_P_impl(lor_handle *h, Work &w, const double *r, double *z, const double *flag,
+                 hipStream_t st) {
+  if (h->method == LOR_CG) return apply_P_cg(h, w, r, z, flag, st);
+  HIPCHK(launch_dg_restrict(h->md, r, w.rL, flag, st));
+  int rc = apply_P_cg(h, w, w.rL, w.zL, flag, st);
   if (rc != LOR_OK) return rc;
-  HIPCHK(launch_dg_prolong_jacobi(h->md, r, h->d_dinv, h->d_zL, z, flag, st));
+  HIPCHK(launch_dg_prolong_jacobi(h->md, r, h->d_dinv, w.zL, z, flag, st));
   return LOR_OK;
 }
 
-int apply_A_impl(lor_handle *h, const double *x, double *y, double *partials, const double *flag,
-                 hipStream_t st) {
+int apply_A_impl(lor_handle *h, Work &w, const double *x, double *y, double *partials,
+                 const double *flag, hipStream_t st) {
   Span sp(h, LOR_T_APPLY_A, st);
-  if (h->method != LOR_CG) HIPCHK(launch_dg_face(h->md, h->d_D, h->d_fg, x, h->d_fo, flag, st));
+  if (h->method != LOR_CG) HIPCHK(launch_dg_face(h->md, h->d_D, h->d_fg, x, w.fo, flag, st));
   HIPCHK(launch_apply_cg(h->md, h->d_G, h->d_D, x, y, partials, flag, st,
-                         h->method != LOR_CG ? h->d_fo : nullptr, h->d_yE));
+                         h->method != LOR_CG ? w.fo : nullptr, w.yE));
   return LOR_OK;
+}
+
+constexpr int kChunk = 8;         // iterations between host checks / per captured graph
+constexpr int kBatchStreams = 4;  // worker streams of a batched solve (HIP's hardware queues)
+
+// Enqueues x = 0, r = b, z = B r, p = z, rho = r.z and the scalars of a new
+// solve (no memset nodes, so that the sequence can be captured).
+int pcg_init(lor_handle *h, Work &w, const double *b, double *x, double rtol, int maxit,
+             hipStream_t st) {
+  const int64_t N = h->ndofs;
+  double *s = w.scal;
+  HIPCHK(launch_fill(x, N, 0.0, st));
+  HIPCHK(launch_copy(w.r, b, N, st));
+  HIPCHK(launch_fill(s, S_COUNT, 0.0, st));
+  HIPCHK(launch_fill(s + S_TOL2, 1, rtol * rtol, st));
+  HIPCHK(launch_fill(s + S_MAXIT, 1, double(maxit), st));
+  const int nbv = red_blocks(N);
+  HIPCHK(launch_dot_partials(b, b, N, w.part, nullptr, st));
+  HIPCHK(launch_finalize(s, w.part, nbv, FIN_BB, nullptr, st));
+  int rc = apply_P_impl(h, w, w.r, w.z, s, st);
+  if (rc != LOR_OK) return rc;
+  HIPCHK(launch_dot_partials(w.r, w.z, N, w.part, s, st));
+  HIPCHK(launch_finalize(s, w.part, nbv, FIN_RHO, nullptr, st));
+  HIPCHK(launch_copy(w.p, w.z, N, st));
+  HIPCHK(launch_fill(w.q, N, 0.0, st));
+  return LOR_OK;
+}
+
+// Enqueues `count` (flexible) CG iterations; every kernel returns at once
+// after the device-side convergence flag is set, so the sequence can be
+// replayed as a graph until the flag is seen on the host.
+int pcg_iterations(lor_handle *h, Work &w, double *x, int count, hipStream_t st) {
+  const int64_t N = h->ndofs;
+  double *s = w.scal;
+  const bool fcg = h->opt.flexible != 0 || h->opt.precision == LOR_PREC_MIXED;
+  // the operator writes q completely (DG, or CG through the skeleton gather);
+  // otherwise q is accumulated atomically and must be cleared each iteration
+  const bool zero_q = h->method == LOR_CG && !apply_cg_uses_skeleton(h->md);
+  const int nba = apply_cg_blocks(h->md, h->method != LOR_CG);
+  const int nbv = red_blocks(N);
+  for (int i = 0; i < count; ++i) {
+    int rc = apply_A_impl(h, w, w.p, w.q, w.part, s, st);
+    if (rc != LOR_OK) return rc;
+    HIPCHK(launch_finalize(s, w.part, nba, FIN_PQ, nullptr, st));
+    HIPCHK(launch_cg_update(x, w.r, fcg ? w.rold : nullptr, w.p, w.q, N, s, w.part, st));
+    HIPCHK(launch_finalize(s, w.part, nbv, FIN_RR, nullptr, st));
+    rc = apply_P_impl(h, w, w.r, w.z, s, st);
+    if (rc != LOR_OK) return rc;
+    HIPCHK(launch_dot_partials(w.r, w.z, N, w.part, s, st));
+    if (fcg) HIPCHK(launch_dot_partials(w.z, w.rold, N, w.part2, s, st));
+    HIPCHK(launch_finalize(s, w.part, nbv, fcg ? FIN_FCG : FIN_RHO, fcg ? w.part2 : nullptr, st));
+    HIPCHK(launch_p_update(w.p, zero_q ? w.q : nullptr, w.z, N, s, st));
+  }
+  return LOR_OK;
+}
+
+// Enqueues the true residual ||b - A x||^2 and copies the scalars to w.h_scal
+// (synchronizes the stream).
+int pcg_finish(lor_handle *h, Work &w, const double *b, const double *x, double rtol,
+               hipStream_t st) {
+  (void)rtol;
+  const int64_t N = h->ndofs;
+  const bool zero_q = h->method == LOR_CG && !apply_cg_uses_skeleton(h->md);
+  if (zero_q) HIPCHK(launch_fill(w.tmp, N, 0.0, st));
+  int rc = apply_A_impl(h, w, x, w.tmp, nullptr, nullptr, st);
+  if (rc != LOR_OK) return rc;
+  HIPCHK(launch_sub_dot(b, w.tmp, N, w.part, st));
+  HIPCHK(launch_finalize(w.scal, w.part, red_blocks(N), FIN_RRTRUE, nullptr, st));
+  HIPCHK(hipMemcpyAsync(w.h_scal, w.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return LOR_OK;
+}
+
+// Status and info from the scalars in w.h_scal.
+int pcg_status(const Work &w, double rtol, double t_solve, lor_solve_info_t *info) {
+  const double *hs = w.h_scal;
+  const double bb = hs[S_BB], rr = hs[S_RR], rt = hs[S_RRTRUE], fail = hs[S_FAIL];
+  int status = LOR_OK;
+  if (fail != 0.0)
+    status = fail == 2.0 ? LOR_EINVAL : LOR_EBREAKDOWN;
+  else if (!(rr <= rtol * rtol * bb))
+    status = LOR_ENOCONV;
+  if (info) {
+    info->iters = int(hs[S_ITERS]);
+    info->status = status;
+    info->rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    info->rel_res_true = bb > 0 ? std::sqrt(rt / bb) : 0.0;
+    info->t_solve = t_solve;
+  }
+  return status;
 }
 
 }  // namespace
@@ -628,6 +755,8 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const l
   hipStream_t st = static_cast<hipStream_t>(stream);
   int rc = setup_impl(*h, st);
   if (rc != LOR_OK) return rc;
+  rc = work_alloc(*h, h->w, h->allocs, h->bytes);
+  if (rc != LOR_OK) return rc;
   *out = h.release();
   return LOR_OK;
 }
@@ -685,13 +814,13 @@ int lor_apply_A(lor_handle_t *h, const double *x_dev, double *y_dev, void *strea
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (h->method == LOR_CG && !apply_cg_uses_skeleton(h->md))
     HIPCHK(hipMemsetAsync(y_dev, 0, h->ndofs * sizeof(double), st));
-  return apply_A_impl(h, x_dev, y_dev, nullptr, nullptr, st);
+  return apply_A_impl(h, h->w, x_dev, y_dev, nullptr, nullptr, st);
 }
 
 int lor_apply_P(lor_handle_t *h, const double *r_dev, double *z_dev, void *stream) {
   if (!h || !r_dev || !z_dev || r_dev == z_dev) return LOR_EINVAL;
   if (!h->has_prec) return LOR_ESTATE;
-  return apply_P_impl(h, r_dev, z_dev, nullptr, static_cast<hipStream_t>(stream));
+  return apply_P_impl(h, h->w, r_dev, z_dev, nullptr, static_cast<hipStream_t>(stream));
 }
 
 int lor_pcg_solve(lor_handle_t *h, const double *b, double *x, double rtol, int maxit,
@@ -699,79 +828,150 @@ int lor_pcg_solve(lor_handle_t *h, const double *b, double *x, double rtol, int 
   if (!h || !b || !x || b == x || !(rtol >= 0.0) || maxit < 0) return LOR_EINVAL;
   if (!h->has_prec) return LOR_ESTATE;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int64_t N = h->ndofs;
-  const bool fcg = h->opt.flexible != 0 || h->opt.precision == LOR_PREC_MIXED;
-  double *s = h->d_scal;
+  Work &w = h->w;
   HIPCHK(hipEventRecord(h->ev0, st));
-  // x = 0, r = b, tol^2
-  HIPCHK(hipMemsetAsync(x, 0, N * sizeof(double), st));
-  HIPCHK(launch_copy(h->d_r, b, N, st));
-  HIPCHK(launch_fill(s, S_COUNT, 0.0, st));
-  HIPCHK(launch_fill(s + S_TOL2, 1, rtol * rtol, st));
-  const int nbv = red_blocks(N);
-  HIPCHK(launch_dot_partials(b, b, N, h->d_part, nullptr, st));
-  HIPCHK(launch_finalize(s, h->d_part, nbv, FIN_BB, 0, nullptr, st));
-  int rc = apply_P_impl(h, h->d_r, h->d_z, s, st);
+  int rc = pcg_init(h, w, b, x, rtol, maxit, st);
   if (rc != LOR_OK) return rc;
-  HIPCHK(launch_dot_partials(h->d_r, h->d_z, N, h->d_part, s, st));
-  HIPCHK(launch_finalize(s, h->d_part, nbv, FIN_RHO, 0, nullptr, st));
-  HIPCHK(launch_copy(h->d_p, h->d_z, N, st));
-  HIPCHK(hipMemsetAsync(h->d_q, 0, N * sizeof(double), st));
-  // the operator writes q completely (DG, or CG through the skeleton gather);
-  // otherwise q is accumulated atomically and must be cleared each iteration
-  const bool zero_q = h->method == LOR_CG && !apply_cg_uses_skeleton(h->md);
-  const int nba = apply_cg_blocks(h->md, h->method != LOR_CG);
-  const int chunk = 8;
   int it = 0;
-  bool done = false;
-  while (!done && it < maxit) {
-    const int upto = std::min(maxit, it + chunk);
-    for (; it < upto; ++it) {
-      rc = apply_A_impl(h, h->d_p, h->d_q, h->d_part, s, st);
-      if (rc != LOR_OK) return rc;
-      HIPCHK(launch_finalize(s, h->d_part, nba, FIN_PQ, it + 1, nullptr, st));
-      HIPCHK(launch_cg_update(x, h->d_r, fcg ? h->d_rold : nullptr, h->d_p, h->d_q, N, s, h->d_part, st));
-      HIPCHK(launch_finalize(s, h->d_part, nbv, FIN_RR, it + 1, nullptr, st));
-      rc = apply_P_impl(h, h->d_r, h->d_z, s, st);
-      if (rc != LOR_OK) return rc;
-      HIPCHK(launch_dot_partials(h->d_r, h->d_z, N, h->d_part, s, st));
-      if (fcg) HIPCHK(launch_dot_partials(h->d_z, h->d_rold, N, h->d_part2, s, st));
-      HIPCHK(launch_finalize(s, h->d_part, nbv, fcg ? FIN_FCG : FIN_RHO, it + 1,
-                             fcg ? h->d_part2 : nullptr, st));
-      HIPCHK(launch_p_update(h->d_p, zero_q ? h->d_q : nullptr, h->d_z, N, s, st));
-    }
-    HIPCHK(hipMemcpyAsync(h->h_scal, s, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+  bool done = maxit == 0;
+  while (!done) {
+    const int k = std::min(kChunk, maxit - it);
+    rc = pcg_iterations(h, w, x, k, st);
+    if (rc != LOR_OK) return rc;
+    it += k;
+    HIPCHK(hipMemcpyAsync(w.h_scal, w.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    done = h->h_scal[S_DONE] != 0.0;
+    done = w.h_scal[S_DONE] != 0.0 || it >= maxit;
   }
   HIPCHK(hipEventRecord(h->ev1, st));
-  // true residual ||b - A x|| (stream-ordered, after the timed region)
-  if (zero_q) HIPCHK(hipMemsetAsync(h->d_tmp, 0, N * sizeof(double), st));
-  rc = apply_A_impl(h, x, h->d_tmp, nullptr, nullptr, st);
+  rc = pcg_finish(h, w, b, x, rtol, st);
   if (rc != LOR_OK) return rc;
-  HIPCHK(launch_sub_dot(b, h->d_tmp, N, h->d_part, st));
-  HIPCHK(launch_finalize(s, h->d_part, nbv, FIN_RRTRUE, 0, nullptr, st));
-  HIPCHK(hipMemcpyAsync(h->h_scal, s, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  const double bb = h->h_scal[S_BB];
-  const double rr = h->h_scal[S_RR];
-  const double rt = h->h_scal[S_RRTRUE];
-  const int iters = int(h->h_scal[S_ITERS]);
-  const double fail = h->h_scal[S_FAIL];
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-  int status = LOR_OK;
-  if (fail != 0.0)
-    status = fail == 2.0 ? LOR_EINVAL : LOR_EBREAKDOWN;
-  else if (!h->h_scal[S_DONE])
-    status = LOR_ENOCONV;
-  if (info) {
-    info->iters = iters;
-    info->status = status;
-    info->rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
-    info->rel_res_true = bb > 0 ? std::sqrt(rt / bb) : 0.0;
-    info->t_solve = ms * 1e-3;
+  return pcg_status(w, rtol, ms * 1e-3, info);
+}
+
+int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const double *const *b,
+                        double *const *x, double rtol, int maxit, lor_solve_info_t *info,
+                        void *stream) {
+  if (!hs || !b || !x || nprob < 1 || nrhs < 1 || !(rtol >= 0.0) || maxit < 0) return LOR_EINVAL;
+  const int npair = nprob * nrhs;
+  for (int i = 0; i < nprob; ++i) {
+    if (!hs[i]) return LOR_EINVAL;
+    if (!hs[i]->has_prec) return LOR_ESTATE;
   }
+  for (int k = 0; k < npair; ++k)
+    if (!b[k] || !x[k] || b[k] == x[k]) return LOR_EINVAL;
+  hipStream_t caller = static_cast<hipStream_t>(stream);
+  struct Pair {
+    lor_handle *h = nullptr;
+    Work w;
+    hipStream_t st = nullptr;
+    hipGraphExec_t chunk = nullptr;
+    int it = 0;
+    bool done = false;
+  };
+  std::vector<Pair> pairs(npair);
+  std::vector<void *> owned;
+  std::vector<hipStream_t> streams;
+  hipEvent_t start = nullptr, stop = nullptr;
+  size_t bytes = 0;
+  int rc = LOR_OK;
+  // everything allocated here is released on every exit path
+  auto cleanup = [&]() {
+    for (Pair &q : pairs) {
+      if (q.chunk) (void)hipGraphExecDestroy(q.chunk);
+      if (q.w.h_scal) (void)hipHostFree(q.w.h_scal);
+    }
+    for (hipStream_t t : streams) (void)hipStreamDestroy(t);
+    for (void *p : owned) (void)hipFree(p);
+    if (start) (void)hipEventDestroy(start);
+    if (stop) (void)hipEventDestroy(stop);
+    for (int i = 0; i < nprob; ++i) hs[i]->capturing = false;
+  };
+  auto fail = [&](int code) {
+    cleanup();
+    return code;
+  };
+#define BCHK(x)                                              \
+  do {                                                       \
+    hipError_t e_ = (x);                                     \
+    if (e_ != hipSuccess) return fail(hip_fail(e_, #x, __LINE__)); \
+  } while (0)
+  const int ns = std::min(kBatchStreams, npair);
+  for (int i = 0; i < ns; ++i) {
+    hipStream_t t = nullptr;
+    BCHK(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));  // default priority
+    streams.push_back(t);
+  }
+  BCHK(hipEventCreate(&start));
+  BCHK(hipEventCreate(&stop));
+  // the caller's stream orders the inputs: every worker stream waits for it
+  BCHK(hipEventRecord(start, caller));
+  for (hipStream_t t : streams) BCHK(hipStreamWaitEvent(t, start, 0));
+  for (int k = 0; k < npair; ++k) {
+    Pair &q = pairs[k];
+    q.h = hs[k / nrhs];
+    q.st = streams[k % ns];
+    rc = work_alloc(*q.h, q.w, owned, bytes);
+    if (rc != LOR_OK) return fail(rc);
+  }
+  // one captured chunk of iterations per pair (kernels become no-ops once the
+  // pair has converged, so the chunk is replayed until its flag is set)
+  for (int k = 0; k < npair; ++k) {
+    Pair &q = pairs[k];
+    hipGraph_t g = nullptr;
+    q.h->capturing = true;
+    BCHK(hipStreamBeginCapture(q.st, hipStreamCaptureModeThreadLocal));
+    rc = pcg_iterations(q.h, q.w, x[k], kChunk, q.st);
+    hipError_t e = hipStreamEndCapture(q.st, &g);
+    q.h->capturing = false;
+    if (rc != LOR_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(rc);
+    }
+    BCHK(e);
+    e = hipGraphInstantiate(&q.chunk, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    BCHK(e);
+  }
+  for (int k = 0; k < npair; ++k) {
+    Pair &q = pairs[k];
+    rc = pcg_init(q.h, q.w, b[k], x[k], rtol, maxit, q.st);
+    if (rc != LOR_OK) return fail(rc);
+    q.done = maxit == 0;
+  }
+  for (;;) {
+    bool any = false;
+    for (Pair &q : pairs) {
+      if (q.done) continue;
+      any = true;
+      BCHK(hipGraphLaunch(q.chunk, q.st));
+      BCHK(hipMemcpyAsync(q.w.h_scal, q.w.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                          q.st));
+      q.it += kChunk;
+    }
+    if (!any) break;
+    for (hipStream_t t : streams) BCHK(hipStreamSynchronize(t));
+    for (Pair &q : pairs)
+      if (!q.done) q.done = q.w.h_scal[S_DONE] != 0.0 || q.it >= maxit;
+  }
+  // every worker stream has been synchronized: stop marks the end of the
+  // iterations of all pairs
+  BCHK(hipEventRecord(stop, streams[0]));
+  BCHK(hipEventSynchronize(stop));
+  float ms = 0.f;
+  BCHK(hipEventElapsedTime(&ms, start, stop));
+  int status = LOR_OK;
+  for (int k = 0; k < npair; ++k) {
+    Pair &q = pairs[k];
+    rc = pcg_finish(q.h, q.w, b[k], x[k], rtol, q.st);
+    if (rc != LOR_OK) return fail(rc);
+    const int sk = pcg_status(q.w, rtol, ms * 1e-3, info ? info + k : nullptr);
+    if (status == LOR_OK) status = sk;
+  }
+#undef BCHK
+  cleanup();
   return status;
 }
 

@@ -174,6 +174,9 @@ hipError_t launch_gemv(int n, const double *A, const double *x, double *y, const
                        hipStream_t st);
 hipError_t launch_gauss_jordan(int n, double *A, double *rowbuf, double *colbuf, int *bad,
                                hipStream_t st);
+// Raises the patch kernel's dynamic LDS limit (call once before launches,
+// outside any stream capture).
+hipError_t prepare_patch_vcycle(const PatchArgs &pa);
 hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r, double *z,
                                const double *flag, hipStream_t st);
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t st);
@@ -185,13 +188,13 @@ hipError_t launch_sym_stencil(const double *soa, int64_t npts, int dim, void *ou
 
 // Krylov helpers.  Scalars live in a small device array.
 enum Scal { S_RHO = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_TOL2, S_DONE, S_ITERS, S_FAIL,
-            S_RRTRUE, S_COUNT };
+            S_RRTRUE, S_MAXIT, S_COUNT };
 enum FinOp { FIN_PQ = 0, FIN_RR = 1, FIN_RHO = 2, FIN_BB = 3, FIN_FCG = 4, FIN_RRTRUE = 5 };
 constexpr int kRedBlocks = 1024;  // most blocks of a two-stage reduction
 int red_blocks(int64_t n);
 hipError_t launch_dot_partials(const double *a, const double *b, int64_t n, double *partials,
                                const double *flag, hipStream_t st);
-hipError_t launch_finalize(double *scal, const double *partials, int count, int which, int iter,
+hipError_t launch_finalize(double *scal, const double *partials, int count, int which,
                            const double *partials2, hipStream_t st);
 hipError_t launch_cg_update(double *x, double *r, double *rold, const double *p, const double *q,
                             int64_t n, const double *scal, double *partials, hipStream_t st);

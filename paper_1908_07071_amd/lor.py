@@ -29,7 +29,7 @@ EXPORTED = [
     "lor_default_options", "lor_error_string", "lor_setup", "lor_ndofs", "lor_device_bytes",
     "lor_dof_coords", "lor_assemble_rhs", "lor_apply_A", "lor_apply_P", "lor_pcg_solve",
     "lor_export_maps", "lor_export_stencils", "lor_gll", "lor_mdf_order", "lor_free",
-    "lor_last_error_detail", "lor_timing", "lor_timing_read",
+    "lor_last_error_detail", "lor_timing", "lor_timing_read", "lor_pcg_solve_batch",
 ]
 LOR_T_APPLY_A, LOR_T_PATCH, LOR_T_COARSE = 0, 1, 2
 
@@ -85,6 +85,8 @@ def _load():
         "lor_last_error_detail": (C.c_char_p, []),
         "lor_timing": (C.c_int, [vp, C.c_int]),
         "lor_timing_read": (C.c_int, [vp, C.c_int, dp, i64p]),
+        "lor_pcg_solve_batch": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int, C.POINTER(vp), C.POINTER(vp),
+                                          C.c_double, C.c_int, C.POINTER(lor_solve_info_t), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -216,6 +218,30 @@ def lor_pcg_solve(h, b, x, rtol: float = 1e-8, maxit: int = 1000, stream=None, c
     if check and rc not in (LOR_OK,):
         raise LorError(rc, "lor_pcg_solve")
     return info
+
+
+def lor_pcg_solve_batch(handles, b, x, rtol: float = 1e-8, maxit: int = 1000, stream=None,
+                        check: bool = True):
+    """Batched solve: ``handles`` has one entry per problem; ``b`` and ``x`` are
+    lists of nprob * nrhs device tensors, pair k = i * nrhs + j using
+    handles[i].  Returns the list of per-pair solve infos."""
+    nprob = len(handles)
+    if nprob == 0 or len(b) != len(x) or len(b) % nprob:
+        raise ValueError("b and x need nprob * nrhs tensors")
+    nrhs = len(b) // nprob
+    for k in range(len(b)):
+        n = lor_ndofs(handles[k // nrhs])
+        if b[k].numel() != n or x[k].numel() != n:
+            raise ValueError(f"pair {k}: vectors must have {n} entries")
+    hs = (C.c_void_p * nprob)(*[h.value for h in handles])
+    bp = (C.c_void_p * len(b))(*[_dev(t, "b").value for t in b])
+    xp = (C.c_void_p * len(x))(*[_dev(t, "x").value for t in x])
+    infos = (lor_solve_info_t * len(b))()
+    rc = _lib.lor_pcg_solve_batch(hs, nprob, nrhs, bp, xp, float(rtol), int(maxit), infos,
+                                  _stream(stream))
+    if check and rc != LOR_OK:
+        raise LorError(rc, "lor_pcg_solve_batch")
+    return list(infos)
 
 
 def lor_export_maps(h, which: int) -> np.ndarray:

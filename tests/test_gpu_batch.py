@@ -1,0 +1,145 @@
+"""Batched solves (many problems x right-hand sides, graph-captured iteration
+chunks replayed on several streams) against the single-solve path and the
+oracle.
+
+Each pair of a batch runs the same kernels in the same order as
+lor_pcg_solve; the patch corrections are scattered with float64 atomics, so
+two solves agree to rounding (not bit for bit) and in their iteration count
+within one.  Every captured chunk is replayed many times with host
+synchronization in between, which the comparison covers replay by replay.
+"""
+import numpy as np
+import pytest
+
+from oracle import highorder as HO, krylov, mesh as M, schwarz as S
+from paper_1908_07071_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+PROBLEMS = [
+    # dim, n, p, perturb, seed, method, eta, precision
+    (3, (2, 2, 2), 3, 0.1, 41, "cg", 0.0, "fp64"),
+    (2, (4, 3), 4, 0.1, 42, "cg", 0.0, "mixed"),
+    (3, (3, 2, 2), 6, 0.1, 43, "cg", 0.0, "mixed"),
+    (3, (2, 2, 1), 2, 0.1, 44, "ip", 1.5 * 9, "fp64"),
+    (2, (3, 3), 5, 0.0, 45, "br2", 10.0, "mixed"),
+]
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "HIP device required"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1908_07071_amd import lor
+    return lor
+
+
+def _setup(L, prob):
+    dim, n, p, pert, seed, method, eta, prec = prob
+    V = inputs.structured_vertices(dim, list(n), pert, seed=seed)
+    opt = L.lor_default_options()
+    opt.precision = L.LOR_PREC_MIXED if prec == "mixed" else L.LOR_PREC_FP64
+    code = {"cg": L.LOR_CG, "ip": L.LOR_IP, "br2": L.LOR_BR2}[method]
+    return L.lor_setup(dim, list(n), V, p, method=code, penalty=eta, options=opt)
+
+
+def test_batch_bitexact_vs_single_solves(L, torch_dev):
+    torch = torch_dev
+    nrhs = 3
+    hs = [_setup(L, pr) for pr in PROBLEMS]
+    try:
+        bs, xs = [], []
+        for i, h in enumerate(hs):
+            N = L.lor_ndofs(h)
+            for j in range(nrhs):
+                bs.append(torch.tensor(inputs.gaussian_rhs(N, 1000 * i + j), device="cuda"))
+                xs.append(torch.full((N,), 7.0, dtype=torch.float64, device="cuda"))
+        print("batch of", len(bs), "pairs", flush=True)
+        infos = L.lor_pcg_solve_batch(hs, bs, xs, rtol=1e-9, maxit=600)
+        torch.cuda.synchronize()
+        for k, info in enumerate(infos):
+            h = hs[k // nrhs]
+            x1 = torch.zeros_like(bs[k])
+            ref = L.lor_pcg_solve(h, bs[k], x1, rtol=1e-9, maxit=600)
+            assert info.status == L.LOR_OK and abs(info.iters - ref.iters) <= 1, (k, info.iters, ref.iters)
+            err = (xs[k] - x1).abs().max().item() / x1.abs().max().item()
+            assert err <= 1e-8, (k, err)
+            assert info.rel_res <= 1e-9 and info.rel_res_true <= 1.05e-9
+    finally:
+        for h in hs:
+            L.lor_free(h)
+
+
+def test_batch_matches_oracle(L, torch_dev):
+    """One CG and one DG problem, two right-hand sides each, against the
+    oracle's PCG (iterations) and the assembled operator (residual)."""
+    torch = torch_dev
+    probs = [PROBLEMS[0], PROBLEMS[3]]
+    hs = [_setup(L, pr) for pr in probs]
+    try:
+        bs, xs, refs = [], [], []
+        for i, (h, pr) in enumerate(zip(hs, probs)):
+            dim, n, p, pert, seed, method, eta, prec = pr
+            mesh = M.make_mesh(dim, list(n), inputs.structured_vertices(dim, list(n), pert, seed=seed))
+            if method == "cg":
+                A = HO.cg_stiffness(mesh, p)
+                B = S.SchwarzLOR(mesh, p)
+            else:
+                A = HO.dg_operator(mesh, p, method, eta)
+                B = S.SchwarzDG(mesh, p, A)
+            for j in range(2):
+                b = inputs.gaussian_rhs(A.shape[0], 77 + j)
+                _, it, _ = krylov.pcg(A, b, B.apply, tol=1e-10)
+                refs.append((A, b, it))
+                bs.append(torch.tensor(b, device="cuda"))
+                xs.append(torch.zeros_like(bs[-1]))
+        infos = L.lor_pcg_solve_batch(hs, bs, xs, rtol=1e-10, maxit=500)
+        for k, (A, b, it) in enumerate(refs):
+            assert abs(infos[k].iters - it) <= 1, (k, infos[k].iters, it)
+            x = xs[k].cpu().numpy()
+            assert np.linalg.norm(b - A @ x) <= 1.05e-10 * np.linalg.norm(b)
+    finally:
+        for h in hs:
+            L.lor_free(h)
+
+
+def test_batch_maxit_and_errors(L, torch_dev):
+    torch = torch_dev
+    hs = [_setup(L, PROBLEMS[0]), _setup(L, PROBLEMS[1])]
+    try:
+        bs, xs = [], []
+        for i, h in enumerate(hs):
+            N = L.lor_ndofs(h)
+            bs.append(torch.tensor(inputs.gaussian_rhs(N, 5 + i), device="cuda"))
+            xs.append(torch.zeros_like(bs[-1]))
+        # maxit not a multiple of the chunk: stops exactly there
+        infos = L.lor_pcg_solve_batch(hs, bs, xs, rtol=1e-14, maxit=5, check=False)
+        for k, info in enumerate(infos):
+            assert info.status == L.LOR_ENOCONV and info.iters == 5
+            x1 = torch.zeros_like(bs[k])
+            ref = L.lor_pcg_solve(hs[k], bs[k], x1, rtol=1e-14, maxit=5, check=False)
+            assert ref.iters == 5
+            err = (xs[k] - x1).abs().max().item() / x1.abs().max().item()
+            assert err <= 1e-10, (k, err)
+        with pytest.raises(ValueError):
+            L.lor_pcg_solve_batch(hs, bs[:1], xs[:1])
+        # a handle without preconditioner (pure Neumann) is refused
+        V = inputs.structured_vertices(2, [2, 2], 0.0, seed=1)
+        hn = L.lor_setup(2, [2, 2], V, 2, bc=L.LOR_BC_NEUMANN)
+        try:
+            N = L.lor_ndofs(hn)
+            b = torch.ones(N, dtype=torch.float64, device="cuda")
+            x = torch.zeros_like(b)
+            with pytest.raises(L.LorError) as e:
+                L.lor_pcg_solve_batch([hn], [b], [x])
+            assert e.value.code == L.LOR_ESTATE
+        finally:
+            L.lor_free(hn)
+    finally:
+        for h in hs:
+            L.lor_free(h)
