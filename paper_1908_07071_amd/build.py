@@ -29,6 +29,7 @@ SOURCES = [
     ("k_schwarz.hip", []),
     ("k_krylov.hip", []),
     ("k_dg.hip", []),
+    ("coarse_inverse.cpp", []),
 ]
 
 ARCH = "gfx950"
@@ -68,7 +69,10 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(*s), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs, "-lpthread"]
+    # rocBLAS: only its plain float64 GEMM (trailing updates of the blocked
+    # Gauss-Jordan inverse of the coarse matrix at set-up)
+    cmd = [_hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs, "-lpthread",
+           "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

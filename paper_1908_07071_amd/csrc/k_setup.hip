@@ -378,30 +378,46 @@ __global__ void k_gemv(int n, const double *__restrict__ A, const double *__rest
 }
 
 // In-place Gauss-Jordan inversion of an SPD matrix, step k (no pivoting).
-__global__ void k_gj_save(int n, int k, const double *__restrict__ A, double *rowbuf,
-                          double *colbuf, int *bad) {
-  const double piv = A[int64_t(k) * n + k];
-  if (!(piv > 0.0)) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) atomicOr(bad, 1);
-  }
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
-    rowbuf[j] = j == k ? 1.0 / piv : A[int64_t(k) * n + j] / piv;
-    colbuf[j] = j == k ? 0.0 : A[int64_t(j) * n + k];
+// Scalar Gauss-Jordan inverse of one bk x bk block (bk <= 128) by one
+// workgroup: M (leading dimension ldm) -> Minv (bk x bk, dense).  The block is
+// the pivot block of an SPD matrix after earlier elimination steps, so every
+// pivot must be positive (otherwise *bad is set).
+__global__ __launch_bounds__(1024) void k_small_inverse(const double *__restrict__ M, int ldm,
+                                                        double *__restrict__ Minv, int bk, int *bad) {
+  __shared__ double rowk[128], colk[128];
+  const int tid = threadIdx.x;
+  for (int t = tid; t < bk * bk; t += blockDim.x) Minv[t] = M[int64_t(t / bk) * ldm + t % bk];
+  __syncthreads();
+  for (int k = 0; k < bk; ++k) {
+    const double piv = Minv[k * bk + k];
+    if (tid == 0 && !(piv > 0.0)) atomicOr(bad, 1);
+    for (int j = tid; j < bk; j += blockDim.x) {
+      rowk[j] = j == k ? 1.0 / piv : Minv[k * bk + j] / piv;
+      colk[j] = j == k ? 0.0 : Minv[j * bk + k];
+    }
+    __syncthreads();
+    for (int t = tid; t < bk * bk; t += blockDim.x) {
+      const int i = t / bk, j = t % bk;
+      if (i == k)
+        Minv[t] = rowk[j];
+      else if (j == k)
+        Minv[t] = -colk[i] * rowk[k];
+      else
+        Minv[t] -= colk[i] * rowk[j];
+    }
+    __syncthreads();
   }
 }
 
-__global__ void k_gj_update(int n, int k, double *__restrict__ A, const double *__restrict__ rowbuf,
-                            const double *__restrict__ colbuf) {
-  const int64_t tot = int64_t(n) * n;
+// dst[i][j] = scale * src[i][j] for a rows x cols block (row-major, leading
+// dimensions lds / ldd).
+__global__ void k_copy_block(const double *__restrict__ src, int64_t lds, double *__restrict__ dst,
+                             int64_t ldd, int rows, int cols, double scale) {
+  const int64_t tot = int64_t(rows) * cols;
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < tot;
        t += int64_t(gridDim.x) * blockDim.x) {
-    const int i = int(t / n), j = int(t % n);
-    if (i == k)
-      A[t] = rowbuf[j];
-    else if (j == k)
-      A[t] = -colbuf[i] * rowbuf[k];
-    else
-      A[t] -= colbuf[i] * rowbuf[j];
+    const int64_t i = t / cols, j = t % cols;
+    dst[i * ldd + j] = scale * src[i * lds + j];
   }
 }
 
@@ -507,13 +523,17 @@ hipError_t launch_gemv(int n, const double *A, const double *x, double *y, const
   return hipGetLastError();
 }
 
-hipError_t launch_gauss_jordan(int n, double *A, double *rowbuf, double *colbuf, int *bad,
-                               hipStream_t st) {
-  const int64_t tot = int64_t(n) * n;
-  for (int k = 0; k < n; ++k) {
-    k_gj_save<<<grid_for(n, 256), 256, 0, st>>>(n, k, A, rowbuf, colbuf, bad);
-    k_gj_update<<<grid_for(tot, 256), 256, 0, st>>>(n, k, A, rowbuf, colbuf);
-  }
+hipError_t launch_small_inverse(const double *M, int ldm, double *Minv, int bk, int *bad,
+                                hipStream_t st) {
+  if (bk < 1 || bk > 128) return hipErrorInvalidValue;
+  k_small_inverse<<<1, 1024, 0, st>>>(M, ldm, Minv, bk, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_block(const double *src, int64_t lds, double *dst, int64_t ldd, int rows,
+                             int cols, double scale, hipStream_t st) {
+  k_copy_block<<<grid_for(int64_t(rows) * cols, 256), 256, 0, st>>>(src, lds, dst, ldd, rows, cols,
+                                                                   scale);
   return hipGetLastError();
 }
 

@@ -274,17 +274,7 @@ int build_coarse(lor_handle &h, const std::vector<double> &st0, hipStream_t st) 
   for (auto &th : pool) th.join();
   HIPCHK(h.alloc(&h.d_A0inv, size_t(h.nc) * h.nc));
   HIPCHK(hipMemcpyAsync(h.d_A0inv, A0.data(), A0.size() * sizeof(double), hipMemcpyHostToDevice, st));
-  double *rowbuf, *colbuf;
-  int *bad;
-  HIPCHK(h.alloc(&rowbuf, h.nc));
-  HIPCHK(h.alloc(&colbuf, h.nc));
-  HIPCHK(h.alloc(&bad, 1));
-  HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), st));
-  HIPCHK(launch_gauss_jordan(h.nc, h.d_A0inv, rowbuf, colbuf, bad, st));
-  int hb = 0;
-  HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return hb ? LOR_EPIVOT : LOR_OK;
+  return coarse_inverse(h.nc, h.d_A0inv, st);
 }
 
 int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hipStream_t st) {

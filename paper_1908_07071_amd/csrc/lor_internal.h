@@ -172,8 +172,13 @@ hipError_t launch_coarse_prolong(const MeshDims &md, const double *gllx, const d
                                  double *z, const double *flag, hipStream_t st);
 hipError_t launch_gemv(int n, const double *A, const double *x, double *y, const double *flag,
                        hipStream_t st);
-hipError_t launch_gauss_jordan(int n, double *A, double *rowbuf, double *colbuf, int *bad,
-                               hipStream_t st);
+hipError_t launch_small_inverse(const double *M, int ldm, double *Minv, int bk, int *bad,
+                                hipStream_t st);
+hipError_t launch_copy_block(const double *src, int64_t lds, double *dst, int64_t ldd, int rows,
+                             int cols, double scale, hipStream_t st);
+// In-place inverse of the dense SPD n x n matrix A (device, row-major);
+// LOR_EPIVOT if a pivot is not positive.
+int coarse_inverse(int n, double *A, hipStream_t st);
 // Raises the patch kernel's dynamic LDS limit (call once before launches,
 // outside any stream capture).
 hipError_t prepare_patch_vcycle(const PatchArgs &pa);

@@ -63,3 +63,14 @@ def gaussian_rhs(n: int, seed: int) -> np.ndarray:
 def uniform_vector(n: int, seed: int) -> np.ndarray:
     """i.i.d. U(-1,1) vector of length n (float64), used as operator input."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, n)
+
+
+def batch_problems(nprob: int = 64, seed: int = 7, nmin: int = 4, nmax: int = 24,
+                   pmin: int = 2, pmax: int = 8):
+    """Sizes of a batch of independent 3D problems: n ~ U{nmin..nmax} elements
+    per direction and p ~ U{pmin..pmax}, drawn with a seeded generator.
+    Problem i uses mesh seed 100 + i and right-hand-side seeds 1000 i + k."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(nmin, nmax + 1, size=nprob)
+    ps = rng.integers(pmin, pmax + 1, size=nprob)
+    return [(int(n), int(p), 100 + i) for i, (n, p) in enumerate(zip(ns, ps))]
