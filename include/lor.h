@@ -176,6 +176,65 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
                         double *const *x_dev, double rtol, int maxit, lor_solve_info_t *info,
                         void *stream);
 
+/* ---------------------------------------------------------------------
+ * Learned patch correction.  A small 3D convolutional network (3 layers of
+ * 3x3x3 convolutions, `channels` hidden channels, ReLU) acts on one vertex
+ * patch at a time, on the level-0 patch grid of G = 2p-1 points per
+ * direction (grid point g_d is level-0 node v_d p - p + 1 + g_d).  Input
+ * channels: the patch residual divided by its 2-norm s_j, and the mask of
+ * the patch unknowns; output: an approximation of the patch V-cycle
+ * (Section 3.3) of the normalised residual.  Trained on pairs (residual,
+ * V-cycle) that the method generates; in LOR_NN_REPLACE mode the
+ * preconditioner becomes z = coarse correction + sum_j R_j^T s_j
+ * net(R_j r / s_j) (eq. as with the network in place of the patch solves);
+ * flexible CG is required (the network is nonlinear).  3D CG handles only.
+ * Arithmetic: BF16 MFMA products with float32 accumulation, float32 master
+ * weights and Adam moments.
+ * Parameters (HOST float64 vectors of lor_nn_param_count values): layer by
+ * layer W [27 cin][cout] row-major (row k cin + c, kernel offset
+ * k = (dx+1) + 3 (dy+1) + 9 (dz+1)), then the bias [cout]; cin = 2, C, C and
+ * cout = C, C, 1.
+ * Data: X [nb][G^3][2] (float32, residual / s_j and mask), T [nb][G^3]
+ * (float32 targets), both DEVICE.  A network must not be used by two calls
+ * at once; a handle with an attached network is refused by
+ * lor_pcg_solve_batch. */
+typedef struct lor_nn lor_nn_t;
+#define LOR_NN_OFF      0   /* patch V-cycles (eq. as) */
+#define LOR_NN_REPLACE  1   /* the network stands in for every patch V-cycle */
+
+int lor_nn_param_count(int channels, int64_t *count);
+/* channels: multiple of 16, 16..64.  max_batch: patches per network pass
+ * (sizes the device buffers: about 4.5 (G^3 max_batch) (27 channels) bytes). */
+int lor_nn_create(lor_handle_t *h, int channels, const double *params_host, int max_batch,
+                  void *stream, lor_nn_t **out);
+int lor_nn_get_params(const lor_nn_t *nn, double *params_host);
+/* Number of patches J (vertex order) and grid points per direction G. */
+int lor_nn_shape(const lor_nn_t *nn, int *npatch, int *grid);
+/* Training data for the global residual r_dev (ndofs): X [J][G^3][2],
+ * T [J][G^3] and scale [J] (DEVICE outputs), from the handle's own patch
+ * V-cycles. */
+int lor_nn_patch_data(lor_nn_t *nn, const double *r_dev, float *X_dev, float *T_dev,
+                      double *scale_dev, void *stream);
+/* Y [nb][G^3] = network output (masked), nb <= max_batch. */
+int lor_nn_forward(lor_nn_t *nn, const float *X_dev, int nb, float *Y_dev, void *stream);
+/* Masked mean squared error of the batch and its gradient (HOST outputs,
+ * the parameter layout), without an update. */
+int lor_nn_gradients(lor_nn_t *nn, const float *X_dev, const float *T_dev, int nb, double *loss,
+                     double *grad_host, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the batch; *loss is
+ * the loss before the step. */
+int lor_nn_train_step(lor_nn_t *nn, const float *X_dev, const float *T_dev, int nb, double lr,
+                      double *loss, void *stream);
+/* Use nn in h's preconditioner (LOR_NN_REPLACE) or not (LOR_NN_OFF, nn may
+ * be NULL).  The network must have been created for h. */
+int lor_nn_attach(lor_handle_t *h, lor_nn_t *nn, int mode);
+int lor_nn_free(lor_nn_t *nn);
+/* The network's BF16 matrix product, exposed for tests: C[M][ldc] (float32,
+ * DEVICE) = A B with A(i,k) = A[i ai + k ak], B(k,j) = B[k bk + j bj]
+ * (bfloat16 bit patterns, DEVICE); M, N, K multiples of 16. */
+int lor_bf16_gemm(int M, int N, int K, const uint16_t *A, int64_t ai, int64_t ak,
+                  const uint16_t *B, int64_t bk, int64_t bj, float *C, int64_t ldc, void *stream);
+
 /* Integer maps for parity checks, HOST output.  If host_out is NULL only
  * *len is set.  which:
  *   LOR_MAP_LDOF          L-vector index -> flat GLL grid index

@@ -30,6 +30,8 @@ SOURCES = [
     ("k_krylov.hip", []),
     ("k_dg.hip", []),
     ("coarse_inverse.cpp", []),
+    ("k_nn.hip", []),
+    ("nn_api.cpp", []),
 ]
 
 ARCH = "gfx950"

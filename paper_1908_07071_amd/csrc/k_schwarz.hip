@@ -291,7 +291,9 @@ __device__ __forceinline__ void residual(T *R, const T *B, const T *X, const Box
 
 template <int DIM, typename T, typename ST, int W>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_patch_vcycle(PatchArgs pa, const double *__restrict__ r,
-                                                     double *__restrict__ z, const double *flag) {
+                                                     double *__restrict__ z, const double *flag,
+                                                     float *__restrict__ dense,
+                                                     const double *__restrict__ dscale) {
   if (flag && flag[S_DONE] != 0.0) return;
   extern __shared__ __align__(16) char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
@@ -461,10 +463,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     for (int i = threadIdx.x; i < fb.n; i += 64) Xk[i] += Rk[i];
     wave_sync();
   }
-  // scatter-add the correction
+  // scatter-add the correction, or (dense mode, training data of the patch
+  // network) write it divided by the patch's scale into the patch's
+  // (2p-1)^d grid: grid point g_d = level-0 node - (v_d p - p + 1)
   {
     const T *X0 = lds_vec<DIM, T>(lds, pa, v, 0, 0);
-    for (int i = threadIdx.x; i < b0.n; i += 64) unsafeAtomicAdd(z + lvec(i), double(X0[i]));
+    if (dense) {
+      const int s0 = pa.s[0], G = 2 * s0 - 1;
+      int gsz = 1;
+      for (int d = 0; d < DIM; ++d) gsz *= G;
+      const double inv = 1.0 / dscale[j];
+      for (int i = threadIdx.x; i < b0.n; i += 64) {
+        const int ix = i % b0.m[0], iy = (i / b0.m[0]) % b0.m[1], iz = i / (b0.m[0] * b0.m[1]);
+        const int gx = ix + b0.lo[0] - (v[0] * s0 - s0 + 1), gy = iy + b0.lo[1] - (v[1] * s0 - s0 + 1),
+                  gz = DIM == 3 ? iz + b0.lo[2] - (v[2] * s0 - s0 + 1) : 0;
+        dense[int64_t(j) * gsz + gx + G * (gy + G * gz)] = float(double(X0[i]) * inv);
+      }
+    } else {
+      for (int i = threadIdx.x; i < b0.n; i += 64) unsafeAtomicAdd(z + lvec(i), double(X0[i]));
+    }
   }
 }
 
@@ -480,11 +497,11 @@ hipError_t prepare_t() {
 
 template <int DIM, typename T, typename ST>
 hipError_t launch_t(const PatchArgs &pa, int npatch, const double *r, double *z, const double *flag,
-                    hipStream_t st) {
+                    float *dense, const double *dscale, hipStream_t st) {
   constexpr int W = DIM == 3 ? 26 : 8;
   const size_t lds = size_t(pa.lds_total) * sizeof(T);
   if (lds > size_t(kMaxDynLds)) return hipErrorInvalidValue;
-  k_patch_vcycle<DIM, T, ST, W><<<npatch, 64, lds, st>>>(pa, r, z, flag);
+  k_patch_vcycle<DIM, T, ST, W><<<npatch, 64, lds, st>>>(pa, r, z, flag, dense, dscale);
   return hipGetLastError();
 }
 
@@ -496,13 +513,14 @@ hipError_t prepare_patch_vcycle(const PatchArgs &pa) {
 }
 
 hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r, double *z,
-                               const double *flag, hipStream_t st) {
+                               const double *flag, hipStream_t st, float *dense,
+                               const double *dscale) {
   if (pa.fp32) {
-    if (pa.md.dim == 3) return launch_t<3, float, float>(pa, npatch, r, z, flag, st);
-    return launch_t<2, float, float>(pa, npatch, r, z, flag, st);
+    if (pa.md.dim == 3) return launch_t<3, float, float>(pa, npatch, r, z, flag, dense, dscale, st);
+    return launch_t<2, float, float>(pa, npatch, r, z, flag, dense, dscale, st);
   }
-  if (pa.md.dim == 3) return launch_t<3, double, double>(pa, npatch, r, z, flag, st);
-  return launch_t<2, double, double>(pa, npatch, r, z, flag, st);
+  if (pa.md.dim == 3) return launch_t<3, double, double>(pa, npatch, r, z, flag, dense, dscale, st);
+  return launch_t<2, double, double>(pa, npatch, r, z, flag, dense, dscale, st);
 }
 
 }  // namespace lor

@@ -12,89 +12,7 @@
 #include <thread>
 #include <vector>
 
-#include "lor_internal.h"
-
-using namespace lor;
-
-// Device workspace of one solve.  The handle holds one; a batched solve holds
-// one per (problem, right-hand side) pair so that the pairs of one problem can
-// run concurrently.
-struct Work {
-  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *rold = nullptr, *tmp = nullptr;
-  double *scal = nullptr, *part = nullptr, *part2 = nullptr;
-  double *rc = nullptr, *xc = nullptr;  // coarse-space vectors
-  double *yE = nullptr;                 // element-boundary operator results (CG skeleton path)
-  double *fo = nullptr;                 // DG face records
-  double *rL = nullptr, *zL = nullptr;  // DG: conforming vectors of E B E^T
-  double *h_scal = nullptr;             // pinned host copy of scal
-};
-
-struct lor_handle {
-  int dim = 3, n[3] = {1, 1, 1}, p = 1, method = LOR_CG, bc = LOR_BC_DIRICHLET;
-  double penalty = 0.0;
-  lor_options_t opt{};
-  MeshDims md{};
-  std::vector<double> verts, gllx, gllw, D;
-  std::vector<std::vector<int>> kept;
-  int L = 1;
-  int64_t ndofs = 0, nfine = 0, nel = 0;
-  int64_t ncg = 0;     // conforming unknowns (the L-vector of the Schwarz preconditioner)
-  int64_t nfaces = 0;  // DG faces
-  int J = 0, nc = 0;
-  // device memory (owned)
-  std::vector<void *> allocs;
-  size_t bytes = 0;
-  double *d_verts = nullptr, *d_gllx = nullptr, *d_gllw = nullptr, *d_D = nullptr;
-  double *d_coords = nullptr, *d_G = nullptr, *d_wdet = nullptr;
-  double *d_stencil[kMaxLevels] = {};
-  int64_t npts[kMaxLevels] = {};
-  char *d_fac = nullptr;
-  int64_t *d_fac_off = nullptr;
-  int64_t fac_bytes = 0;
-  XferTab *d_xfer = nullptr;
-  double *d_A0inv = nullptr;
-  double *d_fg = nullptr, *d_dinv = nullptr;
-  int npart = 0;
-  Work w;                  // workspace of lor_pcg_solve / lor_apply_*
-  bool capturing = false;  // no event timing while a graph is captured
-  PatchArgs pa{};
-  // host copies for parity export
-  std::vector<int32_t> order_all, order_off, sched_all, sched_off;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  bool has_prec = false;
-  // per-kernel event timing
-  bool timing = false;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> tspans[3];
-  hipEvent_t next_event() {
-    if (ev_used == ev_pool.size()) {
-      hipEvent_t e = nullptr;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
-      ev_pool.push_back(e);
-    }
-    return ev_pool[ev_used++];
-  }
-
-  template <class T>
-  hipError_t alloc(T **ptr, size_t count) {
-    void *p = nullptr;
-    size_t b = std::max<size_t>(count * sizeof(T), 16);
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) return e;
-    allocs.push_back(p);
-    bytes += b;
-    *ptr = static_cast<T *>(p);
-    return hipSuccess;
-  }
-  ~lor_handle() {
-    for (void *p : allocs) (void)hipFree(p);
-    if (w.h_scal) (void)hipHostFree(w.h_scal);
-    if (ev0) (void)hipEventDestroy(ev0);
-    if (ev1) (void)hipEventDestroy(ev1);
-    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-  }
-};
+#include "lor_handle.h"
 
 namespace {
 
@@ -563,6 +481,7 @@ int apply_P_cg(lor_handle *h, Work &w, const double *r, double *z, const double 
     HIPCHK(launch_fill(z, h->ncg, 0.0, st));
   }
   Span sp(h, LOR_T_PATCH, st);
+  if (h->nn && h->nn_mode == LOR_NN_REPLACE) return nn_apply_patches(h->nn, r, z, flag, st);
   HIPCHK(launch_patch_vcycle(h->pa, h->J, r, z, flag, st));
   return LOR_OK;
 }
@@ -620,7 +539,10 @@ int pcg_init(lor_handle *h, Work &w, const double *b, double *x, double rtol, in
 int pcg_iterations(lor_handle *h, Work &w, double *x, int count, hipStream_t st) {
   const int64_t N = h->ndofs;
   double *s = w.scal;
-  const bool fcg = h->opt.flexible != 0 || h->opt.precision == LOR_PREC_MIXED;
+  // flexible CG whenever the preconditioner is not a fixed SPD operator
+  // (float32 patch solves, or the nonlinear patch network)
+  const bool fcg = h->opt.flexible != 0 || h->opt.precision == LOR_PREC_MIXED ||
+                   (h->nn && h->nn_mode != LOR_NN_OFF);
   // the operator writes q completely (DG, or CG through the skeleton gather);
   // otherwise q is accumulated atomically and must be cleared each iteration
   const bool zero_q = h->method == LOR_CG && !apply_cg_uses_skeleton(h->md);
@@ -849,6 +771,7 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
   for (int i = 0; i < nprob; ++i) {
     if (!hs[i]) return LOR_EINVAL;
     if (!hs[i]->has_prec) return LOR_ESTATE;
+    if (hs[i]->nn && hs[i]->nn_mode != LOR_NN_OFF) return LOR_ESTATE;  // network buffers are shared
   }
   for (int k = 0; k < npair; ++k)
     if (!b[k] || !x[k] || b[k] == x[k]) return LOR_EINVAL;

@@ -1,0 +1,102 @@
+// Handle of the C ABI (private to the library): mesh, discretization,
+// preconditioner data and the default solve workspace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <utility>
+#include <vector>
+
+#include "lor_internal.h"
+
+using namespace lor;
+
+struct lor_nn;
+
+// Device workspace of one solve.  The handle holds one; a batched solve holds
+// one per (problem, right-hand side) pair so that the pairs of one problem can
+// run concurrently.
+struct Work {
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *rold = nullptr, *tmp = nullptr;
+  double *scal = nullptr, *part = nullptr, *part2 = nullptr;
+  double *rc = nullptr, *xc = nullptr;  // coarse-space vectors
+  double *yE = nullptr;                 // element-boundary operator results (CG skeleton path)
+  double *fo = nullptr;                 // DG face records
+  double *rL = nullptr, *zL = nullptr;  // DG: conforming vectors of E B E^T
+  double *h_scal = nullptr;             // pinned host copy of scal
+};
+
+struct lor_handle {
+  int dim = 3, n[3] = {1, 1, 1}, p = 1, method = LOR_CG, bc = LOR_BC_DIRICHLET;
+  double penalty = 0.0;
+  lor_options_t opt{};
+  MeshDims md{};
+  std::vector<double> verts, gllx, gllw, D;
+  std::vector<std::vector<int>> kept;
+  int L = 1;
+  int64_t ndofs = 0, nfine = 0, nel = 0;
+  int64_t ncg = 0;     // conforming unknowns (the L-vector of the Schwarz preconditioner)
+  int64_t nfaces = 0;  // DG faces
+  int J = 0, nc = 0;
+  // device memory (owned)
+  std::vector<void *> allocs;
+  size_t bytes = 0;
+  double *d_verts = nullptr, *d_gllx = nullptr, *d_gllw = nullptr, *d_D = nullptr;
+  double *d_coords = nullptr, *d_G = nullptr, *d_wdet = nullptr;
+  double *d_stencil[kMaxLevels] = {};
+  int64_t npts[kMaxLevels] = {};
+  char *d_fac = nullptr;
+  int64_t *d_fac_off = nullptr;
+  int64_t fac_bytes = 0;
+  XferTab *d_xfer = nullptr;
+  double *d_A0inv = nullptr;
+  double *d_fg = nullptr, *d_dinv = nullptr;
+  int npart = 0;
+  Work w;                  // workspace of lor_pcg_solve / lor_apply_*
+  lor_nn *nn = nullptr;    // patch network used instead of the V-cycles (LOR_NN_REPLACE)
+  int nn_mode = 0;
+  bool capturing = false;  // no event timing while a graph is captured
+  PatchArgs pa{};
+  // host copies for parity export
+  std::vector<int32_t> order_all, order_off, sched_all, sched_off;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool has_prec = false;
+  // per-kernel event timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tspans[3];
+  hipEvent_t next_event() {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
+  }
+
+  template <class T>
+  hipError_t alloc(T **ptr, size_t count) {
+    void *p = nullptr;
+    size_t b = std::max<size_t>(count * sizeof(T), 16);
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) return e;
+    allocs.push_back(p);
+    bytes += b;
+    *ptr = static_cast<T *>(p);
+    return hipSuccess;
+  }
+  ~lor_handle() {
+    for (void *p : allocs) (void)hipFree(p);
+    if (w.h_scal) (void)hipHostFree(w.h_scal);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
+};
+
+
+// Patches of the Schwarz preconditioner through the attached network:
+// z += sum_j R_j^T s_j net(R_j r / s_j) (nn_api.cpp).
+int nn_apply_patches(lor_nn *nn, const double *r, double *z, const double *flag, hipStream_t st);

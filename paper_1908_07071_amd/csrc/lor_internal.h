@@ -182,14 +182,48 @@ int coarse_inverse(int n, double *A, hipStream_t st);
 // Raises the patch kernel's dynamic LDS limit (call once before launches,
 // outside any stream capture).
 hipError_t prepare_patch_vcycle(const PatchArgs &pa);
+// dense == nullptr: z += sum_j R_j^T V_j(R_j r) (atomically).  Otherwise the
+// patch results V_j(R_j r) / dscale[j] are written into dense
+// [npatch][(2p-1)^d] (grid point g_d = level-0 node - (v_d p - p + 1)) and z
+// is not touched; dense must be zero where no patch unknown lies.
 hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r, double *z,
-                               const double *flag, hipStream_t st);
+                               const double *flag, hipStream_t st, float *dense = nullptr,
+                               const double *dscale = nullptr);
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t st);
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st);
 // slot-major float64 stencil (3^dim x npts) -> symmetric point-major records
 // (sym_width values per point) in float (f32) or float64.
 hipError_t launch_sym_stencil(const double *soa, int64_t npts, int dim, void *out, bool f32,
                               hipStream_t st);
+
+// Learned patch correction (k_nn.hip).  bf16 values are uint16_t bit patterns.
+hipError_t nn_gemm(int M, int N, int K, const uint16_t *A, int64_t ai, int64_t ak,
+                   const uint16_t *B, int64_t bk, int64_t bj, float *C, int64_t ldc, bool acc,
+                   hipStream_t st);
+hipError_t nn_im2col(const uint16_t *act, int64_t rows, int G, int cin, int Kp, int64_t npad,
+                     uint16_t *cols, const double *flag, hipStream_t st);
+hipError_t nn_col2im_relu(const float *dcols, int64_t rows, int64_t npad, int G, int cin, int Kp,
+                          const float *zprev, int ldzp, float *dz, uint16_t *dz16, hipStream_t st);
+hipError_t nn_bias_relu(float *z, int64_t rows, int cout, int Np, const float *bias, uint16_t *a,
+                        const double *flag, hipStream_t st);
+hipError_t nn_input(const float *X, int64_t rows, int64_t npad, uint16_t *a0, const double *flag,
+                    hipStream_t st);
+hipError_t nn_output(const float *z, int Np, const float *X, int64_t rows, float *y,
+                     const double *flag, hipStream_t st);
+int nn_red_blocks(int64_t n);
+hipError_t nn_loss(const float *y, const float *T, const float *X, int64_t rows, int64_t npad,
+                   int Np, double inv_m, float *dz, uint16_t *dz16, double *part, hipStream_t st);
+hipError_t nn_colsum(const float *a, int64_t rows, int ld, int col, double *part, hipStream_t st);
+hipError_t nn_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1,
+                   float b2, float eps, float c1, float c2, hipStream_t st);
+hipError_t nn_pack(const float *wl, int K27, int cout, int Kp, int Np, uint16_t *Wb, float *bias,
+                   hipStream_t st);
+hipError_t nn_grad_gather(const float *dW, int K27, int cout, int Np, float *g, hipStream_t st);
+hipError_t nn_gather(const MeshDims &md, int first, int count, const double *r, float *X,
+                     double *scale, const double *flag, hipStream_t st);
+hipError_t nn_scatter(const MeshDims &md, int first, int count, const float *y,
+                      const double *scale, double *z, const double *flag, hipStream_t st);
+hipError_t nn_fill(float *x, int64_t n, float v, hipStream_t st);
 
 // Krylov helpers.  Scalars live in a small device array.
 enum Scal { S_RHO = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_TOL2, S_DONE, S_ITERS, S_FAIL,

@@ -74,3 +74,18 @@ def batch_problems(nprob: int = 64, seed: int = 7, nmin: int = 4, nmax: int = 24
     ns = rng.integers(nmin, nmax + 1, size=nprob)
     ps = rng.integers(pmin, pmax + 1, size=nprob)
     return [(int(n), int(p), 100 + i) for i, (n, p) in enumerate(zip(ns, ps))]
+
+
+def nn_initial_params(channels: int = 32, seed: int = 11, cin: int = 2, layers: int = 3):
+    """Initial weights of the patch network as one flat float64 vector (layer
+    by layer: W [27 cin, cout] row-major, then the bias [cout]); W uniform in
+    +-sqrt(6 / fan_in) (He / Kaiming uniform), biases zero."""
+    rng = np.random.default_rng(seed)
+    out, c = [], cin
+    for li in range(layers):
+        co = 1 if li == layers - 1 else channels
+        bound = np.sqrt(6.0 / (27 * c))
+        out.append(rng.uniform(-bound, bound, size=27 * c * co))
+        out.append(np.zeros(co))
+        c = co
+    return np.concatenate(out)

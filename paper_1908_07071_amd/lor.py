@@ -30,7 +30,11 @@ EXPORTED = [
     "lor_dof_coords", "lor_assemble_rhs", "lor_apply_A", "lor_apply_P", "lor_pcg_solve",
     "lor_export_maps", "lor_export_stencils", "lor_gll", "lor_mdf_order", "lor_free",
     "lor_last_error_detail", "lor_timing", "lor_timing_read", "lor_pcg_solve_batch",
+    "lor_nn_param_count", "lor_nn_create", "lor_nn_get_params", "lor_nn_shape", "lor_nn_patch_data",
+    "lor_nn_forward", "lor_nn_gradients", "lor_nn_train_step", "lor_nn_attach", "lor_nn_free",
+    "lor_bf16_gemm",
 ]
+LOR_NN_OFF, LOR_NN_REPLACE = 0, 1
 LOR_T_APPLY_A, LOR_T_PATCH, LOR_T_COARSE = 0, 1, 2
 
 
@@ -87,6 +91,18 @@ def _load():
         "lor_timing_read": (C.c_int, [vp, C.c_int, dp, i64p]),
         "lor_pcg_solve_batch": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int, C.POINTER(vp), C.POINTER(vp),
                                           C.c_double, C.c_int, C.POINTER(lor_solve_info_t), vp]),
+        "lor_nn_param_count": (C.c_int, [C.c_int, i64p]),
+        "lor_nn_create": (C.c_int, [vp, C.c_int, dp, C.c_int, vp, C.POINTER(vp)]),
+        "lor_nn_get_params": (C.c_int, [vp, dp]),
+        "lor_nn_shape": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "lor_nn_patch_data": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+        "lor_nn_forward": (C.c_int, [vp, vp, C.c_int, vp, vp]),
+        "lor_nn_gradients": (C.c_int, [vp, vp, vp, C.c_int, dp, dp, vp]),
+        "lor_nn_train_step": (C.c_int, [vp, vp, vp, C.c_int, C.c_double, dp, vp]),
+        "lor_nn_attach": (C.c_int, [vp, vp, C.c_int]),
+        "lor_nn_free": (C.c_int, [vp]),
+        "lor_bf16_gemm": (C.c_int, [C.c_int, C.c_int, C.c_int, vp, C.c_int64, C.c_int64, vp, C.c_int64,
+                                    C.c_int64, vp, C.c_int64, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -120,6 +136,14 @@ def _stream(stream):
         return C.c_void_p(int(stream))
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _devt(t, dtype_name, name):
+    import torch
+    dt = getattr(torch, dtype_name)
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous {dtype_name} device tensor")
+    return C.c_void_p(t.data_ptr())
 
 
 def _dev(t, name):
@@ -276,3 +300,73 @@ def lor_timing_read(h, which: int):
     n = C.c_int64()
     _check(_lib.lor_timing_read(h, int(which), C.byref(t), C.byref(n)), "lor_timing_read")
     return t.value, n.value
+
+
+# ---------------------------------------------------------------- learned patch correction
+
+def lor_nn_param_count(channels: int) -> int:
+    n = C.c_int64()
+    _check(_lib.lor_nn_param_count(int(channels), C.byref(n)), "lor_nn_param_count")
+    return n.value
+
+
+def lor_nn_create(h, channels: int, params: np.ndarray, max_batch: int, stream=None):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    if p.size != lor_nn_param_count(channels):
+        raise ValueError("parameter vector has the wrong length")
+    nn = C.c_void_p()
+    _check(_lib.lor_nn_create(h, int(channels), _dptr(p), int(max_batch), _stream(stream), C.byref(nn)),
+           "lor_nn_create")
+    nn._keep = p
+    return nn
+
+
+def lor_nn_get_params(nn, channels: int) -> np.ndarray:
+    out = np.zeros(lor_nn_param_count(channels))
+    _check(_lib.lor_nn_get_params(nn, _dptr(out)), "lor_nn_get_params")
+    return out
+
+
+def lor_nn_shape(nn):
+    j, g = C.c_int(), C.c_int()
+    _check(_lib.lor_nn_shape(nn, C.byref(j), C.byref(g)), "lor_nn_shape")
+    return j.value, g.value
+
+
+def lor_nn_patch_data(nn, r, X, T, scale, stream=None):
+    _check(_lib.lor_nn_patch_data(nn, _dev(r, "r"), _devt(X, "float32", "X"), _devt(T, "float32", "T"),
+                                  _dev(scale, "scale"), _stream(stream)), "lor_nn_patch_data")
+
+
+def lor_nn_forward(nn, X, nb: int, Y, stream=None):
+    _check(_lib.lor_nn_forward(nn, _devt(X, "float32", "X"), int(nb), _devt(Y, "float32", "Y"),
+                               _stream(stream)), "lor_nn_forward")
+
+
+def lor_nn_gradients(nn, X, T, nb: int, nparam: int, stream=None):
+    loss = C.c_double()
+    g = np.zeros(nparam)
+    _check(_lib.lor_nn_gradients(nn, _devt(X, "float32", "X"), _devt(T, "float32", "T"), int(nb),
+                                 C.byref(loss), _dptr(g), _stream(stream)), "lor_nn_gradients")
+    return loss.value, g
+
+
+def lor_nn_train_step(nn, X, T, nb: int, lr: float, stream=None) -> float:
+    loss = C.c_double()
+    _check(_lib.lor_nn_train_step(nn, _devt(X, "float32", "X"), _devt(T, "float32", "T"), int(nb),
+                                  float(lr), C.byref(loss), _stream(stream)), "lor_nn_train_step")
+    return loss.value
+
+
+def lor_nn_attach(h, nn, mode: int):
+    _check(_lib.lor_nn_attach(h, nn, int(mode)), "lor_nn_attach")
+
+
+def lor_nn_free(nn):
+    _check(_lib.lor_nn_free(nn), "lor_nn_free")
+
+
+def lor_bf16_gemm(M, N, K, A, ai, ak, B, bk, bj, Cmat, ldc, stream=None):
+    _check(_lib.lor_bf16_gemm(int(M), int(N), int(K), _devt(A, "int16", "A"), int(ai), int(ak),
+                              _devt(B, "int16", "B"), int(bk), int(bj), _devt(Cmat, "float32", "C"),
+                              int(ldc), _stream(stream)), "lor_bf16_gemm")

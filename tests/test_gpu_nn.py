@@ -1,0 +1,182 @@
+"""Learned patch correction on the GPU against the float64 reference
+(oracle/nn.py), through the C ABI.
+
+Tolerances: the network's products run in bfloat16 (8-bit significand) with
+float32 accumulation, so outputs and gradients are compared in norm to a few
+percent; the patch data (float32 copies of float64 values) to float32
+rounding.
+"""
+import numpy as np
+import pytest
+
+from oracle import krylov, mesh as M, nn as ONN, schwarz as S
+from paper_1908_07071_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+C = 16
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "HIP device required"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1908_07071_amd import lor
+    return lor
+
+
+def _bf16(x):
+    """float32 -> bfloat16 bit patterns (round to nearest even) and values."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    bits = u.astype(np.uint16)
+    return bits.view(np.int16), (bits.astype(np.uint32) << 16).view(np.float32)
+
+
+def test_bf16_gemm_layouts(L, torch_dev):
+    torch = torch_dev
+    rng = np.random.default_rng(1)
+    Mm, N, K = 48, 32, 64
+    A = rng.standard_normal((Mm, K)).astype(np.float32)
+    B = rng.standard_normal((K, N)).astype(np.float32)
+    Ab, Av = _bf16(A)
+    Bb, Bv = _bf16(B)
+    ref = Av.astype(np.float64) @ Bv.astype(np.float64)
+    Cg = torch.zeros((Mm, N), dtype=torch.float32, device="cuda")
+    # A row-major (k contiguous), B row-major
+    L.lor_bf16_gemm(Mm, N, K, torch.tensor(Ab.ravel(), device="cuda"), K, 1,
+                    torch.tensor(Bb.ravel(), device="cuda"), N, 1, Cg, N)
+    assert np.abs(Cg.cpu().numpy() - ref).max() <= 1e-5 * np.abs(ref).max()
+    # A stored transposed (A(i,k) at k*M + i), B stored transposed (B(k,j) at j*K + k)
+    AbT = np.ascontiguousarray(Ab.T).ravel()
+    BbT = np.ascontiguousarray(Bb.T).ravel()
+    Cg.zero_()
+    L.lor_bf16_gemm(Mm, N, K, torch.tensor(AbT, device="cuda"), 1, Mm,
+                    torch.tensor(BbT, device="cuda"), 1, K, Cg, N)
+    assert np.abs(Cg.cpu().numpy() - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def _problem(L, n=2, p=3, seed=9):
+    V = inputs.structured_vertices(3, n, 0.1, seed=seed)
+    mesh = M.make_mesh(3, [n] * 3, V)
+    h = L.lor_setup(3, n, V, p)
+    return h, mesh, p
+
+
+def _data(L, torch, nn, h, seed):
+    J, G = L.lor_nn_shape(nn)
+    N = L.lor_ndofs(h)
+    r = torch.tensor(inputs.gaussian_rhs(N, seed), device="cuda")
+    X = torch.zeros((J, G ** 3, 2), dtype=torch.float32, device="cuda")
+    T = torch.zeros((J, G ** 3), dtype=torch.float32, device="cuda")
+    sc = torch.zeros(J, dtype=torch.float64, device="cuda")
+    L.lor_nn_patch_data(nn, r, X, T, sc)
+    torch.cuda.synchronize()
+    return r, X, T, sc
+
+
+def test_patch_data_and_forward_match_oracle(L, torch_dev):
+    torch = torch_dev
+    h, mesh, p = _problem(L)
+    params = inputs.nn_initial_params(C, seed=3)
+    nn = L.lor_nn_create(h, C, params, max_batch=32)
+    try:
+        r, X, T, sc = _data(L, torch, nn, h, 5)
+        B = S.SchwarzLOR(mesh, p)
+        Xr, Tr, sr = ONN.patch_samples(B, r.cpu().numpy())
+        assert np.allclose(sc.cpu().numpy(), sr, rtol=1e-14)
+        assert np.abs(X.cpu().numpy() - Xr).max() <= 1e-6
+        assert np.abs(T.cpu().numpy() - Tr).max() <= 1e-6 * np.abs(Tr).max()
+        J, G = L.lor_nn_shape(nn)
+        Y = torch.zeros((J, G ** 3), dtype=torch.float32, device="cuda")
+        L.lor_nn_forward(nn, X, J, Y)
+        torch.cuda.synchronize()
+        shapes = ONN.layer_shapes(C)
+        yref, _ = ONN.forward(ONN.unflatten(params, shapes), X.cpu().numpy().astype(np.float64), G)
+        err = np.linalg.norm(Y.cpu().numpy() - yref) / np.linalg.norm(yref)
+        assert err <= 3e-2, err
+    finally:
+        L.lor_nn_free(nn)
+        L.lor_free(h)
+
+
+def test_gradients_match_oracle(L, torch_dev):
+    torch = torch_dev
+    h, mesh, p = _problem(L)
+    params = inputs.nn_initial_params(C, seed=4)
+    nn = L.lor_nn_create(h, C, params, max_batch=32)
+    try:
+        r, X, T, sc = _data(L, torch, nn, h, 6)
+        J, G = L.lor_nn_shape(nn)
+        nparam = L.lor_nn_param_count(C)
+        loss, g = L.lor_nn_gradients(nn, X, T, J, nparam)
+        shapes = ONN.layer_shapes(C)
+        lref, gref = ONN.loss_and_grads(ONN.unflatten(params, shapes), X.cpu().numpy().astype(np.float64),
+                                        T.cpu().numpy().astype(np.float64), G)
+        assert abs(loss - lref) <= 2e-2 * lref, (loss, lref)
+        o = 0
+        for (k, n), (dW, db) in zip(shapes, gref):
+            gw = g[o:o + k * n].reshape(k, n)
+            o += k * n
+            gb = g[o:o + n]
+            o += n
+            assert np.linalg.norm(gw - dW) <= 5e-2 * np.linalg.norm(dW), (k, n)
+            assert np.linalg.norm(gb - db) <= 5e-2 * np.linalg.norm(db) + 1e-7, (k, n)
+    finally:
+        L.lor_nn_free(nn)
+        L.lor_free(h)
+
+
+def test_training_and_replace_preconditioner(L, torch_dev):
+    """Adam lowers the loss on data the method generates; the network then
+    stands in for the patch V-cycles (parity with the float64 reference
+    preconditioner at bfloat16 accuracy), and flexible CG still converges."""
+    torch = torch_dev
+    h, mesh, p = _problem(L)
+    params = inputs.nn_initial_params(C, seed=5)
+    nn = L.lor_nn_create(h, C, params, max_batch=64)
+    try:
+        J, G = L.lor_nn_shape(nn)
+        Xs, Ts = [], []
+        for s in range(2):
+            _, X, T, _ = _data(L, torch, nn, h, 100 + s)
+            Xs.append(X)
+            Ts.append(T)
+        X = torch.cat(Xs).contiguous()
+        T = torch.cat(Ts).contiguous()
+        first = last = None
+        for it in range(300):
+            loss = L.lor_nn_train_step(nn, X, T, X.shape[0], 3e-3)
+            first = loss if first is None else first
+            last = loss
+        assert last < 0.5 * first, (first, last)
+        # the network inside the preconditioner
+        L.lor_nn_attach(h, nn, L.LOR_NN_REPLACE)
+        N = L.lor_ndofs(h)
+        rin = inputs.gaussian_rhs(N, 7)
+        rt = torch.tensor(rin, device="cuda")
+        z = torch.empty_like(rt)
+        L.lor_apply_P(h, rt, z)
+        torch.cuda.synchronize()
+        shapes = ONN.layer_shapes(C)
+        wn = L.lor_nn_get_params(nn, C)
+        B = S.SchwarzLOR(mesh, p)
+        zref = ONN.preconditioner_replace(B, ONN.unflatten(wn, shapes), rin)
+        err = np.linalg.norm(z.cpu().numpy() - zref) / np.linalg.norm(zref)
+        assert err <= 3e-2, err
+        x = torch.zeros_like(rt)
+        info = L.lor_pcg_solve(h, rt, x, rtol=1e-6, maxit=400, check=False)
+        print("FCG with the network:", info.iters, info.status, flush=True)
+        assert info.status in (L.LOR_OK, L.LOR_ENOCONV)
+        L.lor_nn_attach(h, None, L.LOR_NN_OFF)
+        x.zero_()
+        info0 = L.lor_pcg_solve(h, rt, x, rtol=1e-6, maxit=400)
+        assert info0.status == L.LOR_OK
+    finally:
+        L.lor_nn_free(nn)
+        L.lor_free(h)
