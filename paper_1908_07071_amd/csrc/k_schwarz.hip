@@ -126,29 +126,27 @@ __device__ __forceinline__ void load_chunk(uint4 (&R)[QM], const uint4 *src, int
   }
 }
 
-template <typename T, bool FWD, int QM>
-__device__ __forceinline__ void run_chunk(const uint4 (&R)[QM], T *Y, uint32_t hdr) {
+// The steps of one chunk with NPP coupling pairs per row: the chunk's widest
+// row (rows with fewer couplings have zero padding pairs that read the row
+// itself), so a chunk of narrow rows costs fewer LDS reads and FMAs.
+template <typename T, bool FWD, int QM, int NPP>
+__device__ __forceinline__ void run_steps(const uint4 (&R)[QM], T *Y, int nsteps, int mystep,
+                                          int row) {
   constexpr int H = sweep_head_words<T>(FWD), PW = sweep_pair_words<T>(), SZ = int(sizeof(T)) / 4;
-  constexpr int NP = (kMaxCouplings + 1) / 2;
-  const int nsteps = (hdr >> 8) & 0xFF;
-  (void)hdr;
-  const uint32_t d0 = R[0].x;
-  const int mystep = (d0 >> 31) ? int((d0 >> 16) & 0x3F) : -1;
-  const int row = int(d0 & 0xFFFF);
   for (int s = 0; s < nsteps; ++s) {
     if (mystep == s) {
       T acc0 = FWD ? Y[row] : Y[row] * word_get<T, QM>(R, 1);
       T acc1 = T(0);
       // all LDS reads are issued before the FMAs, with no branch between them
       // (padding pairs have zero values and offsets: they read the row itself)
-      constexpr int HALF = (NP + 1) / 2;  // two halves bound the live registers
+      constexpr int HALF = (NPP + 1) / 2;  // two halves bound the live registers
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        T y[2 * HALF];
+        T y[2 * HALF + 2];
 #pragma unroll
         for (int t = 0; t < HALF; ++t) {
           const int p = h * HALF + t;
-          if (p < NP) {
+          if (p < NPP) {
             const uint32_t o = wget(R, H + p * PW + PW - 1);
             y[2 * t] = Y[row + int(short(o & 0xFFFF))];
             y[2 * t + 1] = Y[row + int(short(o >> 16))];
@@ -157,7 +155,7 @@ __device__ __forceinline__ void run_chunk(const uint4 (&R)[QM], T *Y, uint32_t h
 #pragma unroll
         for (int t = 0; t < HALF; ++t) {
           const int p = h * HALF + t;
-          if (p < NP) {
+          if (p < NPP) {
             acc0 -= word_get<T, QM>(R, H + p * PW) * y[2 * t];
             acc1 -= word_get<T, QM>(R, H + p * PW + SZ) * y[2 * t + 1];
           }
@@ -166,6 +164,31 @@ __device__ __forceinline__ void run_chunk(const uint4 (&R)[QM], T *Y, uint32_t h
       Y[row] = acc0 + acc1;
     }
     wave_sync();
+  }
+}
+
+template <typename T, bool FWD, int QM>
+__device__ __forceinline__ void run_chunk(const uint4 (&R)[QM], T *Y, uint32_t hdr) {
+  const int nsteps = (hdr >> 8) & 0xFF;
+  const int npairs = int((hdr >> 16) & 0xFF) / 2;  // the chunk's widest row, in pairs
+  const uint32_t d0 = R[0].x;
+  const int mystep = (d0 >> 31) ? int((d0 >> 16) & 0x3F) : -1;
+  const int row = int(d0 & 0xFFFF);
+  switch (npairs) {
+    case 0: run_steps<T, FWD, QM, 0>(R, Y, nsteps, mystep, row); break;
+    case 1: run_steps<T, FWD, QM, 1>(R, Y, nsteps, mystep, row); break;
+    case 2: run_steps<T, FWD, QM, 2>(R, Y, nsteps, mystep, row); break;
+    case 3: run_steps<T, FWD, QM, 3>(R, Y, nsteps, mystep, row); break;
+    case 4: run_steps<T, FWD, QM, 4>(R, Y, nsteps, mystep, row); break;
+    case 5: run_steps<T, FWD, QM, 5>(R, Y, nsteps, mystep, row); break;
+    case 6: run_steps<T, FWD, QM, 6>(R, Y, nsteps, mystep, row); break;
+    case 7: run_steps<T, FWD, QM, 7>(R, Y, nsteps, mystep, row); break;
+    case 8: run_steps<T, FWD, QM, 8>(R, Y, nsteps, mystep, row); break;
+    case 9: run_steps<T, FWD, QM, 9>(R, Y, nsteps, mystep, row); break;
+    case 10: run_steps<T, FWD, QM, 10>(R, Y, nsteps, mystep, row); break;
+    case 11: run_steps<T, FWD, QM, 11>(R, Y, nsteps, mystep, row); break;
+    case 12: run_steps<T, FWD, QM, 12>(R, Y, nsteps, mystep, row); break;
+    default: run_steps<T, FWD, QM, (kMaxCouplings + 1) / 2>(R, Y, nsteps, mystep, row); break;
   }
 }
 
