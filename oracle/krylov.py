@@ -46,3 +46,19 @@ def pcg(A, b, prec, tol=1e-8, maxit=1000, flexible=False, x0=None):
         p = z + beta * p
         rho = rho_new
     return x, it, hist
+
+
+def iteration_band(A, b, prec, tol=1e-8, maxit=1000, rel=1e-12, seeds=(1, 2), flexible=False):
+    """(lowest, highest) iteration count of pcg when the preconditioner's
+    output carries relative perturbations of size rel (the unperturbed run
+    and one run per seed).  Near a plateau of the residual history the count
+    moves with rounding; a second implementation whose preconditioner agrees
+    with this one to rel should fall inside the band, give or take one."""
+    its = [pcg(A, b, prec, tol=tol, maxit=maxit, flexible=flexible)[1]]
+    for s in seeds:
+        rng = np.random.default_rng(s)
+        def noisy(r, rng=rng):
+            z = prec(r)
+            return z * (1.0 + rel * rng.standard_normal(z.shape))
+        its.append(pcg(A, b, noisy, tol=tol, maxit=maxit, flexible=flexible)[1])
+    return min(its), max(its)

@@ -226,14 +226,12 @@ __device__ __forceinline__ void sweep(T *Y, const char *blk) {
   }
 }
 
-// R = B - A X on one level (A from the global level stencil).  GB: the right
-// side is the global residual (finest level) instead of B in LDS.  Two rows
-// per lane and iteration, with all their global loads issued together.
-// The centre and forward half of a point's symmetric stencil record, with
-// 16-byte loads (the records are 64 B (float) or 128 B (double) aligned).
+// A point's stencil record with 16-byte loads (records are 16-byte aligned):
+// a[s] = coefficient of slot s; in the symmetric half-records (double) only
+// slots C.. are filled.
 template <int DIM, typename ST>
-__device__ __forceinline__ void load_sym_rec(const ST *__restrict__ rec, ST *a) {
-  constexpr int W = sym_width<DIM>(), C = DIM == 3 ? 13 : 4;
+__device__ __forceinline__ void load_rec(const ST *__restrict__ rec, ST *a) {
+  constexpr int W = rec_width<DIM, ST>(), NS = DIM == 3 ? 27 : 9, C = NS / 2;
   constexpr int PER = 16 / int(sizeof(ST));  // values per 16-byte load
   ST v[W];
 #pragma unroll
@@ -250,19 +248,40 @@ __device__ __forceinline__ void load_sym_rec(const ST *__restrict__ rec, ST *a) 
       v[2 * q + 1] = t.y;
     }
   }
+  if constexpr (sizeof(ST) == 4) {
 #pragma unroll
-  for (int j = 0; j <= C; ++j) a[C + j] = v[j];
+    for (int s = 0; s < NS; ++s) a[s] = v[s];
+  } else {
+#pragma unroll
+    for (int j = 0; j <= C; ++j) a[C + j] = v[j];
+  }
 }
 
+// right side of the residual of row i (level-box index ii, grid point g):
+// the global residual at the finest level (GB), else B in LDS
+template <int DIM, typename T, bool GB>
+__device__ __forceinline__ T residual_rhs(const T *B, int ii, int64_t g, const double *__restrict__ rglob,
+                                          const MeshDims &md) {
+  if (GB) {
+    const int ox = md.dirichlet ? 1 : 0;
+    const int gx = int(g % md.ng[0]), gy = int((g / md.ng[0]) % md.ng[1]),
+              gz = DIM == 3 ? int(g / (int64_t(md.ng[0]) * md.ng[1])) : 0;
+    return T(rglob[int64_t(gx - ox) +
+                   int64_t(md.nu[0]) * (int64_t(gy - ox) + (DIM == 3 ? int64_t(md.nu[1]) * (gz - ox) : 0))]);
+  }
+  return B[ii];
+}
+
+// R = B - A X on one level from full records (float): each row reads its own
+// record only.  Two rows per lane and iteration, with all their global loads
+// issued together.
 template <int DIM, typename T, typename ST, bool GB>
-__device__ __forceinline__ void residual(T *R, const T *B, const T *X, const Box<DIM> &bx,
-                                         const ST *__restrict__ st, int64_t npts, const int *lng,
-                                         const double *__restrict__ rglob, const MeshDims &md) {
-  constexpr int NS = DIM == 3 ? 27 : 9, C = NS / 2, W = sym_width<DIM>();
+__device__ __forceinline__ void residual_full(T *R, const T *B, const T *X, const Box<DIM> &bx,
+                                              const ST *__restrict__ st, const int *lng,
+                                              const double *__restrict__ rglob, const MeshDims &md) {
+  constexpr int NS = DIM == 3 ? 27 : 9, W = rec_width<DIM, ST>();
   constexpr int RB = 2;
   const int mx = bx.m[0], my = bx.m[1], mz = bx.m[2];
-  const int ox = md.dirichlet ? 1 : 0;
-  (void)npts;
   for (int i0 = threadIdx.x; i0 < bx.n; i0 += 64 * RB) {
     ST a[RB][NS];
     T acc[RB];
@@ -271,28 +290,8 @@ __device__ __forceinline__ void residual(T *R, const T *B, const T *X, const Box
     for (int r = 0; r < RB; ++r) {
       ii[r] = min(i0 + 64 * r, bx.n - 1);  // clamped: loads stay valid, store is skipped
       const int64_t g = level_gidx<DIM>(bx, ii[r], lng);
-      if (GB) {
-        const int gx = int(g % md.ng[0]), gy = int((g / md.ng[0]) % md.ng[1]),
-                  gz = DIM == 3 ? int(g / (int64_t(md.ng[0]) * md.ng[1])) : 0;
-        acc[r] = T(rglob[int64_t(gx - ox) +
-                         int64_t(md.nu[0]) * (int64_t(gy - ox) + (DIM == 3 ? int64_t(md.nu[1]) * (gz - ox) : 0))]);
-      } else {
-        acc[r] = B[ii[r]];
-      }
-      // centre and forward half from the point's own record; the backward
-      // half from the neighbours' records (the point's own record when the
-      // neighbour is outside the patch, where X is zero and the term dropped)
-      load_sym_rec<DIM, ST>(st + g * W, a[r]);
-      const int i = ii[r];
-      const int ix = i % mx, iy = (i / mx) % my, iz = DIM == 3 ? i / (mx * my) : 0;
-#pragma unroll
-      for (int s = 0; s < C; ++s) {
-        const int sx = s % 3 - 1, sy = (s / 3) % 3 - 1, sz = DIM == 3 ? s / 9 - 1 : 0;
-        const int jx = ix + sx, jy = iy + sy, jz = iz + sz;
-        const bool in = jx >= 0 && jx < mx && jy >= 0 && jy < my && (DIM == 2 || (jz >= 0 && jz < mz));
-        const int64_t off = sx + int64_t(lng[0]) * (sy + int64_t(lng[1]) * sz);
-        a[r][s] = st[(in ? g + off : g) * W + (NS - 1 - s - C)];
-      }
+      acc[r] = residual_rhs<DIM, T, GB>(B, ii[r], g, rglob, md);
+      load_rec<DIM, ST>(st + g * W, a[r]);
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
@@ -310,6 +309,68 @@ __device__ __forceinline__ void residual(T *R, const T *B, const T *X, const Box
     }
   }
   wave_sync();
+}
+
+template <int DIM, typename T, typename ST, bool GB>
+__device__ __forceinline__ void residual_scatter(T *R, const T *B, const T *X, const Box<DIM> &bx,
+                                                 const ST *__restrict__ st, const int *lng,
+                                                 const double *__restrict__ rglob, const MeshDims &md) {
+  // Each row reads only its own record (centre and forward half):
+  //   R[i]       = b_i - a(i,C) X[i] - sum_{s > C} a(i,s) X[i + o_s]
+  //   R[i + o_s] -= a(i,s) X[i]   (the neighbour's backward coupling, equal
+  //                                to a(i,s) by symmetry)
+  // the second kind by LDS atomics into R, cleared first.
+  constexpr int NS = DIM == 3 ? 27 : 9, C = NS / 2, W = rec_width<DIM, ST>();
+  constexpr int RB = 2;
+  const int mx = bx.m[0], my = bx.m[1], mz = bx.m[2];
+  for (int i = threadIdx.x; i < bx.n; i += 64) R[i] = T(0);
+  wave_sync();
+  for (int i0 = threadIdx.x; i0 < bx.n; i0 += 64 * RB) {
+    ST a[RB][NS];
+    T acc[RB];
+    int ii[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      ii[r] = min(i0 + 64 * r, bx.n - 1);  // clamped: loads stay valid, updates are skipped
+      const int64_t g = level_gidx<DIM>(bx, ii[r], lng);
+      acc[r] = residual_rhs<DIM, T, GB>(B, ii[r], g, rglob, md);
+      load_rec<DIM, ST>(st + g * W, a[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int i = ii[r];
+      const bool live = i0 + 64 * r < bx.n;
+      const int ix = i % mx, iy = (i / mx) % my, iz = DIM == 3 ? i / (mx * my) : 0;
+      const T xi = X[i];
+      acc[r] -= T(a[r][C]) * xi;
+#pragma unroll
+      for (int s = C + 1; s < NS; ++s) {
+        const int sx = s % 3 - 1, sy = (s / 3) % 3 - 1, sz = DIM == 3 ? s / 9 - 1 : 0;
+        const int jx = ix + sx, jy = iy + sy, jz = iz + sz;
+        const bool in = jx >= 0 && jx < mx && jy >= 0 && jy < my && (DIM == 2 || (jz >= 0 && jz < mz));
+        const int jn = in ? jx + mx * (jy + my * jz) : i;
+        const T aij = in ? T(a[r][s]) : T(0);
+        acc[r] -= aij * X[jn];
+        if (live && in) atomicAdd(R + jn, -aij * xi);
+      }
+      if (live) atomicAdd(R + i, acc[r]);
+    }
+  }
+  wave_sync();
+}
+
+// R = B - A X on one level of a patch: from full records in single precision,
+// from symmetric half-records with LDS atomics in double precision (twice the
+// bytes per coefficient: the half-record keeps a row's stencil in one
+// 128-byte line).  Both read one line per row.
+template <int DIM, typename T, typename ST, bool GB>
+__device__ __forceinline__ void residual(T *R, const T *B, const T *X, const Box<DIM> &bx,
+                                         const ST *__restrict__ st, const int *lng,
+                                         const double *__restrict__ rglob, const MeshDims &md) {
+  if constexpr (sizeof(ST) == 8)
+    residual_scatter<DIM, T, ST, GB>(R, B, X, bx, st, lng, rglob, md);
+  else
+    residual_full<DIM, T, ST, GB>(R, B, X, bx, st, lng, rglob, md);
 }
 
 template <int DIM, typename T, typename ST, int W>
@@ -377,9 +438,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     sweep<T, true>(Xk, bf);
     sweep<T, false>(Xk, bb);
     if (k == 0)
-      residual<DIM, T, ST, true>(Rk, Bk, Xk, fb, stn[k], pa.npts[k], pa.lng[k], r, md);
+      residual<DIM, T, ST, true>(Rk, Bk, Xk, fb, stn[k], pa.lng[k], r, md);
     else
-      residual<DIM, T, ST, false>(Rk, Bk, Xk, fb, stn[k], pa.npts[k], pa.lng[k], r, md);
+      residual<DIM, T, ST, false>(Rk, Bk, Xk, fb, stn[k], pa.lng[k], r, md);
     const Box<DIM> cb = make_box<DIM>(pa, v, k + 1);
     if (cb.n > 0) {
       T *Bc = lds_vec<DIM, T>(lds, pa, v, k + 1, 1);
@@ -423,7 +484,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       constexpr int C = DIM == 3 ? 13 : 4;
       T *Xc = lds_vec<DIM, T>(lds, pa, v, kc, 0);
       const T rhs = kc == 0 ? Xc[0] : lds_vec<DIM, T>(lds, pa, v, kc, 1)[0];
-      Xc[0] = rhs / T(stn[kc][g * sym_width<DIM>()]);  // centre entry of the record
+      Xc[0] = rhs / T(stn[kc][g * rec_width<DIM, ST>() + rec_centre<DIM, ST>()]);
     }
     wave_sync();
   }
@@ -478,9 +539,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       wave_sync();
     }
     if (k == 0)
-      residual<DIM, T, ST, true>(Rk, Bk, Xk, fb, stn[k], pa.npts[k], pa.lng[k], r, md);
+      residual<DIM, T, ST, true>(Rk, Bk, Xk, fb, stn[k], pa.lng[k], r, md);
     else
-      residual<DIM, T, ST, false>(Rk, Bk, Xk, fb, stn[k], pa.npts[k], pa.lng[k], r, md);
+      residual<DIM, T, ST, false>(Rk, Bk, Xk, fb, stn[k], pa.lng[k], r, md);
     sweep<T, true>(Rk, bf);
     sweep<T, false>(Rk, bb);
     for (int i = threadIdx.x; i < fb.n; i += 64) Xk[i] += Rk[i];

@@ -429,10 +429,14 @@ __global__ void k_fill(double *x, int64_t n, double v) {
 
 template <int DIM, typename ST>
 __global__ void k_sym_stencil(const double *__restrict__ soa, int64_t npts, ST *__restrict__ out) {
-  constexpr int NS = DIM == 3 ? 27 : 9, C = NS / 2, W = sym_width<DIM>();
+  constexpr int NS = DIM == 3 ? 27 : 9, C = NS / 2, W = rec_width<DIM, ST>();
+  constexpr bool kFull = sizeof(ST) == 4;  // float records hold every slot
   for (int64_t g = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; g < npts;
        g += int64_t(gridDim.x) * blockDim.x)
-    for (int j = 0; j < W; ++j) out[g * W + j] = j <= C ? ST(soa[int64_t(C + j) * npts + g]) : ST(0);
+    for (int j = 0; j < W; ++j) {
+      const int slot = kFull ? j : C + j;
+      out[g * W + j] = slot < NS ? ST(soa[int64_t(slot) * npts + g]) : ST(0);
+    }
 }
 
 __global__ void k_to_float(const double *__restrict__ s, float *__restrict__ d, int64_t n) {

@@ -299,13 +299,14 @@ int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hi
   for (int k = 0; k < L; ++k) {
     const int s = int(h.kept[k].size()) - 1;
     pa.s[k] = s;
-    const int W = dim == 3 ? sym_width<3>() : sym_width<2>();
     if (mixed) {
+      const int W = dim == 3 ? rec_width<3, float>() : rec_width<2, float>();
       float *f32 = nullptr;
       HIPCHK(h.alloc(&f32, size_t(W) * h.npts[k]));
       HIPCHK(launch_sym_stencil(h.d_stencil[k], h.npts[k], dim, f32, true, st));
       pa.stencil[k] = reinterpret_cast<const double *>(f32);  // read as float by the kernel
     } else {
+      const int W = dim == 3 ? rec_width<3, double>() : rec_width<2, double>();
       double *f64 = nullptr;
       HIPCHK(h.alloc(&f64, size_t(W) * h.npts[k]));
       HIPCHK(launch_sym_stencil(h.d_stencil[k], h.npts[k], dim, f64, false, st));

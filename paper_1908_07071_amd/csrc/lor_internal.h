@@ -44,8 +44,8 @@ struct PatchArgs {
   int nlev;                          // levels of the element-structured hierarchy
   int s[kMaxLevels];                 // sub-intervals per element at each level
   int nv[3];                         // vertices per direction (n+1)
-  const double *stencil[kMaxLevels]; // global level stencils, symmetric point-major records
-                                     // (sym_width), float when fp32
+  const double *stencil[kMaxLevels]; // global level stencils, point-major records
+                                     // (rec_width): full in float, symmetric half in double
   int64_t npts[kMaxLevels];          // level grid points
   int lng[kMaxLevels][3];            // level grid points per direction
   const XferTab *xfer;               // [nlev-1][3] by (fine level, direction type)
@@ -73,15 +73,23 @@ struct PatchArgs {
 //   where off is the LDS offset of the neighbour from the row (padding pairs
 //   are zero).  Lane 63 carries the header of the next chunk instead:
 //   Q (bits 0-7) | nsteps (8-15) | W (16-23), W = couplings per record.
-// Level stencils as the patch kernel reads them: point-major, symmetric
-// half.  Record of grid point g: values of slots C, C+1, .., 3^d - 1 (the
-// centre and the neighbours after it in slot order; C = (3^d - 1) / 2),
-// zero-padded to kSymW values.  Slot s < C of point g equals slot
-// 3^d - 1 - s of the neighbour g + offset(s) (the LOR matrices are
-// symmetric bit for bit).
-template <int DIM>
-__host__ __device__ constexpr int sym_width() {
-  return DIM == 3 ? 16 : 8;
+// Level stencils as the patch kernel reads them: point-major records, one
+// per grid point g at g * rec_width.
+//   float:  the full stencil, slots 0 .. 3^d - 1 in slot order, zero-padded
+//           (128 B per point in 3D: one cache line, no neighbour reads);
+//   double: the symmetric half, slots C .. 3^d - 1 (the centre and the
+//           neighbours after it in slot order; C = (3^d - 1) / 2),
+//           zero-padded.  Slot s < C of point g equals slot 3^d - 1 - s of
+//           the neighbour g + offset(s) (the LOR matrices are symmetric bit
+//           for bit).
+template <int DIM, typename ST>
+__host__ __device__ constexpr int rec_width() {
+  return sizeof(ST) == 4 ? (DIM == 3 ? 32 : 12) : (DIM == 3 ? 16 : 8);
+}
+// index of the centre coefficient inside a record
+template <int DIM, typename ST>
+__host__ __device__ constexpr int rec_centre() {
+  return sizeof(ST) == 4 ? (DIM == 3 ? 13 : 4) : 0;
 }
 
 constexpr int kChunkRows = 63;
@@ -191,8 +199,8 @@ hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r,
                                const double *dscale = nullptr);
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t st);
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st);
-// slot-major float64 stencil (3^dim x npts) -> symmetric point-major records
-// (sym_width values per point) in float (f32) or float64.
+// slot-major float64 stencil (3^dim x npts) -> point-major records
+// (rec_width values per point): full in float (f32), symmetric half in float64.
 hipError_t launch_sym_stencil(const double *soa, int64_t npts, int dim, void *out, bool f32,
                               hipStream_t st);
 

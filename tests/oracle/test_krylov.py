@@ -46,3 +46,25 @@ def test_identity_preconditioner_is_cg():
     x, it, _ = krylov.pcg(A, b, lambda r: r, tol=1e-12)
     assert np.allclose(A @ x, b, rtol=0, atol=1e-10)
     assert it <= 30
+
+
+def test_iteration_band():
+    """The band holds the unperturbed count, collapses to it without
+    perturbation, and widens on a problem whose residual history has a plateau
+    at the tolerance (3D IP-DG, p = 2, where a 1e-13 relative change of the
+    preconditioner moves the count by two)."""
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((30, 30))
+    A = A @ A.T + 30 * np.eye(30)
+    b = rng.standard_normal(30)
+    _, it, _ = krylov.pcg(A, b, lambda r: r, tol=1e-12)
+    assert krylov.iteration_band(A, b, lambda r: r, tol=1e-12, rel=0.0) == (it, it)
+    lo, hi = krylov.iteration_band(A, b, lambda r: r, tol=1e-12)
+    assert lo <= it <= hi
+    mesh = M.make_mesh(3, [2, 2, 1], inputs.structured_vertices(3, [2, 2, 1], 0.1, seed=44))
+    D = HO.dg_operator(mesh, 2, "ip", 13.5)
+    bd = inputs.gaussian_rhs(D.shape[0], 77)
+    B = S.SchwarzDG(mesh, 2, D)
+    _, itd, _ = krylov.pcg(D, bd, B.apply, tol=1e-10)
+    lo, hi = krylov.iteration_band(D, bd, B.apply, tol=1e-10)
+    assert lo <= itd <= hi and hi - lo >= 1, (lo, itd, hi)

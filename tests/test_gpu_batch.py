@@ -5,7 +5,10 @@ oracle.
 Each pair of a batch runs the same kernels in the same order as
 lor_pcg_solve; the patch corrections are scattered with float64 atomics, so
 two solves agree to rounding (not bit for bit) and in their iteration count
-within one.  Every captured chunk is replayed many times with host
+within one.  Against the oracle the iteration count falls within one of the
+band the oracle's own count spans when its preconditioner output is
+perturbed at the float64 preconditioner's parity tolerance (1e-12 relative):
+near a plateau of the residual history the count moves with rounding.  Every captured chunk is replayed many times with host
 synchronization in between, which the comparison covers replay by replay.
 """
 import numpy as np
@@ -94,13 +97,13 @@ def test_batch_matches_oracle(L, torch_dev):
                 B = S.SchwarzDG(mesh, p, A)
             for j in range(2):
                 b = inputs.gaussian_rhs(A.shape[0], 77 + j)
-                _, it, _ = krylov.pcg(A, b, B.apply, tol=1e-10)
-                refs.append((A, b, it))
+                band = krylov.iteration_band(A, b, B.apply, tol=1e-10)
+                refs.append((A, b, band))
                 bs.append(torch.tensor(b, device="cuda"))
                 xs.append(torch.zeros_like(bs[-1]))
         infos = L.lor_pcg_solve_batch(hs, bs, xs, rtol=1e-10, maxit=500)
-        for k, (A, b, it) in enumerate(refs):
-            assert abs(infos[k].iters - it) <= 1, (k, infos[k].iters, it)
+        for k, (A, b, (lo, hi)) in enumerate(refs):
+            assert lo - 1 <= infos[k].iters <= hi + 1, (k, infos[k].iters, lo, hi)
             x = xs[k].cpu().numpy()
             assert np.linalg.norm(b - A @ x) <= 1.05e-10 * np.linalg.norm(b)
     finally:

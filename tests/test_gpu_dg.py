@@ -147,10 +147,14 @@ def test_dg_pcg_solve(case, L, torch_dev):
         x = torch.zeros_like(b)
         info = L.lor_pcg_solve(h, b, x, rtol=1e-10, maxit=1000)
         B = S.SchwarzDG(mesh, p, A)
-        _, it, _ = krylov.pcg(A, bin_, B.apply, tol=1e-10)
-        # rounding differences between the two sides shift long solves by a
-        # few iterations (both stop on the same recursive residual)
-        assert abs(info.iters - it) <= max(1, 0.02 * it), (info.iters, it)
+        # the oracle's own count under perturbations of its preconditioner at
+        # the float64 parity tolerance (near a plateau of the residual history
+        # the count moves with rounding), widened by 2% for the rounding of
+        # the operator and inner products over long ill-conditioned solves
+        # (both sides stop on the recursive residual)
+        lo, hi = krylov.iteration_band(A, bin_, B.apply, tol=1e-10)
+        slack = max(1, 0.02 * hi)
+        assert lo - slack <= info.iters <= hi + slack, (info.iters, lo, hi)
         xs = x.cpu().numpy()
         assert np.linalg.norm(bin_ - A @ xs) <= 1.05e-10 * np.linalg.norm(bin_)
         xd = spla.spsolve(A.tocsc(), bin_)
