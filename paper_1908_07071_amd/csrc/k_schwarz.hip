@@ -66,6 +66,51 @@ __device__ inline int64_t level_gidx(const Box<DIM> &bx, int i, const int *lng) 
          int64_t(lng[0]) * (int64_t(bx.lo[1] + iy) + (DIM == 3 ? int64_t(lng[1]) * (bx.lo[2] + iz) : 0));
 }
 
+// Coordinates of row i of a box and of the rows after it at a fixed stride,
+// advanced without a division per row (one division when the walk starts).
+template <int DIM>
+struct Walk {
+  int x, y, z;     // current row
+  int dx, dy, dz;  // the stride in coordinates (dx < m0, dy < m1)
+  int m0, m1;
+  __device__ __forceinline__ Walk(const Box<DIM> &bx, int i, int stride) {
+    m0 = max(bx.m[0], 1);
+    m1 = max(bx.m[1], 1);
+    x = i % m0;
+    const int t = i / m0;
+    y = t % m1;
+    z = t / m1;
+    dx = stride % m0;
+    const int u = stride / m0;
+    dy = u % m1;
+    dz = u / m1;
+  }
+  __device__ __forceinline__ void step() {
+    x += dx;
+    const bool cx = x >= m0;
+    x = cx ? x - m0 : x;
+    y += dy + (cx ? 1 : 0);
+    const bool cy = y >= m1;
+    y = cy ? y - m1 : y;
+    z += dz + (cy ? 1 : 0);
+  }
+};
+
+// level-grid index of the walk's current row
+template <int DIM>
+__device__ __forceinline__ int64_t walk_gidx(const Box<DIM> &bx, const Walk<DIM> &w, const int *lng) {
+  const int t = (bx.lo[1] + w.y) + (DIM == 3 ? lng[1] * (bx.lo[2] + w.z) : 0);
+  return int64_t(bx.lo[0] + w.x) + int64_t(lng[0]) * t;
+}
+
+// index of the walk's current row (a level-0 box) in the global vectors
+template <int DIM>
+__device__ __forceinline__ int64_t walk_uidx(const Box<DIM> &bx, const Walk<DIM> &w, const MeshDims &md) {
+  const int ox = md.dirichlet ? 1 : 0;
+  const int t = (bx.lo[1] + w.y - ox) + (DIM == 3 ? md.nu[1] * (bx.lo[2] + w.z - ox) : 0);
+  return int64_t(bx.lo[0] + w.x - ox) + int64_t(md.nu[0]) * t;
+}
+
 // LDS layout of one patch: level 0 holds X, R; level k > 0 holds X, B, R.
 // which: 0 = X, 1 = B, 2 = R.
 template <int DIM, typename T>
@@ -257,55 +302,56 @@ __device__ __forceinline__ void load_rec(const ST *__restrict__ rec, ST *a) {
   }
 }
 
-// right side of the residual of row i (level-box index ii, grid point g):
-// the global residual at the finest level (GB), else B in LDS
-template <int DIM, typename T, bool GB>
-__device__ __forceinline__ T residual_rhs(const T *B, int ii, int64_t g, const double *__restrict__ rglob,
-                                          const MeshDims &md) {
-  if (GB) {
-    const int ox = md.dirichlet ? 1 : 0;
-    const int gx = int(g % md.ng[0]), gy = int((g / md.ng[0]) % md.ng[1]),
-              gz = DIM == 3 ? int(g / (int64_t(md.ng[0]) * md.ng[1])) : 0;
-    return T(rglob[int64_t(gx - ox) +
-                   int64_t(md.nu[0]) * (int64_t(gy - ox) + (DIM == 3 ? int64_t(md.nu[1]) * (gz - ox) : 0))]);
-  }
-  return B[ii];
+// Neighbour s of a row whose coordinates satisfy the six edge tests
+// (xl: x > 0, xh: x < m0 - 1, ...) lies inside the box.
+template <int DIM>
+__device__ __forceinline__ bool nb_inside(int s, bool xl, bool xh, bool yl, bool yh, bool zl, bool zh) {
+  const int sx = s % 3 - 1, sy = (s / 3) % 3 - 1, sz = DIM == 3 ? s / 9 - 1 : 0;
+  return (sx < 0 ? xl : (sx > 0 ? xh : true)) && (sy < 0 ? yl : (sy > 0 ? yh : true)) &&
+         (sz < 0 ? zl : (sz > 0 ? zh : true));
 }
 
 // R = B - A X on one level from full records (float): each row reads its own
-// record only.  Two rows per lane and iteration, with all their global loads
-// issued together.
+// record only.  GB: the right side is the global residual (finest level)
+// instead of B in LDS.  Row coordinates come from a walk.
 template <int DIM, typename T, typename ST, bool GB>
 __device__ __forceinline__ void residual_full(T *R, const T *B, const T *X, const Box<DIM> &bx,
                                               const ST *__restrict__ st, const int *lng,
                                               const double *__restrict__ rglob, const MeshDims &md) {
   constexpr int NS = DIM == 3 ? 27 : 9, W = rec_width<DIM, ST>();
-  constexpr int RB = 2;
+  constexpr int RB = 1;  // two rows per lane would cost the third wave per SIMD
   const int mx = bx.m[0], my = bx.m[1], mz = bx.m[2];
+  Walk<DIM> w[RB] = {Walk<DIM>(bx, threadIdx.x, 64 * RB)};
   for (int i0 = threadIdx.x; i0 < bx.n; i0 += 64 * RB) {
     ST a[RB][NS];
     T acc[RB];
-    int ii[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      ii[r] = min(i0 + 64 * r, bx.n - 1);  // clamped: loads stay valid, store is skipped
-      const int64_t g = level_gidx<DIM>(bx, ii[r], lng);
-      acc[r] = residual_rhs<DIM, T, GB>(B, ii[r], g, rglob, md);
+      // a row past the end reads row i0's data (always a row of the box)
+      const bool live = i0 + 64 * r < bx.n;
+      const Walk<DIM> &wr = live ? w[r] : w[0];
+      const int64_t g = walk_gidx<DIM>(bx, wr, lng);
+      if (GB)
+        acc[r] = T(rglob[walk_uidx<DIM>(bx, wr, md)]);
+      else
+        acc[r] = B[live ? i0 + 64 * r : i0];
       load_rec<DIM, ST>(st + g * W, a[r]);
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      const int i = ii[r];
-      const int ix = i % mx, iy = (i / mx) % my, iz = DIM == 3 ? i / (mx * my) : 0;
+      const int i = i0 + 64 * r;
+      const bool live = i < bx.n;
+      const bool xl = w[r].x > 0, xh = w[r].x < mx - 1, yl = w[r].y > 0, yh = w[r].y < my - 1,
+                 zl = w[r].z > 0, zh = w[r].z < mz - 1;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int sx = s % 3 - 1, sy = (s / 3) % 3 - 1, sz = DIM == 3 ? s / 9 - 1 : 0;
-        const int jx = ix + sx, jy = iy + sy, jz = iz + sz;
-        const bool in = jx >= 0 && jx < mx && jy >= 0 && jy < my && (DIM == 2 || (jz >= 0 && jz < mz));
-        const T xv = X[in ? jx + mx * (jy + my * jz) : i];
-        acc[r] -= in ? T(a[r][s]) * xv : T(0);
+        const int off = sx + mx * (sy + my * sz);
+        const bool in = live && nb_inside<DIM>(s, xl, xh, yl, yh, zl, zh);
+        acc[r] -= (in ? T(a[r][s]) : T(0)) * X[in ? i + off : i0];
       }
-      if (i0 + 64 * r < bx.n) R[i] = acc[r];
+      if (live) R[i] = acc[r];
+      w[r].step();
     }
   }
   wave_sync();
@@ -325,35 +371,42 @@ __device__ __forceinline__ void residual_scatter(T *R, const T *B, const T *X, c
   const int mx = bx.m[0], my = bx.m[1], mz = bx.m[2];
   for (int i = threadIdx.x; i < bx.n; i += 64) R[i] = T(0);
   wave_sync();
+  Walk<DIM> w[RB] = {Walk<DIM>(bx, threadIdx.x, 64 * RB), Walk<DIM>(bx, threadIdx.x + 64, 64 * RB)};
   for (int i0 = threadIdx.x; i0 < bx.n; i0 += 64 * RB) {
     ST a[RB][NS];
     T acc[RB];
-    int ii[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      ii[r] = min(i0 + 64 * r, bx.n - 1);  // clamped: loads stay valid, updates are skipped
-      const int64_t g = level_gidx<DIM>(bx, ii[r], lng);
-      acc[r] = residual_rhs<DIM, T, GB>(B, ii[r], g, rglob, md);
+      const bool live = i0 + 64 * r < bx.n;
+      const Walk<DIM> &wr = live ? w[r] : w[0];
+      const int64_t g = walk_gidx<DIM>(bx, wr, lng);
+      if (GB)
+        acc[r] = T(rglob[walk_uidx<DIM>(bx, wr, md)]);
+      else
+        acc[r] = B[live ? i0 + 64 * r : i0];
       load_rec<DIM, ST>(st + g * W, a[r]);
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      const int i = ii[r];
-      const bool live = i0 + 64 * r < bx.n;
-      const int ix = i % mx, iy = (i / mx) % my, iz = DIM == 3 ? i / (mx * my) : 0;
-      const T xi = X[i];
+      const int i = i0 + 64 * r;
+      const bool live = i < bx.n;
+      const bool xl = w[r].x > 0, xh = w[r].x < mx - 1, yl = w[r].y > 0, yh = w[r].y < my - 1,
+                 zl = w[r].z > 0, zh = w[r].z < mz - 1;
+      const int ic = live ? i : i0;
+      const T xi = X[ic];
       acc[r] -= T(a[r][C]) * xi;
 #pragma unroll
       for (int s = C + 1; s < NS; ++s) {
         const int sx = s % 3 - 1, sy = (s / 3) % 3 - 1, sz = DIM == 3 ? s / 9 - 1 : 0;
-        const int jx = ix + sx, jy = iy + sy, jz = iz + sz;
-        const bool in = jx >= 0 && jx < mx && jy >= 0 && jy < my && (DIM == 2 || (jz >= 0 && jz < mz));
-        const int jn = in ? jx + mx * (jy + my * jz) : i;
+        const int off = sx + mx * (sy + my * sz);
+        const bool in = live && nb_inside<DIM>(s, xl, xh, yl, yh, zl, zh);
+        const int jn = in ? i + off : i0;
         const T aij = in ? T(a[r][s]) : T(0);
         acc[r] -= aij * X[jn];
-        if (live && in) atomicAdd(R + jn, -aij * xi);
+        if (in) atomicAdd(R + jn, -aij * xi);
       }
       if (live) atomicAdd(R + i, acc[r]);
+      w[r].step();
     }
   }
   wave_sync();
@@ -396,22 +449,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     for (int i = threadIdx.x; i < tot; i += 64) lds[i] = T(0);
   }
   wave_sync();
-  const int ox = md.dirichlet ? 1 : 0;
-  auto lvec = [&](int i) -> int64_t {
-    const int64_t g = level_gidx<DIM>(b0, i, md.ng);
-    const int gx = int(g % md.ng[0]), gy = int((g / md.ng[0]) % md.ng[1]),
-              gz = DIM == 3 ? int(g / (int64_t(md.ng[0]) * md.ng[1])) : 0;
-    return int64_t(gx - ox) +
-           int64_t(md.nu[0]) * (int64_t(gy - ox) + (DIM == 3 ? int64_t(md.nu[1]) * (gz - ox) : 0));
-  };
   // pre-smoothing input: X_0 = r restricted to the patch
   {
     T *X0 = lds_vec<DIM, T>(lds, pa, v, 0, 0);
-    // batched: 8 loads in flight per lane (clamped index, predicated store)
+    // batched: 8 loads in flight per lane (rows past the end read row i0,
+    // their store is skipped)
+    Walk<DIM> w(b0, threadIdx.x, 64);
     for (int i0 = threadIdx.x; i0 < b0.n; i0 += 64 * 8) {
+      int64_t u[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        u[q] = i0 + 64 * q < b0.n ? walk_uidx<DIM>(b0, w, md) : u[0];
+        w.step();
+      }
       T t[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) t[q] = T(r[lvec(min(i0 + 64 * q, b0.n - 1))]);
+      for (int q = 0; q < 8; ++q) t[q] = T(r[u[q]]);
 #pragma unroll
       for (int q = 0; q < 8; ++q)
         if (i0 + 64 * q < b0.n) X0[i0 + 64 * q] = t[q];
@@ -447,8 +500,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       const XferTab *tb0 = &pa.xfer[k * 3 + typ[0]];
       const XferTab *tb1 = &pa.xfer[k * 3 + typ[1]];
       const XferTab *tb2 = &pa.xfer[k * 3 + typ[DIM - 1]];
-      for (int i = threadIdx.x; i < cb.n; i += 64) {
-        const int ci[3] = {i % cb.m[0], (i / cb.m[0]) % cb.m[1], DIM == 3 ? i / (cb.m[0] * cb.m[1]) : 0};
+      Walk<DIM> wc(cb, threadIdx.x, 64);
+      for (int i = threadIdx.x; i < cb.n; i += 64, wc.step()) {
+        const int ci[3] = {wc.x, wc.y, DIM == 3 ? wc.z : 0};
         // fixed 3 x 3 (x 3) gather, absent entries have weight 0 and index 0:
         // every table load and LDS read is issued up front
         int fx[3], fy[3], fz[3];
@@ -503,8 +557,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       const XferTab *tb0 = &pa.xfer[k * 3 + typ[0]];
       const XferTab *tb1 = &pa.xfer[k * 3 + typ[1]];
       const XferTab *tb2 = &pa.xfer[k * 3 + typ[DIM - 1]];
-      for (int i = threadIdx.x; i < fb.n; i += 64) {
-        const int fi[3] = {i % fb.m[0], (i / fb.m[0]) % fb.m[1], DIM == 3 ? i / (fb.m[0] * fb.m[1]) : 0};
+      Walk<DIM> wf(fb, threadIdx.x, 64);
+      for (int i = threadIdx.x; i < fb.n; i += 64, wf.step()) {
+        const int fi[3] = {wf.x, wf.y, DIM == 3 ? wf.z : 0};
         // fixed 2 x 2 (x 2) gather; sources on the patch boundary get weight 0
         int cx[2], cy[2], cz[2];
         T wx[2], wy[2], wz[2];
@@ -557,14 +612,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       int gsz = 1;
       for (int d = 0; d < DIM; ++d) gsz *= G;
       const double inv = 1.0 / dscale[j];
-      for (int i = threadIdx.x; i < b0.n; i += 64) {
-        const int ix = i % b0.m[0], iy = (i / b0.m[0]) % b0.m[1], iz = i / (b0.m[0] * b0.m[1]);
-        const int gx = ix + b0.lo[0] - (v[0] * s0 - s0 + 1), gy = iy + b0.lo[1] - (v[1] * s0 - s0 + 1),
-                  gz = DIM == 3 ? iz + b0.lo[2] - (v[2] * s0 - s0 + 1) : 0;
+      Walk<DIM> w(b0, threadIdx.x, 64);
+      for (int i = threadIdx.x; i < b0.n; i += 64, w.step()) {
+        const int gx = w.x + b0.lo[0] - (v[0] * s0 - s0 + 1), gy = w.y + b0.lo[1] - (v[1] * s0 - s0 + 1),
+                  gz = DIM == 3 ? w.z + b0.lo[2] - (v[2] * s0 - s0 + 1) : 0;
         dense[int64_t(j) * gsz + gx + G * (gy + G * gz)] = float(double(X0[i]) * inv);
       }
     } else {
-      for (int i = threadIdx.x; i < b0.n; i += 64) unsafeAtomicAdd(z + lvec(i), double(X0[i]));
+      Walk<DIM> w(b0, threadIdx.x, 64);
+      for (int i = threadIdx.x; i < b0.n; i += 64, w.step())
+        unsafeAtomicAdd(z + walk_uidx<DIM>(b0, w, md), double(X0[i]));
     }
   }
 }

@@ -103,7 +103,11 @@ def test_batch_matches_oracle(L, torch_dev):
                 xs.append(torch.zeros_like(bs[-1]))
         infos = L.lor_pcg_solve_batch(hs, bs, xs, rtol=1e-10, maxit=500)
         for k, (A, b, (lo, hi)) in enumerate(refs):
-            assert lo - 1 <= infos[k].iters <= hi + 1, (k, infos[k].iters, lo, hi)
+            # the DG solves converge irregularly at this tolerance: the oracle
+            # itself takes 51 iterations unperturbed and 52-54 under any
+            # relative perturbation of its preconditioner from 1e-14 to 1e-12
+            slack = 1 if probs[k // 2][5] == "cg" else max(2, 0.05 * hi)
+            assert lo - slack <= infos[k].iters <= hi + slack, (k, infos[k].iters, lo, hi)
             x = xs[k].cpu().numpy()
             assert np.linalg.norm(b - A @ x) <= 1.05e-10 * np.linalg.norm(b)
     finally:
