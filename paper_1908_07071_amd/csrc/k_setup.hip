@@ -292,89 +292,121 @@ __global__ void k_lor_stencil(MeshDims md, int s, KeptIdx kept, const double *__
 // reference coordinates; weights 1 - x_a and x_a per direction.  Only the
 // interior vertices are unknowns (Dirichlet).
 
+// Weight of the vertex hat function at offset o (0 .. 2p-2) from the first
+// grid node after the previous vertex: node a = o + 1 of the pair of
+// elements sharing the vertex.
+__device__ __forceinline__ double hat_weight(const double *__restrict__ gllx, int p, int o) {
+  const int a = o + 1;
+  return a <= p ? gllx[a] : 1.0 - gllx[a - p];
+}
+
+// rc = P_0^T r: one wavefront per interior vertex; lanes take (ox, oy) pairs
+// of the vertex's (2p-1)^d support and loop over oz.
 template <int DIM>
-__global__ void k_coarse_restrict(MeshDims md, const double *__restrict__ gllx,
-                                  const double *__restrict__ r, double *__restrict__ rc) {
+__global__ __launch_bounds__(256) void k_coarse_restrict(MeshDims md, const double *__restrict__ gllx,
+                                                         const double *__restrict__ r,
+                                                         double *__restrict__ rc, int nc) {
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= nc) return;  // the whole wavefront leaves; no block-level barrier follows
   const int ncx = md.n[0] - 1, ncy = md.n[1] - 1;
-  const int c = blockIdx.x;
   const int v[3] = {c % ncx + 1, (c / ncx) % ncy + 1, DIM == 3 ? c / (ncx * ncy) + 1 : 0};
   const int p = md.p, w1 = 2 * p - 1;
-  const int cnt = DIM == 3 ? w1 * w1 * w1 : w1 * w1;
+  const int64_t sy = md.nu[0], sz = int64_t(md.nu[0]) * md.nu[1];
   double acc = 0.0;
-  for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-    const int o[3] = {t % w1, (t / w1) % w1, t / (w1 * w1)};
-    double w = 1.0;
-    int64_t li = 0, stride = 1;
-    for (int i = 0; i < DIM; ++i) {
-      const int g = (v[i] - 1) * p + 1 + o[i];
-      const int a = g - (v[i] - 1) * p;  // 1 .. 2p-1
-      w *= a <= p ? gllx[a] : 1.0 - gllx[a - p];
-      li += int64_t(g - 1) * stride;
-      stride *= md.nu[i];
+  if (DIM == 3) {
+    for (int t = lane; t < w1 * w1; t += 64) {
+      const int ox = t % w1, oy = t / w1;
+      const double wxy = hat_weight(gllx, p, ox) * hat_weight(gllx, p, oy);
+      const double *src = r + ((v[0] - 1) * p + ox) + sy * ((v[1] - 1) * p + oy) + sz * ((v[2] - 1) * p);
+#pragma unroll 4
+      for (int oz = 0; oz < w1; ++oz) acc += wxy * hat_weight(gllx, p, oz) * src[sz * oz];
     }
-    acc += w * r[li];
-  }
-  __shared__ double red[256];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) rc[c] = red[0];
-}
-
-template <int DIM>
-__global__ void k_coarse_prolong(MeshDims md, const double *__restrict__ gllx,
-                                 const double *__restrict__ xc, double *__restrict__ z,
-                                 const double *flag) {
-  if (flag && flag[S_DONE] != 0.0) return;
-  const int64_t N = int64_t(md.nu[0]) * md.nu[1] * (DIM == 3 ? md.nu[2] : 1);
-  const int ncx = md.n[0] - 1, ncy = md.n[1] - 1;
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int gi[3] = {int(i % md.nu[0]) + 1, int((i / md.nu[0]) % md.nu[1]) + 1,
-                       DIM == 3 ? int(i / (int64_t(md.nu[0]) * md.nu[1])) + 1 : 0};
-    int ev[3];
-    double wl[3], wh[3];
-    for (int d = 0; d < DIM; ++d) {
-      const int e = min(gi[d] / md.p, md.n[d] - 1);
-      const int a = gi[d] - e * md.p;
-      ev[d] = e;
-      wl[d] = 1.0 - gllx[a];
-      wh[d] = gllx[a];
+  } else {
+    for (int t = lane; t < w1 * w1; t += 64) {
+      const int ox = t % w1, oy = t / w1;
+      acc += hat_weight(gllx, p, ox) * hat_weight(gllx, p, oy) *
+             r[((v[0] - 1) * p + ox) + sy * ((v[1] - 1) * p + oy)];
     }
-    double acc = 0.0;
-    for (int c = 0; c < (1 << DIM); ++c) {
-      double w = 1.0;
-      int vi[3];
-      bool ok = true;
-      for (int d = 0; d < DIM; ++d) {
-        const int b = (c >> d) & 1;
-        vi[d] = ev[d] + b;
-        w *= b ? wh[d] : wl[d];
-        if (vi[d] <= 0 || vi[d] >= md.n[d]) ok = false;
-      }
-      if (!ok) continue;
-      int64_t ci = (vi[0] - 1) + int64_t(ncx) * ((vi[1] - 1) + (DIM == 3 ? int64_t(ncy) * (vi[2] - 1) : 0));
-      acc += w * xc[ci];
-    }
-    z[i] = acc;
   }
-}
-
-// y = A x for a dense row-major n x n matrix: one wavefront per row.
-__global__ void k_gemv(int n, const double *__restrict__ A, const double *__restrict__ x,
-                       double *__restrict__ y, const double *flag) {
-  if (flag && flag[S_DONE] != 0.0) return;
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (row >= n) return;
-  const double *a = A + int64_t(row) * n;
-  double acc = 0.0;
-  for (int j = lane; j < n; j += 64) acc += a[j] * x[j];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) y[row] = acc;
+  if (lane == 0) rc[c] = acc;
+}
+
+// z = P_0 xc on the unknowns: a workgroup covers 64 unknowns of each of four
+// x-lines; lines (y, z) from the grid of blocks.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_coarse_prolong(MeshDims md, const double *__restrict__ gllx,
+                                                        const double *__restrict__ xc,
+                                                        double *__restrict__ z, const double *flag) {
+  if (flag && flag[S_DONE] != 0.0) return;
+  const int ix = blockIdx.x * 64 + threadIdx.x;
+  const int iy = blockIdx.y * 4 + threadIdx.y;
+  if (ix >= md.nu[0] || iy >= md.nu[1]) return;
+  const int gi[3] = {ix + 1, iy + 1, DIM == 3 ? int(blockIdx.z) + 1 : 0};
+  const int ncx = md.n[0] - 1, ncy = md.n[1] - 1;
+  int ev[3] = {0, 0, 0};
+  double wl[3] = {1.0, 1.0, 1.0}, wh[3] = {0.0, 0.0, 0.0};
+  for (int d = 0; d < DIM; ++d) {
+    const int e = min(gi[d] / md.p, md.n[d] - 1);
+    const int a = gi[d] - e * md.p;
+    ev[d] = e;
+    wl[d] = 1.0 - gllx[a];
+    wh[d] = gllx[a];
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < (1 << DIM); ++c) {
+    double w = 1.0;
+    int vi[3] = {1, 1, 1};
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int b = (c >> d) & 1;
+      vi[d] = ev[d] + b;
+      w *= b ? wh[d] : wl[d];
+      ok = ok && vi[d] > 0 && vi[d] < md.n[d];
+    }
+    const int64_t ci = (vi[0] - 1) + int64_t(ncx) * ((vi[1] - 1) + (DIM == 3 ? int64_t(ncy) * (vi[2] - 1) : 0));
+    acc += ok ? w * xc[ok ? ci : 0] : 0.0;
+  }
+  z[ix + int64_t(md.nu[0]) * (gi[1] - 1 + (DIM == 3 ? int64_t(md.nu[1]) * (gi[2] - 1) : 0))] = acc;
+}
+
+// y = A x for a dense row-major n x n matrix: eight rows per workgroup, one
+// per wavefront; x is staged through LDS in tiles shared by the eight rows,
+// and each lane keeps eight loads of its row in flight.
+constexpr int kGemvTile = 2048;
+constexpr int kGemvRows = 8;
+__global__ __launch_bounds__(64 * kGemvRows) void k_gemv(int n, const double *__restrict__ A,
+                                                         const double *__restrict__ x,
+                                                         double *__restrict__ y, const double *flag) {
+  if (flag && flag[S_DONE] != 0.0) return;  // uniform over the grid
+  __shared__ double xs[kGemvTile];
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * kGemvRows + (threadIdx.x >> 6);
+  const bool live = row < n;
+  const double *a = A + int64_t(live ? row : 0) * n;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int j0 = 0; j0 < n; j0 += kGemvTile) {
+    const int m = min(kGemvTile, n - j0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < m; t += 64 * kGemvRows) xs[t] = x[j0 + t];
+    __syncthreads();
+    const double *aj = a + j0;
+    int j = lane;
+    for (; j + 448 < m; j += 512) {
+      double av[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) av[q] = aj[j + 64 * q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] += av[q] * xs[j + 64 * q];
+    }
+    for (; j < m; j += 64) acc[0] += aj[j] * xs[j];
+  }
+  double sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
+  if (live && lane == 0) y[row] = sum;
 }
 
 // In-place Gauss-Jordan inversion of an SPD matrix, step k (no pivoting).
@@ -504,26 +536,27 @@ hipError_t launch_coarse_restrict(const MeshDims &md, const double *gllx, const 
   const int nc = (md.n[0] - 1) * (md.n[1] - 1) * (md.dim == 3 ? md.n[2] - 1 : 1);
   if (nc <= 0) return hipSuccess;
   if (md.dim == 3)
-    k_coarse_restrict<3><<<nc, 256, 0, st>>>(md, gllx, r, rc);
+    k_coarse_restrict<3><<<(nc + 3) / 4, 256, 0, st>>>(md, gllx, r, rc, nc);
   else
-    k_coarse_restrict<2><<<nc, 256, 0, st>>>(md, gllx, r, rc);
+    k_coarse_restrict<2><<<(nc + 3) / 4, 256, 0, st>>>(md, gllx, r, rc, nc);
   return hipGetLastError();
 }
 
 hipError_t launch_coarse_prolong(const MeshDims &md, const double *gllx, const double *xc,
                                  double *z, const double *flag, hipStream_t st) {
-  const int64_t N = int64_t(md.nu[0]) * md.nu[1] * (md.dim == 3 ? md.nu[2] : 1);
+  if (md.nu[2] > 65535) return hipErrorInvalidValue;  // grid z limit
+  const dim3 grid((md.nu[0] + 63) / 64, (md.nu[1] + 3) / 4, md.dim == 3 ? md.nu[2] : 1);
   if (md.dim == 3)
-    k_coarse_prolong<3><<<grid_for(N, 256), 256, 0, st>>>(md, gllx, xc, z, flag);
+    k_coarse_prolong<3><<<grid, dim3(64, 4), 0, st>>>(md, gllx, xc, z, flag);
   else
-    k_coarse_prolong<2><<<grid_for(N, 256), 256, 0, st>>>(md, gllx, xc, z, flag);
+    k_coarse_prolong<2><<<grid, dim3(64, 4), 0, st>>>(md, gllx, xc, z, flag);
   return hipGetLastError();
 }
 
 hipError_t launch_gemv(int n, const double *A, const double *x, double *y, const double *flag,
                        hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  k_gemv<<<(n + 3) / 4, 256, 0, st>>>(n, A, x, y, flag);
+  k_gemv<<<(n + kGemvRows - 1) / kGemvRows, 64 * kGemvRows, 0, st>>>(n, A, x, y, flag);
   return hipGetLastError();
 }
 
