@@ -187,7 +187,8 @@ def learned_measure(L, torch, rtol, channels=32, train_seconds=90.0, n_test=32, 
     residuals of PCG iterates and Gaussian right-hand sides), judge it against
     the V-cycle on held-out patches, then solve on the n_test^3 test mesh
     (seed 3) with flexible CG to rtol: V-cycles (the plain fallback) against
-    the network standing in for every patch V-cycle."""
+    the network standing in for every patch V-cycle and against the network's
+    prediction as the start of each patch V-cycle."""
     import numpy as np
 
     from paper_1908_07071_amd import inputs
@@ -291,6 +292,19 @@ def learned_measure(L, torch, rtol, channels=32, train_seconds=90.0, n_test=32, 
                               "rel_res": info.rel_res, "rel_res_true": info.rel_res_true,
                               "s_per_iteration": tn / max(info.iters, 1), "maxit": maxit}
     print(f"[bench] learned: network FCG {info.iters} iters status {info.status} {tn:.2f} s "
+          f"rel_res {info.rel_res:.2e}", file=sys.stderr, flush=True)
+    # warm start: the network's prediction corrected by one V-cycle per patch
+    L.lor_nn_attach(h, nn, L.LOR_NN_WARMSTART)
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = L.lor_pcg_solve(h, b, x, rtol=rtol, maxit=maxit, check=False)
+    torch.cuda.synchronize()
+    tw = time.perf_counter() - t0
+    out["network_warmstart"] = {"iters": info.iters, "converged": info.status == L.LOR_OK, "s": tw,
+                                "rel_res": info.rel_res, "rel_res_true": info.rel_res_true,
+                                "s_per_iteration": tw / max(info.iters, 1), "maxit": maxit}
+    print(f"[bench] learned: warm-start FCG {info.iters} iters status {info.status} {tw:.2f} s "
           f"rel_res {info.rel_res:.2e}", file=sys.stderr, flush=True)
     L.lor_nn_attach(h, None, L.LOR_NN_OFF)
     L.lor_nn_free(nn)

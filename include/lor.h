@@ -199,8 +199,11 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
  * at once; a handle with an attached network is refused by
  * lor_pcg_solve_batch. */
 typedef struct lor_nn lor_nn_t;
-#define LOR_NN_OFF      0   /* patch V-cycles (eq. as) */
-#define LOR_NN_REPLACE  1   /* the network stands in for every patch V-cycle */
+#define LOR_NN_OFF       0   /* patch V-cycles (eq. as) */
+#define LOR_NN_REPLACE   1   /* the network stands in for every patch V-cycle */
+#define LOR_NN_WARMSTART 2   /* y_j = s_j net(r_j / s_j) starts the patch solve:
+                                z_j = y_j + V_j(r_j - A_j y_j), A_j the patch's
+                                level-0 LOR matrix (a V-cycle-corrected guess) */
 
 int lor_nn_param_count(int channels, int64_t *count);
 /* channels: multiple of 16, 16..64.  max_batch: patches per network pass
@@ -225,8 +228,10 @@ int lor_nn_gradients(lor_nn_t *nn, const float *X_dev, const float *T_dev, int n
  * the loss before the step. */
 int lor_nn_train_step(lor_nn_t *nn, const float *X_dev, const float *T_dev, int nb, double lr,
                       double *loss, void *stream);
-/* Use nn in h's preconditioner (LOR_NN_REPLACE) or not (LOR_NN_OFF, nn may
- * be NULL).  The network must have been created for h. */
+/* Use nn in h's preconditioner (LOR_NN_REPLACE or LOR_NN_WARMSTART) or not
+ * (LOR_NN_OFF, nn may be NULL).  The network must have been created for h.
+ * Either mode makes the preconditioner nonlinear: lor_pcg_solve then runs
+ * flexible CG. */
 int lor_nn_attach(lor_handle_t *h, lor_nn_t *nn, int mode);
 int lor_nn_free(lor_nn_t *nn);
 /* The network's BF16 matrix product, exposed for tests: C[M][ldc] (float32,

@@ -192,6 +192,32 @@ def preconditioner_replace(B: "_sw.SchwarzLOR", params, r: np.ndarray) -> np.nda
     return z
 
 
+def preconditioner_warmstart(B: "_sw.SchwarzLOR", params, r: np.ndarray, predictor=None) -> np.ndarray:
+    """z = coarse correction + sum_j R_j^T (y_j + V_j(r_j - A_j y_j)): the
+    prediction y_j = scale_j net(r_j / scale_j) starts each patch solve and
+    one V-cycle corrects it (A_j the patch's level-0 LOR matrix).
+    predictor(j, P, r_j) -> y_j replaces the network when given (pins)."""
+    mesh, p = B.H.mesh, B.H.p
+    G = 2 * p - 1
+    if predictor is None:
+        X, _, scale = _inputs_only(B, r)
+        y, _ = forward(params, X, G)
+    z = B.coarse.apply(r) if B.coarse is not None else np.zeros_like(r)
+    for j, P in enumerate(B.patches):
+        lv = P.levels[0]
+        if lv["graph"] is None:
+            continue
+        u = B.fnum[lv["flat"]]
+        rj = r[u]
+        if predictor is None:
+            _, q = patch_grid(mesh, p, P.v)
+            yj = scale[j] * y[j, q]
+        else:
+            yj = predictor(j, P, rj)
+        z[u] += yj + P.solve(rj - lv["A"] @ yj)
+    return z
+
+
 def _inputs_only(B, r):
     mesh, p = B.H.mesh, B.H.p
     G = 2 * p - 1

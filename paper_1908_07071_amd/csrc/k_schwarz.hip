@@ -111,14 +111,15 @@ __device__ __forceinline__ int64_t walk_uidx(const Box<DIM> &bx, const Walk<DIM>
   return int64_t(bx.lo[0] + w.x - ox) + int64_t(md.nu[0]) * t;
 }
 
-// LDS layout of one patch: level 0 holds X, R; level k > 0 holds X, B, R.
-// which: 0 = X, 1 = B, 2 = R.
-template <int DIM, typename T>
+// LDS layout of one patch: level 0 holds X, R (the right side is the global
+// residual); level k > 0 holds X, B, R.  With a warm start (WARM) level 0
+// also holds its own right side B.  which: 0 = X, 1 = B, 2 = R.
+template <int DIM, typename T, bool WARM>
 __device__ __forceinline__ T *lds_vec(T *lds, const PatchArgs &pa, const int *v, int k, int which) {
   int off = 0;
-  for (int q = 0; q < k; ++q) off += (q == 0 ? 2 : 3) * make_box<DIM>(pa, v, q).n;
+  for (int q = 0; q < k; ++q) off += (q == 0 && !WARM ? 2 : 3) * make_box<DIM>(pa, v, q).n;
   const int n = make_box<DIM>(pa, v, k).n;
-  if (k == 0) return lds + (which == 0 ? 0 : n);
+  if (k == 0 && !WARM) return lds + (which == 0 ? 0 : n);
   return lds + off + which * n;
 }
 
@@ -426,15 +427,21 @@ __device__ __forceinline__ void residual(T *R, const T *B, const T *X, const Box
     residual_full<DIM, T, ST, GB>(R, B, X, bx, st, lng, rglob, md);
 }
 
-template <int DIM, typename T, typename ST, int W>
+// One wavefront per patch.  Modes: scatter-add the correction into z (the
+// preconditioner); write it into the patch grid (dense, training data); or,
+// with WARM, start from a prediction y_j of the patch solve (patch-grid
+// values wy[block][G^d] times dscale[block], patches jfirst + block) and
+// scatter y_j + V_j(r_j - A_j y_j).
+template <int DIM, typename T, typename ST, int W, bool WARM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_patch_vcycle(PatchArgs pa, const double *__restrict__ r,
                                                      double *__restrict__ z, const double *flag,
                                                      float *__restrict__ dense,
-                                                     const double *__restrict__ dscale) {
+                                                     const double *__restrict__ dscale,
+                                                     const float *__restrict__ wy, int jfirst) {
   if (flag && flag[S_DONE] != 0.0) return;
   extern __shared__ __align__(16) char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
-  const int j = blockIdx.x;
+  const int j = jfirst + int(blockIdx.x);
   const int L = pa.nlev;
   const MeshDims &md = pa.md;
   const int v[3] = {j % pa.nv[0], (j / pa.nv[0]) % pa.nv[1],
@@ -445,13 +452,33 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   if (b0.n <= 0) return;
   {
     int tot = 0;
-    for (int k = 0; k < L; ++k) tot += (k == 0 ? 2 : 3) * make_box<DIM>(pa, v, k).n;
+    for (int k = 0; k < L; ++k) tot += (k == 0 && !WARM ? 2 : 3) * make_box<DIM>(pa, v, k).n;
     for (int i = threadIdx.x; i < tot; i += 64) lds[i] = T(0);
   }
   wave_sync();
+  // patch-grid index of a level-0 row: grid point g_d = node - (v_d p - p + 1)
+  auto grid_q = [&](const Walk<DIM> &w) {
+    const int s0 = pa.s[0], G = 2 * s0 - 1;
+    const int gx = w.x + b0.lo[0] - (v[0] * s0 - s0 + 1), gy = w.y + b0.lo[1] - (v[1] * s0 - s0 + 1),
+              gz = DIM == 3 ? w.z + b0.lo[2] - (v[2] * s0 - s0 + 1) : 0;
+    return gx + G * (gy + G * gz);
+  };
+  int G3 = 1;
+  for (int d = 0; d < DIM; ++d) G3 *= 2 * pa.s[0] - 1;
+  if (WARM) {
+    // X_0 = y_j, then the level-0 right side B_0 = r_j - A_j y_j
+    T *X0 = lds_vec<DIM, T, WARM>(lds, pa, v, 0, 0);
+    T *B0 = lds_vec<DIM, T, WARM>(lds, pa, v, 0, 1);
+    const T sc = T(dscale[blockIdx.x]);
+    const float *yj = wy + int64_t(blockIdx.x) * G3;
+    Walk<DIM> w(b0, threadIdx.x, 64);
+    for (int i = threadIdx.x; i < b0.n; i += 64, w.step()) X0[i] = T(yj[grid_q(w)]) * sc;
+    wave_sync();
+    residual<DIM, T, ST, true>(B0, nullptr, X0, b0, reinterpret_cast<const ST *>(pa.stencil[0]), pa.lng[0], r, md);
+  } else {
   // pre-smoothing input: X_0 = r restricted to the patch
   {
-    T *X0 = lds_vec<DIM, T>(lds, pa, v, 0, 0);
+    T *X0 = lds_vec<DIM, T, WARM>(lds, pa, v, 0, 0);
     // batched: 8 loads in flight per lane (rows past the end read row i0,
     // their store is skipped)
     Walk<DIM> w(b0, threadIdx.x, 64);
@@ -471,6 +498,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
   }
   wave_sync();
+  }
 
   const int nf = L - 1;
   const int64_t fbase = int64_t(j) * (nf > 0 ? nf : 1);
@@ -479,24 +507,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   for (int k = 0; k < nf; ++k) {
     const Box<DIM> fb = make_box<DIM>(pa, v, k);
     if (fb.n <= 0) break;
-    T *Xk = lds_vec<DIM, T>(lds, pa, v, k, 0);
-    T *Bk = k > 0 ? lds_vec<DIM, T>(lds, pa, v, k, 1) : nullptr;
-    T *Rk = lds_vec<DIM, T>(lds, pa, v, k, 2);
+    T *Xk = lds_vec<DIM, T, WARM>(lds, pa, v, k, 0);
+    T *Bk = (k > 0 || WARM) ? lds_vec<DIM, T, WARM>(lds, pa, v, k, 1) : nullptr;
+    T *Rk = lds_vec<DIM, T, WARM>(lds, pa, v, k, 2);
     const char *bf = pa.fac + pa.fac_off[2 * (fbase + k)];
     const char *bb = pa.fac + pa.fac_off[2 * (fbase + k) + 1];
-    if (k > 0) {
+    if (k > 0 || WARM) {
       for (int i = threadIdx.x; i < fb.n; i += 64) Xk[i] = Bk[i];
       wave_sync();
     }
     sweep<T, true>(Xk, bf);
     sweep<T, false>(Xk, bb);
-    if (k == 0)
+    if (k == 0 && !WARM)
       residual<DIM, T, ST, true>(Rk, Bk, Xk, fb, stn[k], pa.lng[k], r, md);
     else
       residual<DIM, T, ST, false>(Rk, Bk, Xk, fb, stn[k], pa.lng[k], r, md);
     const Box<DIM> cb = make_box<DIM>(pa, v, k + 1);
     if (cb.n > 0) {
-      T *Bc = lds_vec<DIM, T>(lds, pa, v, k + 1, 1);
+      T *Bc = lds_vec<DIM, T, WARM>(lds, pa, v, k + 1, 1);
       const XferTab *tb0 = &pa.xfer[k * 3 + typ[0]];
       const XferTab *tb1 = &pa.xfer[k * 3 + typ[1]];
       const XferTab *tb2 = &pa.xfer[k * 3 + typ[DIM - 1]];
@@ -536,8 +564,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if (bc.n == 1 && threadIdx.x == 0) {
       const int64_t g = level_gidx<DIM>(bc, 0, pa.lng[kc]);
       constexpr int C = DIM == 3 ? 13 : 4;
-      T *Xc = lds_vec<DIM, T>(lds, pa, v, kc, 0);
-      const T rhs = kc == 0 ? Xc[0] : lds_vec<DIM, T>(lds, pa, v, kc, 1)[0];
+      T *Xc = lds_vec<DIM, T, WARM>(lds, pa, v, kc, 0);
+      const T rhs = (kc == 0 && !WARM) ? Xc[0] : lds_vec<DIM, T, WARM>(lds, pa, v, kc, 1)[0];
       Xc[0] = rhs / T(stn[kc][g * rec_width<DIM, ST>() + rec_centre<DIM, ST>()]);
     }
     wave_sync();
@@ -546,14 +574,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   for (int k = nf - 1; k >= 0; --k) {
     const Box<DIM> fb = make_box<DIM>(pa, v, k);
     if (fb.n <= 0) continue;
-    T *Xk = lds_vec<DIM, T>(lds, pa, v, k, 0);
-    T *Bk = k > 0 ? lds_vec<DIM, T>(lds, pa, v, k, 1) : nullptr;
-    T *Rk = lds_vec<DIM, T>(lds, pa, v, k, 2);
+    T *Xk = lds_vec<DIM, T, WARM>(lds, pa, v, k, 0);
+    T *Bk = (k > 0 || WARM) ? lds_vec<DIM, T, WARM>(lds, pa, v, k, 1) : nullptr;
+    T *Rk = lds_vec<DIM, T, WARM>(lds, pa, v, k, 2);
     const char *bf = pa.fac + pa.fac_off[2 * (fbase + k)];
     const char *bb = pa.fac + pa.fac_off[2 * (fbase + k) + 1];
     const Box<DIM> cb = make_box<DIM>(pa, v, k + 1);
     if (cb.n > 0) {
-      const T *Xc = lds_vec<DIM, T>(lds, pa, v, k + 1, 0);
+      const T *Xc = lds_vec<DIM, T, WARM>(lds, pa, v, k + 1, 0);
       const XferTab *tb0 = &pa.xfer[k * 3 + typ[0]];
       const XferTab *tb1 = &pa.xfer[k * 3 + typ[1]];
       const XferTab *tb2 = &pa.xfer[k * 3 + typ[DIM - 1]];
@@ -593,7 +621,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       }
       wave_sync();
     }
-    if (k == 0)
+    if (k == 0 && !WARM)
       residual<DIM, T, ST, true>(Rk, Bk, Xk, fb, stn[k], pa.lng[k], r, md);
     else
       residual<DIM, T, ST, false>(Rk, Bk, Xk, fb, stn[k], pa.lng[k], r, md);
@@ -606,22 +634,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   // network) write it divided by the patch's scale into the patch's
   // (2p-1)^d grid: grid point g_d = level-0 node - (v_d p - p + 1)
   {
-    const T *X0 = lds_vec<DIM, T>(lds, pa, v, 0, 0);
+    const T *X0 = lds_vec<DIM, T, WARM>(lds, pa, v, 0, 0);
     if (dense) {
-      const int s0 = pa.s[0], G = 2 * s0 - 1;
-      int gsz = 1;
-      for (int d = 0; d < DIM; ++d) gsz *= G;
       const double inv = 1.0 / dscale[j];
       Walk<DIM> w(b0, threadIdx.x, 64);
-      for (int i = threadIdx.x; i < b0.n; i += 64, w.step()) {
-        const int gx = w.x + b0.lo[0] - (v[0] * s0 - s0 + 1), gy = w.y + b0.lo[1] - (v[1] * s0 - s0 + 1),
-                  gz = DIM == 3 ? w.z + b0.lo[2] - (v[2] * s0 - s0 + 1) : 0;
-        dense[int64_t(j) * gsz + gx + G * (gy + G * gz)] = float(double(X0[i]) * inv);
-      }
+      for (int i = threadIdx.x; i < b0.n; i += 64, w.step())
+        dense[int64_t(j) * G3 + grid_q(w)] = float(double(X0[i]) * inv);
     } else {
       Walk<DIM> w(b0, threadIdx.x, 64);
-      for (int i = threadIdx.x; i < b0.n; i += 64, w.step())
-        unsafeAtomicAdd(z + walk_uidx<DIM>(b0, w, md), double(X0[i]));
+      if (WARM) {
+        const double sc = dscale[blockIdx.x];
+        const float *yj = wy + int64_t(blockIdx.x) * G3;
+        for (int i = threadIdx.x; i < b0.n; i += 64, w.step())
+          unsafeAtomicAdd(z + walk_uidx<DIM>(b0, w, md), double(X0[i]) + double(yj[grid_q(w)]) * sc);
+      } else {
+        for (int i = threadIdx.x; i < b0.n; i += 64, w.step())
+          unsafeAtomicAdd(z + walk_uidx<DIM>(b0, w, md), double(X0[i]));
+      }
     }
   }
 }
@@ -629,39 +658,64 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 // gfx950: 160 KB of LDS per CU, all of it addressable by one workgroup.
 constexpr int kMaxDynLds = 160 * 1024;
 
-template <int DIM, typename T, typename ST>
+template <int DIM, typename T, typename ST, bool WARM>
 hipError_t prepare_t() {
   constexpr int W = DIM == 3 ? 26 : 8;
-  return hipFuncSetAttribute((const void *)k_patch_vcycle<DIM, T, ST, W>,
+  return hipFuncSetAttribute((const void *)k_patch_vcycle<DIM, T, ST, W, WARM>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
 }
 
-template <int DIM, typename T, typename ST>
+// LDS values per patch: the largest patch's, plus its level-0 right side
+// with a warm start
+template <int DIM, bool WARM>
+size_t lds_values(const PatchArgs &pa) {
+  size_t n0 = 1;
+  for (int d = 0; d < DIM; ++d) n0 *= size_t(2 * pa.s[0] - 1);
+  return size_t(pa.lds_total) + (WARM ? n0 : 0);
+}
+
+template <int DIM, typename T, typename ST, bool WARM>
 hipError_t launch_t(const PatchArgs &pa, int npatch, const double *r, double *z, const double *flag,
-                    float *dense, const double *dscale, hipStream_t st) {
+                    float *dense, const double *dscale, const float *wy, int jfirst, hipStream_t st) {
   constexpr int W = DIM == 3 ? 26 : 8;
-  const size_t lds = size_t(pa.lds_total) * sizeof(T);
+  const size_t lds = lds_values<DIM, WARM>(pa) * sizeof(T);
   if (lds > size_t(kMaxDynLds)) return hipErrorInvalidValue;
-  k_patch_vcycle<DIM, T, ST, W><<<npatch, 64, lds, st>>>(pa, r, z, flag, dense, dscale);
+  if (npatch <= 0) return hipSuccess;
+  k_patch_vcycle<DIM, T, ST, W, WARM><<<npatch, 64, lds, st>>>(pa, r, z, flag, dense, dscale, wy, jfirst);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t prepare_patch_vcycle(const PatchArgs &pa) {
-  if (pa.md.dim == 3) return pa.fp32 ? prepare_t<3, float, float>() : prepare_t<3, double, double>();
-  return pa.fp32 ? prepare_t<2, float, float>() : prepare_t<2, double, double>();
+  if (pa.md.dim == 3) {
+    hipError_t e = pa.fp32 ? prepare_t<3, float, float, false>() : prepare_t<3, double, double, false>();
+    if (e != hipSuccess) return e;
+    return pa.fp32 ? prepare_t<3, float, float, true>() : prepare_t<3, double, double, true>();
+  }
+  return pa.fp32 ? prepare_t<2, float, float, false>() : prepare_t<2, double, double, false>();
 }
 
 hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r, double *z,
                                const double *flag, hipStream_t st, float *dense,
                                const double *dscale) {
   if (pa.fp32) {
-    if (pa.md.dim == 3) return launch_t<3, float, float>(pa, npatch, r, z, flag, dense, dscale, st);
-    return launch_t<2, float, float>(pa, npatch, r, z, flag, dense, dscale, st);
+    if (pa.md.dim == 3)
+      return launch_t<3, float, float, false>(pa, npatch, r, z, flag, dense, dscale, nullptr, 0, st);
+    return launch_t<2, float, float, false>(pa, npatch, r, z, flag, dense, dscale, nullptr, 0, st);
   }
-  if (pa.md.dim == 3) return launch_t<3, double, double>(pa, npatch, r, z, flag, dense, dscale, st);
-  return launch_t<2, double, double>(pa, npatch, r, z, flag, dense, dscale, st);
+  if (pa.md.dim == 3)
+    return launch_t<3, double, double, false>(pa, npatch, r, z, flag, dense, dscale, nullptr, 0, st);
+  return launch_t<2, double, double, false>(pa, npatch, r, z, flag, dense, dscale, nullptr, 0, st);
+}
+
+hipError_t launch_patch_vcycle_warm(const PatchArgs &pa, int first, int count, const double *r,
+                                    double *z, const float *y, const double *scale,
+                                    const double *flag, hipStream_t st) {
+  if (pa.md.dim != 3 || !y || !scale || first < 0 || count < 0) return hipErrorInvalidValue;
+  if (pa.fp32)
+    return launch_t<3, float, float, true>(pa, count, r, z, flag, nullptr, scale, y, first, st);
+  return launch_t<3, double, double, true>(pa, count, r, z, flag, nullptr, scale, y, first, st);
 }
 
 }  // namespace lor

@@ -483,6 +483,7 @@ int apply_P_cg(lor_handle *h, Work &w, const double *r, double *z, const double 
   }
   Span sp(h, LOR_T_PATCH, st);
   if (h->nn && h->nn_mode == LOR_NN_REPLACE) return nn_apply_patches(h->nn, r, z, flag, st);
+  if (h->nn && h->nn_mode == LOR_NN_WARMSTART) return nn_apply_patches_warm(h->nn, r, z, flag, st);
   HIPCHK(launch_patch_vcycle(h->pa, h->J, r, z, flag, st));
   return LOR_OK;
 }

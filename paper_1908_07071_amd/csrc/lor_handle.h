@@ -100,3 +100,5 @@ struct lor_handle {
 // Patches of the Schwarz preconditioner through the attached network:
 // z += sum_j R_j^T s_j net(R_j r / s_j) (nn_api.cpp).
 int nn_apply_patches(lor_nn *nn, const double *r, double *z, const double *flag, hipStream_t st);
+int nn_apply_patches_warm(lor_nn *nn, const double *r, double *z, const double *flag,
+                          hipStream_t st);

@@ -197,6 +197,12 @@ hipError_t prepare_patch_vcycle(const PatchArgs &pa);
 hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r, double *z,
                                const double *flag, hipStream_t st, float *dense = nullptr,
                                const double *dscale = nullptr);
+// Warm start of the patch V-cycles for patches first .. first + count - 1
+// (3D): y [count][(2p-1)^3] predictions on the patch grid, scale [count];
+// z += y_j + V_j(r_j - A_j y_j) (scaled) for each.
+hipError_t launch_patch_vcycle_warm(const PatchArgs &pa, int first, int count, const double *r,
+                                    double *z, const float *y, const double *scale,
+                                    const double *flag, hipStream_t st);
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t st);
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st);
 // slot-major float64 stencil (3^dim x npts) -> point-major records

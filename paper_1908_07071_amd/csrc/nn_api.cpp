@@ -136,6 +136,21 @@ int nn_apply_patches(lor_nn *nn, const double *r, double *z, const double *flag,
   return LOR_OK;
 }
 
+// Warm start: per chunk of patches, the network's prediction y_j (scaled by
+// s_j) starts the patch V-cycle, which adds y_j + V_j(r_j - A_j y_j) into z.
+int nn_apply_patches_warm(lor_nn *nn, const double *r, double *z, const double *flag,
+                          hipStream_t st) {
+  const int J = nn->h->J;
+  for (int first = 0; first < J; first += nn->maxb) {
+    const int cnt = std::min(nn->maxb, J - first);
+    NCHK(nn_gather(nn->h->md, first, cnt, r, nn->Xbuf, nn->sbuf, flag, st));
+    int rc = forward(nn, nn->Xbuf, cnt, flag, st);
+    if (rc != LOR_OK) return rc;
+    NCHK(launch_patch_vcycle_warm(nn->h->pa, first, cnt, r, z, nn->y, nn->sbuf, flag, st));
+  }
+  return LOR_OK;
+}
+
 extern "C" {
 
 int lor_nn_param_count(int channels, int64_t *count) {
@@ -274,8 +289,9 @@ int lor_nn_train_step(lor_nn_t *nn, const float *X, const float *T, int nb, doub
 }
 
 int lor_nn_attach(lor_handle_t *h, lor_nn_t *nn, int mode) {
-  if (!h || (mode != LOR_NN_OFF && mode != LOR_NN_REPLACE)) return LOR_EINVAL;
-  if (mode == LOR_NN_REPLACE && (!nn || nn->h != h)) return LOR_EINVAL;
+  if (!h || (mode != LOR_NN_OFF && mode != LOR_NN_REPLACE && mode != LOR_NN_WARMSTART))
+    return LOR_EINVAL;
+  if (mode != LOR_NN_OFF && (!nn || nn->h != h)) return LOR_EINVAL;
   h->nn = mode == LOR_NN_OFF ? nullptr : nn;
   h->nn_mode = mode;
   return LOR_OK;

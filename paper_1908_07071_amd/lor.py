@@ -34,7 +34,7 @@ EXPORTED = [
     "lor_nn_forward", "lor_nn_gradients", "lor_nn_train_step", "lor_nn_attach", "lor_nn_free",
     "lor_bf16_gemm",
 ]
-LOR_NN_OFF, LOR_NN_REPLACE = 0, 1
+LOR_NN_OFF, LOR_NN_REPLACE, LOR_NN_WARMSTART = 0, 1, 2
 LOR_T_APPLY_A, LOR_T_PATCH, LOR_T_COARSE = 0, 1, 2
 
 

@@ -108,3 +108,34 @@ def test_training_data_scale_free():
         _, q = nn.patch_grid(mesh, 3, P.v)
         z[B.fnum[lv["flat"]]] += s1[j] * T1[j, q]
     assert np.allclose(z, B.apply(r, with_coarse=False), rtol=1e-12, atol=1e-14)
+
+
+def test_warmstart_reduces_to_known_preconditioners():
+    """WARMSTART z_j = y_j + V_j(r_j - A_j y_j): a zero network gives the
+    V-cycle Schwarz preconditioner; an exact local prediction y_j = A_j^-1 r_j
+    leaves nothing for the V-cycle and gives Schwarz with exact local solves;
+    a V-cycle prediction gives two V-cycle Richardson steps per patch."""
+    V = inputs.structured_vertices(3, 2, 0.1, seed=8)
+    mesh = M.make_mesh(3, [2, 2, 2], V)
+    p = 3
+    B = S.SchwarzLOR(mesh, p)
+    r = inputs.gaussian_rhs(B.Kh.shape[0], 9)
+    zero = [(np.zeros(s), np.zeros(s[1])) for s in nn.layer_shapes(4)]
+    assert np.allclose(nn.preconditioner_warmstart(B, zero, r), B.apply(r), rtol=1e-13, atol=1e-14)
+    exact = S.SchwarzLOR(mesh, p, exact_local=True)
+    z = nn.preconditioner_warmstart(B, None, r,
+                                    predictor=lambda j, P, rj: np.linalg.solve(P.levels[0]["A"], rj))
+    assert np.allclose(z, exact.apply(r), rtol=1e-11, atol=1e-13)
+    def two_steps(j, P, rj):
+        return P.solve(rj)
+    z2 = nn.preconditioner_warmstart(B, None, r, predictor=two_steps)
+    ref = B.coarse.apply(r)
+    for P in B.patches:
+        lv = P.levels[0]
+        if lv["graph"] is None:
+            continue
+        u = B.fnum[lv["flat"]]
+        x1 = P.solve(r[u])
+        ref[u] += x1 + P.solve(r[u] - lv["A"] @ x1)
+    assert np.allclose(z2, ref, rtol=1e-13, atol=1e-14)
+    assert not np.allclose(z2, B.apply(r), rtol=1e-6)

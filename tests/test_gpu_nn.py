@@ -135,7 +135,9 @@ def test_gradients_match_oracle(L, torch_dev):
 def test_training_and_replace_preconditioner(L, torch_dev):
     """Adam lowers the loss on data the method generates; the network then
     stands in for the patch V-cycles (parity with the float64 reference
-    preconditioner at bfloat16 accuracy), and flexible CG still converges."""
+    preconditioner at bfloat16 accuracy), and flexible CG still converges;
+    as a warm start of the patch V-cycles it matches the float64 reference
+    warm start and flexible CG converges in about the V-cycle's iterations."""
     torch = torch_dev
     h, mesh, p = _problem(L)
     params = inputs.nn_initial_params(C, seed=5)
@@ -173,10 +175,24 @@ def test_training_and_replace_preconditioner(L, torch_dev):
         info = L.lor_pcg_solve(h, rt, x, rtol=1e-6, maxit=400, check=False)
         print("FCG with the network:", info.iters, info.status, flush=True)
         assert info.status in (L.LOR_OK, L.LOR_ENOCONV)
+        # warm start: the network's prediction corrected by one V-cycle per
+        # patch; the V-cycle damps the network's BF16 error
+        L.lor_nn_attach(h, nn, L.LOR_NN_WARMSTART)
+        L.lor_apply_P(h, rt, z)
+        torch.cuda.synchronize()
+        zw = ONN.preconditioner_warmstart(B, ONN.unflatten(wn, shapes), rin)
+        errw = np.linalg.norm(z.cpu().numpy() - zw) / np.linalg.norm(zw)
+        print("warm start parity", errw, flush=True)
+        assert errw <= 3e-2, errw
+        x.zero_()
+        infow = L.lor_pcg_solve(h, rt, x, rtol=1e-6, maxit=400, check=False)
+        print("FCG with the warm start:", infow.iters, infow.status, flush=True)
+        assert infow.status == L.LOR_OK
         L.lor_nn_attach(h, None, L.LOR_NN_OFF)
         x.zero_()
         info0 = L.lor_pcg_solve(h, rt, x, rtol=1e-6, maxit=400)
         assert info0.status == L.LOR_OK
+        assert infow.iters <= 1.5 * info0.iters + 3, (infow.iters, info0.iters)
     finally:
         L.lor_nn_free(nn)
         L.lor_free(h)
