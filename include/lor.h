@@ -231,7 +231,8 @@ int lor_nn_train_step(lor_nn_t *nn, const float *X_dev, const float *T_dev, int 
 /* Use nn in h's preconditioner (LOR_NN_REPLACE or LOR_NN_WARMSTART) or not
  * (LOR_NN_OFF, nn may be NULL).  The network must have been created for h.
  * Either mode makes the preconditioner nonlinear: lor_pcg_solve then runs
- * flexible CG. */
+ * flexible CG.  The first warm-start attach allocates the predictions of
+ * every patch, J (2p-1)^3 floats and J doubles (LOR_ENOMEM on failure). */
 int lor_nn_attach(lor_handle_t *h, lor_nn_t *nn, int mode);
 int lor_nn_free(lor_nn_t *nn);
 /* The network's BF16 matrix product, exposed for tests: C[M][ldc] (float32,

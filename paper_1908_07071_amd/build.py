@@ -31,6 +31,7 @@ SOURCES = [
     ("k_dg.hip", []),
     ("coarse_inverse.cpp", []),
     ("k_nn.hip", []),
+    ("k_nnconv.hip", []),
     ("nn_api.cpp", []),
 ]
 

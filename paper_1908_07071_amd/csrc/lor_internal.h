@@ -238,6 +238,17 @@ hipError_t nn_gather(const MeshDims &md, int first, int count, const double *r, 
 hipError_t nn_scatter(const MeshDims &md, int first, int count, const float *y,
                       const double *scale, double *z, const double *flag, hipStream_t st);
 hipError_t nn_fill(float *x, int64_t n, float v, hipStream_t st);
+// Fused implicit-GEMM convolution layer (layer 0: 2 -> C channels, 1: C -> C,
+// 2: C -> 1 masked output y) for C in {16, 32} and 3 <= G <= 15: zout
+// [rows][Np] pre-activations (may be NULL), aout [rows][C] bf16 ReLU output
+// of layers 0 and 1, y [rows] of layer 2 (X: the network input, for the mask).
+bool nn_conv_supported(int channels, int G);
+hipError_t nn_conv_prepare(int channels);
+// Wf: the layer's weights in MFMA fragment order (nn_conv_frag of Wb [Kp][Np]).
+hipError_t nn_conv_frag(const uint16_t *Wb, int Kp, int Np, uint16_t *Wf, hipStream_t st);
+hipError_t nn_conv_layer(int channels, int layer, const uint16_t *ain, int nb, int G,
+                         const uint16_t *Wf, const float *bias, float *zout, uint16_t *aout,
+                         const float *X, float *y, const double *flag, hipStream_t st);
 
 // Krylov helpers.  Scalars live in a small device array.
 enum Scal { S_RHO = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_TOL2, S_DONE, S_ITERS, S_FAIL,

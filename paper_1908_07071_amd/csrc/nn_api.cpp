@@ -17,13 +17,17 @@ struct lor_nn {
   int64_t nparam = 0, npad_max = 0;
   float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
   uint16_t *Wb[3] = {};
+  uint16_t *Wf[3] = {};  // fused path: weights in MFMA fragment order
   float *bias[3] = {};
   uint16_t *a[3] = {};  // layer inputs (bf16)
   float *z[3] = {};     // pre-activations [npad][Np]
   uint16_t *cols = nullptr, *dz16 = nullptr;
   float *dcols = nullptr, *dz = nullptr, *dW = nullptr, *y = nullptr, *Xbuf = nullptr;
   double *part = nullptr, *sbuf = nullptr;
+  float *yall = nullptr;    // warm start: predictions of every patch [J][G^3]
+  double *sall = nullptr;   // and their scales [J]
   int step = 0;
+  bool fused = false;  // fused convolution kernels for this shape
   std::vector<void *> allocs;
   template <class T>
   hipError_t alloc(T **p, size_t count) {
@@ -54,16 +58,29 @@ int64_t param_count(int C) {
 }
 
 int pack_all(lor_nn *nn, hipStream_t st) {
-  for (int l = 0; l < 3; ++l)
+  for (int l = 0; l < 3; ++l) {
     NCHK(nn_pack(nn->w + nn->off[l], nn->K27[l], nn->cout[l], nn->Kp[l], nn->Np[l], nn->Wb[l],
                  nn->bias[l], st));
+    if (nn->fused) NCHK(nn_conv_frag(nn->Wb[l], nn->Kp[l], nn->Np[l], nn->Wf[l], st));
+  }
   return LOR_OK;
 }
 
 // Forward pass of nb samples X [nb][G^3][2]; output in nn->y.
-int forward(lor_nn *nn, const float *X, int nb, const double *flag, hipStream_t st) {
+// Network output y for nb patches.  keep: also the pre-activations z[l]
+// (the backward pass needs them).  The fused convolution kernels serve the
+// supported shapes, the explicit im2col + GEMM path the others.
+int forward(lor_nn *nn, const float *X, int nb, const double *flag, hipStream_t st, bool keep = true,
+            float *yout = nullptr) {
   const int64_t rows = int64_t(nb) * nn->G3, npad = pad16(rows);
   NCHK(nn_input(X, rows, npad, nn->a[0], flag, st));
+  if (nn->fused) {
+    float *y = yout ? yout : nn->y;
+    for (int l = 0; l < 3; ++l)
+      NCHK(nn_conv_layer(nn->C, l, nn->a[l], nb, nn->G, nn->Wf[l], nn->bias[l], keep ? nn->z[l] : nullptr,
+                         l < 2 ? nn->a[l + 1] : nullptr, X, l == 2 ? y : nullptr, flag, st));
+    return LOR_OK;
+  }
   for (int l = 0; l < 3; ++l) {
     NCHK(nn_im2col(nn->a[l], rows, nn->G, nn->cin[l], nn->Kp[l], npad, nn->cols, flag, st));
     NCHK(nn_gemm(int(npad), nn->Np[l], nn->Kp[l], nn->cols, nn->Kp[l], 1, nn->Wb[l], nn->Np[l], 1,
@@ -71,7 +88,7 @@ int forward(lor_nn *nn, const float *X, int nb, const double *flag, hipStream_t 
     NCHK(nn_bias_relu(nn->z[l], rows, nn->cout[l], nn->Np[l], nn->bias[l], l < 2 ? nn->a[l + 1] : nullptr,
                       flag, st));
   }
-  NCHK(nn_output(nn->z[2], nn->Np[2], X, rows, nn->y, flag, st));
+  NCHK(nn_output(nn->z[2], nn->Np[2], X, rows, yout ? yout : nn->y, flag, st));
   return LOR_OK;
 }
 
@@ -129,7 +146,7 @@ int nn_apply_patches(lor_nn *nn, const double *r, double *z, const double *flag,
   for (int first = 0; first < J; first += nn->maxb) {
     const int cnt = std::min(nn->maxb, J - first);
     NCHK(nn_gather(nn->h->md, first, cnt, r, nn->Xbuf, nn->sbuf, flag, st));
-    int rc = forward(nn, nn->Xbuf, cnt, flag, st);
+    int rc = forward(nn, nn->Xbuf, cnt, flag, st, false);
     if (rc != LOR_OK) return rc;
     NCHK(nn_scatter(nn->h->md, first, cnt, nn->y, nn->sbuf, z, flag, st));
   }
@@ -141,13 +158,14 @@ int nn_apply_patches(lor_nn *nn, const double *r, double *z, const double *flag,
 int nn_apply_patches_warm(lor_nn *nn, const double *r, double *z, const double *flag,
                           hipStream_t st) {
   const int J = nn->h->J;
+  if (!nn->yall || !nn->sall) return LOR_ESTATE;  // allocated when attached for a warm start
   for (int first = 0; first < J; first += nn->maxb) {
     const int cnt = std::min(nn->maxb, J - first);
-    NCHK(nn_gather(nn->h->md, first, cnt, r, nn->Xbuf, nn->sbuf, flag, st));
-    int rc = forward(nn, nn->Xbuf, cnt, flag, st);
+    NCHK(nn_gather(nn->h->md, first, cnt, r, nn->Xbuf, nn->sall + first, flag, st));
+    int rc = forward(nn, nn->Xbuf, cnt, flag, st, false, nn->yall + size_t(first) * nn->G3);
     if (rc != LOR_OK) return rc;
-    NCHK(launch_patch_vcycle_warm(nn->h->pa, first, cnt, r, z, nn->y, nn->sbuf, flag, st));
   }
+  NCHK(launch_patch_vcycle_warm(nn->h->pa, 0, J, r, z, nn->yall, nn->sall, flag, st));
   return LOR_OK;
 }
 
@@ -174,6 +192,8 @@ int lor_nn_create(lor_handle_t *h, int channels, const double *params, int max_b
   nn->G = 2 * h->p - 1;
   nn->G3 = nn->G * nn->G * nn->G;
   nn->maxb = max_batch;
+  nn->fused = nn_conv_supported(channels, nn->G);
+  if (nn->fused) NCHK(nn_conv_prepare(channels));
   const int C = channels;
   const int cin[3] = {2, C, C}, cout[3] = {C, C, 1};
   int64_t o = 0;
@@ -198,6 +218,7 @@ int lor_nn_create(lor_handle_t *h, int channels, const double *params, int max_b
   NCHK(nn->alloc(&nn->g, o));
   for (int l = 0; l < 3; ++l) {
     NCHK(nn->alloc(&nn->Wb[l], size_t(nn->Kp[l]) * nn->Np[l]));
+    NCHK(nn->alloc(&nn->Wf[l], size_t(nn->Kp[l]) * nn->Np[l]));
     NCHK(nn->alloc(&nn->bias[l], nn->Np[l]));
     NCHK(nn->alloc(&nn->a[l], size_t(npad) * cin[l]));
     NCHK(nn->alloc(&nn->z[l], size_t(npad) * nn->Np[l]));
@@ -292,6 +313,13 @@ int lor_nn_attach(lor_handle_t *h, lor_nn_t *nn, int mode) {
   if (!h || (mode != LOR_NN_OFF && mode != LOR_NN_REPLACE && mode != LOR_NN_WARMSTART))
     return LOR_EINVAL;
   if (mode != LOR_NN_OFF && (!nn || nn->h != h)) return LOR_EINVAL;
+  if (mode == LOR_NN_WARMSTART && !nn->yall) {
+    // predictions and scales of every patch, so that one launch runs all
+    // the warm-started V-cycles
+    if (nn->alloc(&nn->yall, size_t(h->J) * nn->G3) != hipSuccess ||
+        nn->alloc(&nn->sall, size_t(h->J)) != hipSuccess)
+      return LOR_ENOMEM;
+  }
   h->nn = mode == LOR_NN_OFF ? nullptr : nn;
   h->nn_mode = mode;
   return LOR_OK;

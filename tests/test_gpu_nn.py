@@ -105,6 +105,31 @@ def test_patch_data_and_forward_match_oracle(L, torch_dev):
         L.lor_free(h)
 
 
+@pytest.mark.parametrize("channels", [32, 48])
+def test_forward_paths_match_oracle(channels, L, torch_dev):
+    """The fused implicit-GEMM convolutions (16 and 32 channels) and the
+    explicit im2col + GEMM path (other widths) against the float64 forward
+    pass, on a p = 4 grid (G = 7) with boundary and interior patches."""
+    torch = torch_dev
+    h, mesh, p = _problem(L, n=2, p=4, seed=12)
+    params = inputs.nn_initial_params(channels, seed=6)
+    nn = L.lor_nn_create(h, channels, params, max_batch=32)
+    try:
+        r, X, T, sc = _data(L, torch, nn, h, 8)
+        J, G = L.lor_nn_shape(nn)
+        Y = torch.zeros((J, G ** 3), dtype=torch.float32, device="cuda")
+        L.lor_nn_forward(nn, X, J, Y)
+        torch.cuda.synchronize()
+        shapes = ONN.layer_shapes(channels)
+        yref, _ = ONN.forward(ONN.unflatten(params, shapes), X.cpu().numpy().astype(np.float64), G)
+        err = np.linalg.norm(Y.cpu().numpy() - yref) / np.linalg.norm(yref)
+        print("channels", channels, "forward error", err, flush=True)
+        assert err <= 3e-2, err
+    finally:
+        L.lor_nn_free(nn)
+        L.lor_free(h)
+
+
 def test_gradients_match_oracle(L, torch_dev):
     torch = torch_dev
     h, mesh, p = _problem(L)
