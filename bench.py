@@ -312,6 +312,38 @@ def learned_measure(L, torch, rtol, channels=32, train_seconds=90.0, n_test=32, 
     return out
 
 
+def nn_apply_measure(L, torch, n, p=6, channels=32, reps=3):
+    """Milliseconds per preconditioner application at n^3, p: patch V-cycles,
+    the network for every patch, and the network starting every V-cycle
+    (untrained weights: the cost does not depend on them)."""
+    from paper_1908_07071_amd import inputs
+    V = inputs.structured_vertices(3, n, 0.1, seed=3)
+    opt = L.lor_default_options()
+    opt.precision = L.LOR_PREC_MIXED
+    h = L.lor_setup(3, n, V, p, options=opt)
+    N = L.lor_ndofs(h)
+    nn = L.lor_nn_create(h, channels, inputs.nn_initial_params(channels, seed=11), max_batch=512)
+    r = torch.tensor(inputs.gaussian_rhs(N, 1), device="cuda:0")
+    z = torch.empty_like(r)
+    out = {"workload": f"preconditioner application, 3D CG {n}^3 perturbed hexes (seed 3), p={p}",
+           "N": N, "channels": channels}
+    for name, mode in (("vcycle", L.LOR_NN_OFF), ("network_replace", L.LOR_NN_REPLACE),
+                       ("network_warmstart", L.LOR_NN_WARMSTART)):
+        L.lor_nn_attach(h, nn if mode != L.LOR_NN_OFF else None, mode)
+        L.lor_apply_P(h, r, z)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            L.lor_apply_P(h, r, z)
+        torch.cuda.synchronize()
+        out[name + "_ms"] = (time.perf_counter() - t0) / reps * 1e3
+        print(f"[bench] {name}: {out[name + '_ms']:.2f} ms per application", file=sys.stderr, flush=True)
+    L.lor_nn_attach(h, None, L.LOR_NN_OFF)
+    L.lor_nn_free(nn)
+    L.lor_free(h)
+    return out
+
+
 def _kept(p):
     levels = [list(range(p + 1))]
     while len(levels[-1]) > 2:
@@ -394,6 +426,9 @@ def main():
                     help="only run the learned patch correction workload (train, then 32^3 p=6 solves)")
     ap.add_argument("--learned-train-s", type=float, default=90.0)
     ap.add_argument("--learned-n", type=int, default=32)
+    ap.add_argument("--nn-apply", action="store_true",
+                    help="only time one preconditioner application per mode (V-cycles, network, warm start) "
+                         "with an untrained 32-channel network at --learned-n^3, p=6 (kernel profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -434,6 +469,9 @@ def main():
         return
     if args.batch:
         print(json.dumps(batch_measure(L, torch, args.batch, args.batch_rhs, args.rtol, args.precision)))
+        return
+    if args.nn_apply:
+        print(json.dumps(nn_apply_measure(L, torch, args.learned_n)))
         return
 
     dim, n, p = args.dim, args.n, args.p

@@ -37,8 +37,17 @@ constexpr int kSlots = 4;  // plane slots: three in use, one loading
 constexpr int kRP = 17;    // LDS row pitch of a plane in points (G + 2 <= 17): every
                            // neighbour offset is then a compile-time immediate
 
+// LDS values (uint16) of one workgroup: kSlots planes and two output
+// staging buffers (bf16 [G^2][COUT], or float [G^2] for the output layer)
+__host__ __device__ constexpr int conv_plane(int G, int cin) { return (G + 2) * kRP * cpad(cin); }
+__host__ __device__ constexpr int conv_stage(int G, int cout, bool last) {
+  return last ? 2 * G * G : G * G * cout;
+}
+
 // CIN input channels, NT output tiles of 16 channels, COUT output channels,
-// LAST: the output layer (masked, one channel).
+// LAST: the output layer (masked, one channel).  Each wavefront computes
+// every output tile of its M-tiles (m = wave, wave + 4, ...), so an A
+// fragment read from LDS serves NT MFMAs.
 template <int CIN, int NT, int COUT, bool LAST>
 __global__ __launch_bounds__(256) void k_conv3(const uint16_t *__restrict__ ain, int nb, int G,
                                                const uint16_t *__restrict__ Wf,
@@ -48,18 +57,25 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t *__restrict__ ain,
                                                const double *flag) {
   if (flag && flag[S_DONE] != 0.0) return;  // uniform over the grid
   constexpr int KP = pad16c(27 * CIN), KS = KP / 16, NP = NT * 16, CP = cpad(CIN);
+  constexpr int UM = 2;       // M-tiles in flight per wavefront (UM NT MFMA chains)
+  constexpr int kGroup = 3;   // K-steps between scheduling barriers
   extern __shared__ __align__(16) uint16_t pl[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int G2 = G * G, G3 = G2 * G, GP = G + 2, PP = GP * kRP * CP;  // plane pitch
-  const int nt = wv % NT, mg = wv / NT, ngr = 4 / NT;
+  const int G2 = G * G, G3 = G2 * G, PP = conv_plane(G, CIN);
+  const int OS = conv_stage(G, COUT, LAST);
+  uint16_t *stage0 = pl + kSlots * PP;  // two staging buffers of OS values
   const int MT = (G2 + 15) / 16;
-  // weights of this wavefront's tile in fragment order (B[4(l/16)+t][l%16]
-  // of K-step s at ((s NT + nt) 64 + l) 4 + t): one 8-byte load per step
-  bf16x4 w[KS];
+  // the weights of every output tile in fragment order (B[4(l/16)+t][l%16]
+  // of K-step s and tile nt at ((s NT + nt) 64 + l) 4 + t)
+  bf16x4 w[NT][KS];
 #pragma unroll
   for (int s = 0; s < KS; ++s)
-    w[s] = *reinterpret_cast<const bf16x4 *>(Wf + ((s * NT + nt) * 64 + lane) * 4);
-  const float bv = bias[nt * 16 + (lane & 15)];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+      w[nt][s] = *reinterpret_cast<const bf16x4 *>(Wf + ((s * NT + nt) * 64 + lane) * 4);
+  float bv[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) bv[nt] = bias[nt * 16 + (lane & 15)];
   for (int i = threadIdx.x; i < kSlots * PP; i += 256) pl[i] = 0;  // halos stay zero
   __syncthreads();
   // one plane of a patch into a slot (interior points only); out-of-grid
@@ -100,6 +116,21 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t *__restrict__ ain,
       }
     }
   };
+  // a staged output plane to global memory: contiguous rows, 16-byte stores
+  // (ReLU bf16 activations) or the masked float output
+  auto flush = [&](int n, int z, const uint16_t *st) {
+    const int64_t row0 = int64_t(n) * G3 + int64_t(z) * G2;
+    if (LAST) {
+      const float *sf = reinterpret_cast<const float *>(st);
+      for (int i = threadIdx.x; i < G2; i += 256) y[row0 + i] = sf[i] * X[(row0 + i) * 2 + 1];
+    } else {
+      constexpr int PER = 8;  // bf16 per 16-byte store
+      const int nv = G2 * COUT / PER;
+      uint4 *dst = reinterpret_cast<uint4 *>(aout + row0 * COUT);
+      const uint4 *src = reinterpret_cast<const uint4 *>(st);
+      for (int i = threadIdx.x; i < nv; i += 256) dst[i] = src[i];
+    }
+  };
   for (int n = blockIdx.x; n < nb; n += gridDim.x) {
     word2 buf[RI];
     // planes -1, 0, 1 into slots 0, 1, 2 (slot of plane gz: (gz + 1) mod 4)
@@ -109,28 +140,32 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t *__restrict__ ain,
     }
     __syncthreads();
     for (int z = 0; z < G; ++z) {
+      if (z > 0) flush(n, z - 1, stage0 + ((z - 1) & 1) * OS);
       fetch(n, z + 2, buf);  // in flight during the plane's MFMAs
+      uint16_t *st = stage0 + (z & 1) * OS;
       // slot offsets of planes z-1, z, z+1 as element indices into pl (kept
       // as integers, so that every access stays an LDS access)
       const int sl[3] = {((z) % kSlots) * PP, ((z + 1) % kSlots) * PP, ((z + 2) % kSlots) * PP};
-      // two M-tiles per pass (m and m + ngr): two independent MFMA chains
-      for (int m = mg; m < MT; m += 2 * ngr) {
-        const int mm[2] = {m, m + ngr < MT ? m + ngr : m};
-        // per tile and plane: the LDS index of the point's (-1, -1) neighbour
-        // plus the lane's channel group; offsets from it are immediates
-        int bz[2][3];
+      for (int m = wv; m < MT; m += UM * 4) {
+        int mm[UM];
+        int bz[UM][3];  // per tile and plane: LDS index of the (-1, -1) neighbour + channel group
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < UM; ++u) {
+          mm[u] = m + u * 4 < MT ? m + u * 4 : m;
           const int pv = min(mm[u] * 16 + (lane & 15), G2 - 1);
           const int corner = ((pv / G) * kRP + pv % G) * CP + (CIN % 16 == 0 ? 4 * (lane >> 4) : 0);
 #pragma unroll
           for (int d = 0; d < 3; ++d) bz[u][d] = sl[d] + corner;
         }
-        f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+        f32x4 acc[UM][NT];
+#pragma unroll
+        for (int u = 0; u < UM; ++u)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) acc[u][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
 #pragma unroll
-          for (int u = 0; u < 2; ++u) {
+          for (int u = 0; u < UM; ++u) {
             bf16x4 a;
             if (CIN % 16 == 0) {
               const int k = (s * 16) / CIN, c0 = (s * 16) % CIN;
@@ -148,35 +183,41 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t *__restrict__ ain,
                 a[t] = jj < 54 ? v : short(0);
               }
             }
-            acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w[s], acc[u], 0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+              acc[u][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w[nt][s], acc[u][nt], 0, 0, 0);
           }
           // bounds how far the scheduler hoists the LDS reads (register use)
-          if (s % 6 == 5) __builtin_amdgcn_sched_barrier(0);
+          if (s % kGroup == kGroup - 1) __builtin_amdgcn_sched_barrier(0);
         }
-        // C[4(l/16)+t][l%16]: points m*16 + 4(l/16) + t, channel nt*16 + l%16
+        // C[4(l/16)+t][l%16]: points mm*16 + 4(l/16) + t, channel nt*16 + l%16,
+        // staged in LDS (pre-activations straight to zout when kept)
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          if (u == 1 && mm[1] == mm[0]) break;
+        for (int u = 0; u < UM; ++u) {
+          if (u > 0 && mm[u] == m) break;  // tiles past the plane repeat tile m
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int pr = mm[u] * 16 + 4 * (lane >> 4) + t;
-            const int o = nt * 16 + (lane & 15);
-            if (pr < G2) {
-              const int64_t row = int64_t(n) * G3 + int64_t(z) * G2 + pr;
-              const float v = acc[u][t] + bv;
-              if (zout) zout[row * NP + o] = v;
-              if (LAST) {
-                if (o == 0) y[row] = v * X[row * 2 + 1];
-              } else if (o < COUT) {
-                aout[row * COUT + o] = f2bf_rne(v > 0.f ? v : 0.f);
+          for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const int pr = mm[u] * 16 + 4 * (lane >> 4) + t;
+              const int o = nt * 16 + (lane & 15);
+              if (pr < G2) {
+                const float v = acc[u][nt][t] + bv[nt];
+                if (zout) zout[(int64_t(n) * G3 + int64_t(z) * G2 + pr) * NP + o] = v;
+                if (LAST) {
+                  if (o == 0) reinterpret_cast<float *>(st)[pr] = v;
+                } else if (o < COUT) {
+                  st[pr * COUT + o] = f2bf_rne(v > 0.f ? v : 0.f);
+                }
               }
             }
-          }
         }
       }
       store((z + 3) % kSlots, buf);  // plane z + 2: its slot held plane z - 2
       __syncthreads();
     }
+    flush(n, G - 1, stage0 + ((G - 1) & 1) * OS);
+    __syncthreads();  // the staging buffers are reused by the next patch
   }
 }
 
@@ -195,7 +236,8 @@ template <int CIN, int NT, int COUT, bool LAST>
 hipError_t launch_conv(const uint16_t *ain, int nb, int G, const uint16_t *Wf, const float *bias,
                        float *zout, uint16_t *aout, const float *X, float *y, const double *flag,
                        hipStream_t st) {
-  const size_t lds = size_t(kSlots) * (G + 2) * kRP * cpad(CIN) * sizeof(uint16_t);
+  const size_t lds = (size_t(kSlots) * conv_plane(G, CIN) + 2 * size_t(conv_stage(G, COUT, LAST))) *
+                     sizeof(uint16_t);
   const int grid = nb < 2048 ? nb : 2048;
   k_conv3<CIN, NT, COUT, LAST><<<grid, 256, lds, st>>>(ain, nb, G, Wf, bias, zout, aout, X, y, flag);
   return hipGetLastError();
