@@ -238,10 +238,15 @@ def stencil_matrix(stencils: np.ndarray, shape, rows_mask=None) -> sp.csr_matrix
 class LORHierarchy:
     """Global LOR level grids, coordinates and stencils for a mesh and degree p."""
 
-    def __init__(self, mesh, p: int):
+    def __init__(self, mesh, p: int, fine_coords=None):
+        """fine_coords: the GLL node coordinates of mesh (computed when None);
+        given for a submesh, they keep the nodes on its boundary bitwise equal
+        to the enclosing mesh's, which evaluates interface nodes with the
+        lower-indexed element's map."""
         self.mesh, self.p = mesh, p
         self.ref_nodes, _ = _gll.gll(p)
-        self.fine_coords = _mesh.global_node_coords(mesh, self.ref_nodes, p)
+        self.fine_coords = (_mesh.global_node_coords(mesh, self.ref_nodes, p) if fine_coords is None
+                            else np.asarray(fine_coords, dtype=np.float64))
         self.kept = kept_points(p)
         self.sizes = [len(k) - 1 for k in self.kept]
         self.nlevels = len(self.kept)

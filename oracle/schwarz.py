@@ -28,6 +28,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
+from . import gll as _gll
 from . import lor as _lor
 from . import mdf as _mdf
 from . import mesh as _mesh
@@ -119,6 +120,36 @@ class Patch:
 
     def solve(self, r_patch):
         return self.vcycle(0, r_patch)
+
+
+def local_patch(mesh, p: int, v, fine_coords=None):
+    """The patch of vertex v built on the submesh of the (up to 2^d) elements
+    around v, with the enclosing mesh's node coordinates.  Rows of the level
+    matrices at patch unknowns involve only sub-elements of those elements,
+    so the patch (matrices, MDF orders, factors, transfers, V-cycle) equals
+    the one built on the whole mesh (pinned), at the cost of 2^d elements.
+    Returns (patch, global L-vector index of each level-0 patch unknown in
+    the patch's order)."""
+    dim = mesh.dim
+    if fine_coords is None:
+        ref, _ = _gll.gll(p)
+        fine_coords = _mesh.global_node_coords(mesh, ref, p)
+    elo = [max(v[i] - 1, 0) for i in range(dim)]
+    ne = [min(v[i], mesh.n[i] - 1) - elo[i] + 1 for i in range(dim)]
+    vidx = np.indices([ne[i] + 1 for i in range(dim)]).reshape(dim, -1, order="F")
+    vflat = _mesh.lex_index([vidx[i] + elo[i] for i in range(dim)], [m + 1 for m in mesh.n])
+    sub = _mesh.make_mesh(dim, ne, mesh.vertices[vflat])
+    gshape = _mesh.grid_shape(mesh, p)
+    sshape = _mesh.grid_shape(sub, p)
+    gidx = np.indices(sshape).reshape(dim, -1, order="F")
+    gflat = _mesh.lex_index([gidx[i] + elo[i] * p for i in range(dim)], gshape)
+    H = _lor.LORHierarchy(sub, p, fine_coords=fine_coords[gflat])
+    P = Patch(H, tuple(v[i] - elo[i] for i in range(dim)))
+    lv = P.levels[0]
+    loc = np.unravel_index(lv["flat"], sshape, order="F") if len(lv["flat"]) else [np.zeros(0, int)] * dim
+    glob = _mesh.lex_index([np.asarray(loc[i]) + elo[i] * p for i in range(dim)], gshape)
+    num = _mesh.interior_numbering(gshape)
+    return P, num[glob]
 
 
 class CoarseSpace:

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import scipy.linalg as sla
 
-from oracle import highorder as HO, lor, mesh as M, schwarz as S
+from oracle import gll, highorder as HO, lor, mesh as M, schwarz as S
 from paper_1908_07071_amd import inputs
 
 
@@ -105,3 +105,27 @@ def test_kappa_bounded_in_h_and_p():
     k_p6, _ = _kappa(2, 2, 6)
     assert k_p6 / k_n2 <= 1.35
     assert k_n4 < 25 and k_p6 < 25
+
+
+@pytest.mark.parametrize("dim,n,p", [(3, 3, 3), (2, 4, 6), (3, 2, 4)])
+def test_local_patch_equals_full_mesh_patch(dim, n, p):
+    """A patch built on the 2^d elements around its vertex (with the mesh's
+    node coordinates) has the same MDF orders and gives the same V-cycle, bit
+    for bit, as the patch built on the whole mesh: the full-size GPU tests
+    rest on this."""
+    V = inputs.structured_vertices(dim, n, 0.1, seed=21)
+    mesh = M.make_mesh(dim, n, V)
+    B = S.SchwarzLOR(mesh, p)
+    r = inputs.gaussian_rhs(B.Kh.shape[0], 22)
+    ref, _ = gll.gll(p)
+    fc = M.global_node_coords(mesh, ref, p)
+    for j, v in enumerate(S.vertices(mesh)):
+        Pf = B.patches[j]
+        Pl, u = S.local_patch(mesh, p, v, fine_coords=fc)
+        uf = B.fnum[Pf.levels[0]["flat"]]
+        assert np.array_equal(u, uf), v
+        for k in range(len(Pf.levels) - 1):
+            if "order" in Pf.levels[k]:
+                assert np.array_equal(Pf.levels[k]["order"], Pl.levels[k]["order"]), (v, k)
+        if len(u):
+            assert np.array_equal(Pf.solve(r[u]), Pl.solve(r[u])), v
