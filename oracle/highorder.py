@@ -311,6 +311,92 @@ def dg_operator(mesh, p: int, method: str, eta: float, boundary: bool = True) ->
     return A.tocsr()
 
 
+_physical_grad_rows = physical_grad_rows
+_face_geometry_ = _face_geometry
+
+
+def dg_apply_rows(mesh, p: int, method: str, eta: float, x: np.ndarray, rows) -> np.ndarray:
+    """(A_IP or A_BR2 x)[rows] for selected E-vector rows, from the same face
+    terms as dg_operator written row by row: for a face node q with jump
+    vector j_q and average normal-flux vector f_q (both over the two
+    elements' nodes), row r receives
+    omega_q (-j_q[r] (f_q . x) - f_q[r] (j_q . x) + sigma_q j_q[r] (j_q . x)),
+    plus the element row (A_K x_K)[r].  Only the elements of the sampled
+    rows and their face neighbours are visited."""
+    if method not in ("ip", "br2"):
+        raise ValueError(method)
+    dim = mesh.dim
+    nloc = (p + 1) ** dim
+    elems = list(mesh.elements())
+    out = np.zeros(len(rows))
+    cache = {}
+
+    def memo(key, f):  # rows of one element share its matrices and faces
+        if key not in cache:
+            cache[key] = f()
+        return cache[key]
+
+    def physical_grad_rows(mesh_, p_, e_):
+        return memo(("G", e_), lambda: _physical_grad_rows(mesh_, p_, e_))
+
+    def _face_geometry(mesh_, p_, s_, e_, side_):
+        return memo(("F", s_, e_, side_), lambda: _face_geometry_(mesh_, p_, s_, e_, side_))
+
+    for k, r in enumerate(rows):
+        e = elems[int(r) // nloc]
+        i = int(r) % nloc
+        xe = x[_elem_flat(mesh, e) * nloc + np.arange(nloc)]
+        acc = memo(("A", e), lambda: element_stiffness(mesh, p, e))[i] @ xe
+        Ge = physical_grad_rows(mesh, p, e)
+        for s in range(dim):
+            for side in (0, 1):
+                nb = list(e)
+                nb[s] += 1 if side else -1
+                if 0 <= nb[s] < mesh.n[s]:
+                    nb = tuple(nb)
+                    em, ep = (e, nb) if side else (nb, e)
+                    flm, nrm, omega, volwm, volm = _face_geometry(mesh, p, s, em, 1)
+                    flp, _, _, volwp, volp = _face_geometry(mesh, p, s, ep, 0)
+                    Gm = physical_grad_rows(mesh, p, em)
+                    Gp = Ge if ep == e else physical_grad_rows(mesh, p, ep)
+                    if em == e:
+                        Gm = Ge
+                    xm = x[_elem_flat(mesh, em) * nloc + np.arange(nloc)]
+                    xp = x[_elem_flat(mesh, ep) * nloc + np.arange(nloc)]
+                    if method == "ip":
+                        he = min(volm, volp) / omega.sum()
+                        sig = np.full(len(flm), eta * p * p / he)
+                    else:
+                        sig = br2_sigma(eta, omega, [volwm, volwp])
+                    for q in range(len(flm)):
+                        jx = xm[flm[q]] - xp[flp[q]]
+                        fx = 0.5 * (sum(nrm[q, t] * Gm[t, flm[q]] for t in range(dim)) @ xm
+                                    + sum(nrm[q, t] * Gp[t, flp[q]] for t in range(dim)) @ xp)
+                        if e == em:
+                            jr = 1.0 if i == flm[q] else 0.0
+                            fr = 0.5 * sum(nrm[q, t] * Gm[t, flm[q], i] for t in range(dim))
+                        else:
+                            jr = -1.0 if i == flp[q] else 0.0
+                            fr = 0.5 * sum(nrm[q, t] * Gp[t, flp[q], i] for t in range(dim))
+                        acc += omega[q] * (-jr * fx - fr * jx + sig[q] * jr * jx)
+                else:
+                    # boundary face of e (side 0: xi_s = 0, side 1: xi_s = 1)
+                    fl, nrm, omega, volw, volK = _face_geometry(mesh, p, s, e, side)
+                    if method == "ip":
+                        he = volK / omega.sum()
+                        sig = np.full(len(fl), eta * p * p / he)
+                    else:
+                        sig = br2_sigma(eta, omega, [volw])
+                    for q in range(len(fl)):
+                        jx = xe[fl[q]]
+                        fx = sum(nrm[q, t] * Ge[t, fl[q]] for t in range(dim)) @ xe
+                        jr = 1.0 if i == fl[q] else 0.0
+                        fr = sum(nrm[q, t] * Ge[t, fl[q], i] for t in range(dim))
+                        acc += omega[q] * (-jr * fx - fr * jx + sig[q] * jr * jx)
+        out[k] = acc
+    return out
+
+
 def br2_lifting_matrix(mesh, p: int, eta: float) -> sp.csr_matrix:
     """The BR2 stabilisation eta sum_e (r_e([u]), r_e([v])) built from explicit liftings.
 

@@ -120,3 +120,19 @@ def test_dg_preconditioner_penalty_robust(method):
         assert ev[0] > 0
         ks.append(ev[-1] / ev[0])
     assert max(ks) / min(ks) <= 1.6, ks
+
+
+@pytest.mark.parametrize("dim,n,p,method", [(3, (2, 2, 1), 2, "ip"), (3, (2, 1, 2), 3, "br2"), (2, (3, 2), 4, "ip"),
+                                            (2, (2, 3), 3, "br2")])
+def test_dg_apply_rows_matches_assembled(dim, n, p, method):
+    """The row-by-row DG apply (used at full size on sampled rows) equals the
+    assembled operator on every row, with boundary faces."""
+    V = inputs.structured_vertices(dim, list(n), 0.1, seed=3)
+    mesh = M.make_mesh(dim, list(n), V)
+    eta = 1.5 * (p + 1) ** 2
+    A = HO.dg_operator(mesh, p, method, eta)
+    x = inputs.uniform_vector(A.shape[0], 4)
+    rows = np.arange(A.shape[0])
+    y = HO.dg_apply_rows(mesh, p, method, eta, x, rows)
+    ref = A @ x
+    assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()

@@ -12,7 +12,10 @@ by one:
 * the preconditioner as a whole: symmetry and positivity, which hold at any
   size, and the float32 preconditioner against the float64 one;
 * the solve: the true residual reaches the tolerance, and the float32 and
-  float64 preconditioners take the same number of iterations within two.
+  float64 preconditioners take the same number of iterations within two;
+* DG at its benchmark size (12^3, seed 2, p = 6, IP and BR2, eta = 1.5 (p+1)^2):
+  operator rows from the element and face terms around them, symmetry and
+  positivity of the DG preconditioner, float32 against float64, the solve.
 
 Tolerances: float64 paths 1e-12 relative as in the small cases, except
 where the output is float32 (the patch-grid output, 2e-7); the float32
@@ -165,3 +168,74 @@ def test_solve(L, torch_dev, problem):
         assert info.status == L.LOR_OK and info.rel_res_true <= 1.05e-8
         its[name] = info.iters
     assert abs(its["mixed"] - its["fp64"]) <= 2, its
+
+
+# ---------------------------------------------------------------------------
+# DG at its benchmark size: 12^3 hexes perturbed by at most 10% of h (seed 2),
+# p = 6, IP and BR2 (N_DG = 592,704)
+DG_EL, DG_ETA = 12, 1.5 * (P + 1) ** 2
+
+
+@pytest.fixture(scope="module")
+def dg_problem(L, torch_dev):
+    V = inputs.structured_vertices(3, DG_EL, 0.1, seed=2)
+    mesh = M.make_mesh(3, [DG_EL] * 3, V)
+    handles = {}
+    for method, code in (("ip", L.LOR_IP), ("br2", L.LOR_BR2)):
+        for name, prec in (("mixed", L.LOR_PREC_MIXED), ("fp64", L.LOR_PREC_FP64)):
+            opt = L.lor_default_options()
+            opt.precision = prec
+            handles[(method, name)] = L.lor_setup(3, DG_EL, V, P, method=code, penalty=DG_ETA, options=opt)
+    print("full-size DG handles ready", flush=True)
+    yield mesh, handles
+    for h in handles.values():
+        L.lor_free(h)
+
+
+@pytest.mark.parametrize("method", ["ip", "br2"])
+def test_dg_operator_sampled_rows(method, L, torch_dev, dg_problem):
+    torch = torch_dev
+    mesh, handles = dg_problem
+    h = handles[(method, "fp64")]
+    N = L.lor_ndofs(h)
+    nloc = (P + 1) ** 3
+    assert N == DG_EL ** 3 * nloc
+    xin = inputs.uniform_vector(N, 17)
+    x = torch.tensor(xin, device="cuda")
+    y = torch.empty_like(x)
+    L.lor_apply_A(h, x, y)
+    torch.cuda.synchronize()
+    yh = y.cpu().numpy()
+    rng = np.random.default_rng(9)
+    # a corner, an interior and an edge element, eight rows each
+    elems = [0, 5 + DG_EL * (6 + DG_EL * 7), DG_EL - 1 + DG_EL * (DG_EL - 1 + DG_EL * 3)]
+    rows = np.concatenate([e * nloc + rng.choice(nloc, 8, replace=False) for e in elems])
+    ref = HO.dg_apply_rows(mesh, P, method, DG_ETA, xin, rows)
+    err = np.abs(yh[rows] - ref).max() / np.abs(yh).max()
+    print(method, "DG operator rows error", err, flush=True)
+    assert err <= 1e-12, err
+
+
+@pytest.mark.parametrize("method", ["ip", "br2"])
+def test_dg_preconditioner_and_solve(method, L, torch_dev, dg_problem):
+    torch = torch_dev
+    _, handles = dg_problem
+    h, h64 = handles[(method, "mixed")], handles[(method, "fp64")]
+    N = L.lor_ndofs(h)
+    r1 = torch.tensor(inputs.gaussian_rhs(N, 61), device="cuda")
+    r2 = torch.tensor(inputs.gaussian_rhs(N, 62), device="cuda")
+    z1, z2, z64 = torch.empty_like(r1), torch.empty_like(r1), torch.empty_like(r1)
+    L.lor_apply_P(h, r1, z1)
+    L.lor_apply_P(h, r2, z2)
+    L.lor_apply_P(h64, r1, z64)
+    torch.cuda.synchronize()
+    e1, e2 = float(r1 @ z1), float(r2 @ z2)
+    assert e1 > 0 and e2 > 0
+    asym = abs(float(r2 @ z1) - float(r1 @ z2)) / np.sqrt(e1 * e2)
+    err = float((z1 - z64).norm() / z64.norm())
+    print(method, "DG asymmetry", asym, "float32 against float64", err, flush=True)
+    assert asym <= 2e-5 and err <= 2e-5, (asym, err)
+    x = torch.zeros_like(r1)
+    info = L.lor_pcg_solve(h, r1, x, rtol=1e-8, maxit=1000)
+    print(method, "DG iterations", info.iters, "true residual", info.rel_res_true, flush=True)
+    assert info.status == L.LOR_OK and info.rel_res_true <= 1.05e-8
