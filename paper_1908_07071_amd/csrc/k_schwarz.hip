@@ -111,16 +111,23 @@ __device__ __forceinline__ int64_t walk_uidx(const Box<DIM> &bx, const Walk<DIM>
   return int64_t(bx.lo[0] + w.x - ox) + int64_t(md.nu[0]) * t;
 }
 
-// LDS layout of one patch: level 0 holds X, R (the right side is the global
-// residual); level k > 0 holds X, B, R.  With a warm start (WARM) level 0
-// also holds its own right side B.  which: 0 = X, 1 = B, 2 = R.
+// LDS layout of one patch (values of T):
+//   X_0 | B_0 (warm start only) | R_0 | B_1
+// and, inside R_0's space, X_1, R_1, then X_k, B_k, R_k for k >= 2: R_0 is
+// dead from the restriction to level 1 (which reads R_0 and writes B_1, kept
+// apart) until the level-0 residual after the prolongation from level 1.
+// Without a warm start the level-0 right side is the global residual.
+// which: 0 = X, 1 = B, 2 = R.
 template <int DIM, typename T, bool WARM>
 __device__ __forceinline__ T *lds_vec(T *lds, const PatchArgs &pa, const int *v, int k, int which) {
-  int off = 0;
-  for (int q = 0; q < k; ++q) off += (q == 0 && !WARM ? 2 : 3) * make_box<DIM>(pa, v, q).n;
-  const int n = make_box<DIM>(pa, v, k).n;
-  if (k == 0 && !WARM) return lds + (which == 0 ? 0 : n);
-  return lds + off + which * n;
+  const int n0 = make_box<DIM>(pa, v, 0).n;
+  T *R0 = lds + (WARM ? 2 : 1) * n0;
+  if (k == 0) return which == 0 ? lds : (which == 2 ? R0 : (WARM ? lds + n0 : nullptr));
+  const int n1 = make_box<DIM>(pa, v, 1).n;
+  if (k == 1) return which == 0 ? R0 : (which == 1 ? R0 + n0 : R0 + n1);
+  int off = 2 * n1;
+  for (int q = 2; q < k; ++q) off += 3 * make_box<DIM>(pa, v, q).n;
+  return R0 + off + which * make_box<DIM>(pa, v, k).n;
 }
 
 // ---------------------------------------------------------------- sweeps
@@ -451,8 +458,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const Box<DIM> b0 = make_box<DIM>(pa, v, 0);
   if (b0.n <= 0) return;
   {
-    int tot = 0;
-    for (int k = 0; k < L; ++k) tot += (k == 0 && !WARM ? 2 : 3) * make_box<DIM>(pa, v, k).n;
+    const int tot = (WARM ? 3 : 2) * b0.n + (L > 1 ? make_box<DIM>(pa, v, 1).n : 0);
     for (int i = threadIdx.x; i < tot; i += 64) lds[i] = T(0);
   }
   wave_sync();

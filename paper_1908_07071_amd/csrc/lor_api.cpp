@@ -318,14 +318,25 @@ int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hi
   pa.xfer = h.d_xfer;
   pa.fac = h.d_fac;
   pa.fac_off = h.d_fac_off;
-  // LDS of the largest patch: level 0 X, R; coarser levels X, B, R
-  int tot = 0;
-  for (int k = 0; k < L; ++k) {
-    const int s = pa.s[k];
+  // LDS of the largest patch: X_0, R_0 and B_1, the coarser levels inside
+  // R_0's space.  That space must hold X_1, R_1 and X_k, B_k, R_k (k >= 2)
+  // for every patch shape (each direction interior, 2 s - 1 points, or at
+  // the boundary, s - 1).
+  auto level_n = [&](int k, int mask) {
     int ps = 1;
-    for (int d = 0; d < dim; ++d) ps *= std::max(h.n[d] >= 2 ? 2 * s - 1 : s - 1, 0);
-    tot += (k == 0 ? 2 : 3) * ps;
+    for (int d = 0; d < dim; ++d) {
+      const bool interior = ((mask >> d) & 1) && h.n[d] >= 2;
+      ps *= std::max(interior ? 2 * pa.s[k] - 1 : pa.s[k] - 1, 0);
+    }
+    return ps;
+  };
+  for (int mask = 0; mask < (1 << dim); ++mask) {
+    int coarse = L > 1 ? 2 * level_n(1, mask) : 0;
+    for (int k = 2; k < L; ++k) coarse += 3 * level_n(k, mask);
+    if (coarse > level_n(0, mask)) return LOR_EINVAL;  // never for the kept-point rule
   }
+  const int full = (1 << dim) - 1;
+  const int tot = 2 * level_n(0, full) + (L > 1 ? level_n(1, full) : 0);
   pa.lds_total = tot;
   pa.fp32 = mixed ? 1 : 0;
   if (size_t(tot) * (mixed ? sizeof(float) : sizeof(double)) > 160 * 1024) return LOR_EINVAL;
