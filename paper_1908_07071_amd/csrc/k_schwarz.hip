@@ -131,7 +131,7 @@ __device__ __forceinline__ T *lds_vec(T *lds, const PatchArgs &pa, const int *v,
 }
 
 // ---------------------------------------------------------------- sweeps
-// A sweep block (layout at kChunkRows) is consumed chunk by chunk from two
+// A sweep block (layout at kChunkLanes) is consumed chunk by chunk from two
 // register buffers: wait for chunk c, issue the coalesced loads of chunk c+1
 // into the other buffer, then run the dependency levels of chunk c from
 // registers and LDS.  The only wait on global memory is the one before new
@@ -150,18 +150,21 @@ __device__ __forceinline__ uint32_t wget(const uint4 (&R)[QM], int k) {
   }
 }
 template <typename T, int QM>
-__device__ __forceinline__ T word_get(const uint4 (&R)[QM], int b);
-template <>
-__device__ __forceinline__ float word_get<float, 10>(const uint4 (&R)[10], int b) {
-  return __uint_as_float(wget(R, b));
+__device__ __forceinline__ T word_get(const uint4 (&R)[QM], int b) {
+  if constexpr (sizeof(T) == 4)
+    return __uint_as_float(wget(R, b));
+  else
+    return __hiloint2double(int(wget(R, b + 1)), int(wget(R, b)));
 }
-template <>
-__device__ __forceinline__ float word_get<float, 11>(const uint4 (&R)[11], int b) {
-  return __uint_as_float(wget(R, b));
+
+// Value of lane l ^ 1 (DPP quad permutation [1, 0, 3, 2]; every lane active).
+__device__ __forceinline__ float pair_swap(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
 }
-template <>
-__device__ __forceinline__ double word_get<double, 17>(const uint4 (&R)[17], int b) {
-  return __hiloint2double(int(wget(R, b + 1)), int(wget(R, b)));
+__device__ __forceinline__ double pair_swap(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
 }
 
 __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
@@ -179,16 +182,20 @@ __device__ __forceinline__ void load_chunk(uint4 (&R)[QM], const uint4 *src, int
   }
 }
 
-// The steps of one chunk with NPP coupling pairs per row: the chunk's widest
-// row (rows with fewer couplings have zero padding pairs that read the row
-// itself), so a chunk of narrow rows costs fewer LDS reads and FMAs.
-template <typename T, bool FWD, int QM, int NPP>
+// The steps of one chunk with NPP coupling pairs per lane record: the
+// chunk's widest record (records with fewer couplings have zero padding pairs
+// that read the row itself), so a chunk of narrow rows costs fewer LDS reads
+// and FMAs.  SPLIT: the chunk holds rows split over a lane pair; the second
+// lane of a pair starts from zero, and the first adds the pair's partial sum.
+template <typename T, bool FWD, int QM, int NPP, bool SPLIT>
 __device__ __forceinline__ void run_steps(const uint4 (&R)[QM], T *Y, int nsteps, int mystep,
-                                          int row) {
+                                          int row, bool second, bool paired) {
   constexpr int H = sweep_head_words<T>(FWD), PW = sweep_pair_words<T>(), SZ = int(sizeof(T)) / 4;
   for (int s = 0; s < nsteps; ++s) {
+    T part = T(0);
     if (mystep == s) {
       T acc0 = FWD ? Y[row] : Y[row] * word_get<T, QM>(R, 1);
+      if (SPLIT) acc0 = second ? T(0) : acc0;
       T acc1 = T(0);
       // all LDS reads are issued before the FMAs, with no branch between them
       // (padding pairs have zero values and offsets: they read the row itself)
@@ -214,42 +221,53 @@ __device__ __forceinline__ void run_steps(const uint4 (&R)[QM], T *Y, int nsteps
           }
         }
       }
-      Y[row] = acc0 + acc1;
+      if (SPLIT)
+        part = acc0 + acc1;
+      else
+        Y[row] = acc0 + acc1;
+    }
+    if (SPLIT) {
+      const T other = pair_swap(part);
+      if (mystep == s && !second) Y[row] = paired ? part + other : part;
     }
     wave_sync();
+  }
+}
+
+template <typename T, bool FWD, int QM, bool SPLIT>
+__device__ __forceinline__ void run_chunk_w(const uint4 (&R)[QM], T *Y, int npairs, int nsteps, int mystep,
+                                            int row, bool second, bool paired) {
+  switch (npairs) {
+    case 0: run_steps<T, FWD, QM, 0, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
+    case 1: run_steps<T, FWD, QM, 1, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
+    case 2: run_steps<T, FWD, QM, 2, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
+    case 3: run_steps<T, FWD, QM, 3, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
+    case 4: run_steps<T, FWD, QM, 4, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
+    case 5: run_steps<T, FWD, QM, 5, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
+    case 6: run_steps<T, FWD, QM, 6, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
+    default: run_steps<T, FWD, QM, kLaneCouplings / 2, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
   }
 }
 
 template <typename T, bool FWD, int QM>
 __device__ __forceinline__ void run_chunk(const uint4 (&R)[QM], T *Y, uint32_t hdr) {
   const int nsteps = (hdr >> 8) & 0xFF;
-  const int npairs = int((hdr >> 16) & 0xFF) / 2;  // the chunk's widest row, in pairs
+  const int npairs = int((hdr >> 16) & 0xFF) / 2;  // the chunk's widest record, in pairs
   const uint32_t d0 = R[0].x;
-  const int mystep = (d0 >> 31) ? int((d0 >> 16) & 0x3F) : -1;
+  const int mystep = (d0 & kSweepValid) ? int((d0 >> 16) & 0x3F) : -1;
   const int row = int(d0 & 0xFFFF);
-  switch (npairs) {
-    case 0: run_steps<T, FWD, QM, 0>(R, Y, nsteps, mystep, row); break;
-    case 1: run_steps<T, FWD, QM, 1>(R, Y, nsteps, mystep, row); break;
-    case 2: run_steps<T, FWD, QM, 2>(R, Y, nsteps, mystep, row); break;
-    case 3: run_steps<T, FWD, QM, 3>(R, Y, nsteps, mystep, row); break;
-    case 4: run_steps<T, FWD, QM, 4>(R, Y, nsteps, mystep, row); break;
-    case 5: run_steps<T, FWD, QM, 5>(R, Y, nsteps, mystep, row); break;
-    case 6: run_steps<T, FWD, QM, 6>(R, Y, nsteps, mystep, row); break;
-    case 7: run_steps<T, FWD, QM, 7>(R, Y, nsteps, mystep, row); break;
-    case 8: run_steps<T, FWD, QM, 8>(R, Y, nsteps, mystep, row); break;
-    case 9: run_steps<T, FWD, QM, 9>(R, Y, nsteps, mystep, row); break;
-    case 10: run_steps<T, FWD, QM, 10>(R, Y, nsteps, mystep, row); break;
-    case 11: run_steps<T, FWD, QM, 11>(R, Y, nsteps, mystep, row); break;
-    case 12: run_steps<T, FWD, QM, 12>(R, Y, nsteps, mystep, row); break;
-    default: run_steps<T, FWD, QM, (kMaxCouplings + 1) / 2>(R, Y, nsteps, mystep, row); break;
-  }
+  if (hdr & kChunkSplit)
+    run_chunk_w<T, FWD, QM, true>(R, Y, npairs, nsteps, mystep, row, (d0 & kSweepSecond) != 0,
+                                  (d0 & kSweepPaired) != 0);
+  else
+    run_chunk_w<T, FWD, QM, false>(R, Y, npairs, nsteps, mystep, row, false, false);
 }
 
 // forward:  w_i = y_i - sum_{earlier m} l_im w_m
 // backward: y_i = w_i / D_i - sum_{later m} l_mi y_m       (both in place on Y)
 template <typename T, bool FWD>
 __device__ __forceinline__ void sweep(T *Y, const char *blk) {
-  constexpr int QM = sweep_quads<T>(FWD, kMaxCouplings);
+  constexpr int QM = sweep_quads<T>(FWD, kLaneCouplings);
   const int nch = *reinterpret_cast<const int *>(blk);
   uint32_t hdr = reinterpret_cast<const uint32_t *>(blk)[1];
   const int lane = threadIdx.x;

@@ -61,18 +61,22 @@ struct PatchArgs {
 //   header (kSweepHeader B): int32 nchunks, uint32 hdr0 (header of chunk 0),
 //   8 B pad, uint8 q0[64] (quads lane l loads from chunk 0), 16 zero bytes.
 //   chunks: a chunk is a run of consecutive dependency levels ("steps")
-//   holding at most 63 rows in total, so that every lane owns at most one
-//   row of the chunk.  It is stored as Q quads (16 B) per lane, interleaved
-//   by lane: quad q of lane l at byte 16 * (q * 64 + l) from the chunk start,
-//   so that one coalesced 1 KiB load brings every lane its own quad.
+//   whose rows fit lanes 0-62: a row with at most kLaneCouplings couplings
+//   takes one lane, a wider one the lane pair (2k, 2k+1), the even lane
+//   holding the first couplings and the odd lane the rest, the two partial
+//   sums added across the pair.  A chunk is stored as Q quads (16 B) per
+//   lane, interleaved by lane: quad q of lane l at byte 16 * (q * 64 + l)
+//   from the chunk start, so that one coalesced 1 KiB load brings every lane
+//   its own quad.
 //   Lane record (uint32 words): word 0 = row (bits 0-15) | step (16-21) |
-//   quads of this lane's record in the next chunk (22-26) | valid (bit 31)
-//   (lanes without a row only carry the next size); for the backward sweep
-//   then 1 / D as T; then the
-//   couplings in pairs: T v0, T v1, uint32 (int16 off0 | int16 off1 << 16),
-//   where off is the LDS offset of the neighbour from the row (padding pairs
-//   are zero).  Lane 63 carries the header of the next chunk instead:
-//   Q (bits 0-7) | nsteps (8-15) | W (16-23), W = couplings per record.
+//   quads of this lane's record in the next chunk (22-26) | kSweepPaired |
+//   kSweepSecond | kSweepValid (lanes without a row only carry the next
+//   size); for the backward sweep then 1 / D as T (zero in the second lane
+//   of a pair); then the couplings in pairs: T v0, T v1, uint32 (int16 off0 |
+//   int16 off1 << 16), where off is the LDS offset of the neighbour from the
+//   row (padding pairs are zero).  Lane 63 carries the header of the next
+//   chunk instead: Q (bits 0-7) | nsteps (8-15) | W (16-23) | kChunkSplit,
+//   W = couplings per lane record (even).
 // Level stencils as the patch kernel reads them: point-major records, one
 // per grid point g at g * rec_width.
 //   float:  the full stencil, slots 0 .. 3^d - 1 in slot order, zero-padded
@@ -92,10 +96,15 @@ __host__ __device__ constexpr int rec_centre() {
   return sizeof(ST) == 4 ? (DIM == 3 ? 13 : 4) : 0;
 }
 
-constexpr int kChunkRows = 63;
+constexpr int kChunkLanes = 63;   // lanes holding rows (lane 63: next header)
 constexpr int kSweepHeader = 96;
 constexpr int kSweepZero = 80;   // 16 zero bytes inside the header
 constexpr int kMaxCouplings = 26;
+constexpr int kLaneCouplings = 14;  // per lane record; wider rows take a lane pair
+constexpr uint32_t kSweepPaired = 1u << 27;  // the row is split over lanes 2k, 2k+1
+constexpr uint32_t kSweepSecond = 1u << 28;  // odd lane of a pair: partial sum only
+constexpr uint32_t kSweepValid = 1u << 31;
+constexpr uint32_t kChunkSplit = 1u << 24;   // the chunk holds split rows
 template <typename T>
 __host__ __device__ constexpr int sweep_head_words(bool fwd) {
   return fwd ? 1 : 1 + int(sizeof(T)) / 4;
@@ -127,7 +136,7 @@ struct MdfResult {
 // rows: n x nslots values (row-major), box shape m[0..dim-1].
 // Returns LOR_OK or LOR_EPIVOT.
 int mdf_factor(int dim, const int *m, std::vector<double> &rows, bool natural, MdfResult &out);
-// Sweep block of one direction (layout at kChunkRows).
+// Sweep block of one direction (layout at kChunkLanes).
 template <typename T>
 std::vector<char> pack_sweep(const MdfResult &res, int dim, const int *m, bool fwd);
 

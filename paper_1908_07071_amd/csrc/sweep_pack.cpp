@@ -1,12 +1,14 @@
 // Packs the ILU(0) triangular sweeps of one patch level for the wavefront
-// kernel (layout documented at kChunkRows in lor_internal.h).
+// kernel (layout documented at kChunkLanes in lor_internal.h).
 //
 // Rows are taken in dependency-level order (forward: first level first,
-// backward: last level first).  A level holding more than kChunkRows rows is
-// split into consecutive steps (rows of one level are independent, so any
-// split is a valid schedule).  Consecutive steps are grouped into chunks of at
-// most kChunkRows rows; lanes 0.. take the chunk's rows in order and lane 63
-// carries the header of the next chunk.
+// backward: last level first).  Each level becomes one step of the current
+// chunk; when a row no longer fits the chunk's lanes, the chunk is closed and
+// the rest of the level continues as a step of the next chunk (rows of one
+// level are independent, so any split is a valid schedule).  A row with more
+// than kLaneCouplings couplings takes an aligned lane pair; single-lane rows
+// fill the lanes left free by that alignment first.
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -20,6 +22,44 @@ template <typename T>
 void put(std::vector<uint32_t> &rec, int word, T v) {
   std::memcpy(&rec[word], &v, sizeof(T));
 }
+
+// One lane's share of a row: couplings [c0, c1) of the row's list.
+struct LaneRec {
+  int row = -1, step = 0, c0 = 0, c1 = 0;
+  bool paired = false, second = false;
+};
+
+struct Chunk {
+  std::vector<LaneRec> lane = std::vector<LaneRec>(kChunkLanes);
+  std::vector<int> holes;  // free lanes below `next`
+  int next = 0, nsteps = 0, w = 0, q = 1;
+  bool split = false;
+  // places row i (n couplings) in step st; false if the lanes are full
+  bool place(int i, int n, int st) {
+    if (n > kLaneCouplings) {
+      const int a = (next + 1) & ~1;
+      if (a + 1 >= kChunkLanes) return false;
+      if (a != next) holes.push_back(next);
+      const int n0 = std::min(kLaneCouplings, 2 * ((n + 3) / 4));
+      lane[a] = LaneRec{i, st, 0, n0, true, false};
+      lane[a + 1] = LaneRec{i, st, n0, n, true, true};
+      next = a + 2;
+      split = true;
+      return true;
+    }
+    int l;
+    if (!holes.empty()) {
+      l = holes.back();
+      holes.pop_back();
+    } else if (next < kChunkLanes) {
+      l = next++;
+    } else {
+      return false;
+    }
+    lane[l] = LaneRec{i, st, 0, n, false, false};
+    return true;
+  }
+};
 
 }  // namespace
 
@@ -44,58 +84,49 @@ std::vector<char> pack_sweep(const MdfResult &res, int dim, const int *m, bool f
       if (earlier == fwd) slots.push_back(s);
     }
   };
-  // steps in sweep order, each a list of rows
-  std::vector<std::vector<int>> steps;
+  std::vector<Chunk> chunks(1);
+  std::vector<int> slots;
   for (int q = 0; q < depth; ++q) {
     const int d = fwd ? q : depth - 1 - q;
-    std::vector<int> cur;
+    int st = -1;  // this level's step in the current chunk (opened by its first row)
     for (int t = res.level_ptr[d]; t < res.level_ptr[d + 1]; ++t) {
-      cur.push_back(res.sched[t]);
-      if (int(cur.size()) == kChunkRows) {
-        steps.push_back(cur);
-        cur.clear();
+      const int i = res.sched[t];
+      couplings(i, slots);
+      const int n = int(slots.size());
+      for (;;) {
+        Chunk &c = chunks.back();
+        if (st < 0 && c.nsteps == 63) {
+          chunks.emplace_back();
+          continue;
+        }
+        const int s_try = st < 0 ? c.nsteps : st;
+        if (c.place(i, n, s_try)) {
+          if (st < 0) st = c.nsteps++;
+          break;
+        }
+        chunks.emplace_back();  // full: the rest of the level goes to a new chunk
+        st = -1;
       }
     }
-    if (!cur.empty()) steps.push_back(cur);
   }
-  // chunks of consecutive steps with at most kChunkRows rows
-  struct Chunk {
-    int first, nsteps, rows, w, q;
-  };
-  std::vector<Chunk> chunks;
-  std::vector<int> slots;
-  for (size_t s = 0; s < steps.size();) {
-    Chunk c{int(s), 0, 0, 0, 0};
-    while (s < steps.size() && c.rows + int(steps[s].size()) <= kChunkRows && c.nsteps < 63) {
-      for (int i : steps[s]) {
-        couplings(i, slots);
-        c.w = std::max(c.w, int(slots.size()));
-      }
-      c.rows += int(steps[s].size());
-      ++c.nsteps;
-      ++s;
-    }
-    c.w = (c.w + 1) & ~1;  // whole pairs
-    c.q = sweep_quads<T>(fwd, c.w);
-    chunks.push_back(c);
-  }
-  auto header = [](const Chunk &c) {
-    return uint32_t(c.q) | (uint32_t(c.nsteps) << 8) | (uint32_t(c.w) << 16);
-  };
-  // quads each lane loads in each chunk: its own record (at least the word
-  // that tells it the size of its next record); lane 63 only the header
+  if (chunks.back().nsteps == 0) chunks.pop_back();
+  // per-lane quads, chunk width and size
   const int hw = sweep_head_words<T>(fwd), pw = sweep_pair_words<T>();
   std::vector<std::vector<int>> lane_q(chunks.size(), std::vector<int>(64, 1));
   for (size_t ci = 0; ci < chunks.size(); ++ci) {
-    const Chunk &c = chunks[ci];
-    int lane = 0;
-    for (int st = 0; st < c.nsteps; ++st)
-      for (int i : steps[c.first + st]) {
-        couplings(i, slots);
-        const int w = int(slots.size() + 1) & ~1;
-        lane_q[ci][lane++] = sweep_quads<T>(fwd, w);
-      }
+    Chunk &c = chunks[ci];
+    for (int l = 0; l < kChunkLanes; ++l) {
+      const LaneRec &r = c.lane[l];
+      if (r.row < 0) continue;
+      const int w = (r.c1 - r.c0 + 1) & ~1;
+      c.w = std::max(c.w, w);
+      lane_q[ci][l] = sweep_quads<T>(fwd, w);
+    }
+    c.q = sweep_quads<T>(fwd, c.w);
   }
+  auto header = [](const Chunk &c) {
+    return uint32_t(c.q) | (uint32_t(c.nsteps) << 8) | (uint32_t(c.w) << 16) | (c.split ? kChunkSplit : 0u);
+  };
   int64_t bytes = kSweepHeader;
   for (const Chunk &c : chunks) bytes += int64_t(c.q) * 64 * 16;
   std::vector<char> out(bytes, 0);
@@ -110,28 +141,27 @@ std::vector<char> pack_sweep(const MdfResult &res, int dim, const int *m, bool f
     const Chunk &c = chunks[ci];
     const int words = c.q * 4;
     auto nextq = [&](int l) -> uint32_t { return ci + 1 < chunks.size() ? uint32_t(lane_q[ci + 1][l]) : 0u; };
-    int lane = 0;
-    for (int st = 0; st < c.nsteps; ++st) {
-      for (int i : steps[c.first + st]) {
-        rec.assign(words, 0u);
-        rec[0] = uint32_t(i & 0xFFFF) | (uint32_t(st) << 16) | (nextq(lane) << 22) | (1u << 31);
-        if (!fwd) put<T>(rec, 1, T(1.0 / res.D[i]));
-        couplings(i, slots);
-        for (size_t q = 0; q < slots.size(); ++q) {
-          const int pr = int(q) / 2, hi = int(q) % 2;
-          const int w0 = hw + pr * pw;
-          put<T>(rec, w0 + hi * int(sizeof(T)) / 4, T(res.L[size_t(i) * NS + slots[q]]));
-          const uint32_t o = uint32_t(uint16_t(int16_t(dl[slots[q]])));
-          rec[w0 + pw - 1] |= hi ? (o << 16) : o;
-        }
-        for (int qd = 0; qd < c.q; ++qd)
-          std::memcpy(out.data() + base + 16 * (int64_t(qd) * 64 + lane), &rec[4 * qd], 16);
-        ++lane;
+    for (int l = 0; l < kChunkLanes; ++l) {
+      const LaneRec &r = c.lane[l];
+      if (r.row < 0) {  // lanes without a row still learn their next size
+        const uint32_t w0 = nextq(l) << 22;
+        std::memcpy(out.data() + base + 16 * l, &w0, 4);
+        continue;
       }
-    }
-    for (; lane < 63; ++lane) {  // lanes without a row still learn their next size
-      const uint32_t w0 = nextq(lane) << 22;
-      std::memcpy(out.data() + base + 16 * lane, &w0, 4);
+      rec.assign(words, 0u);
+      rec[0] = uint32_t(r.row & 0xFFFF) | (uint32_t(r.step) << 16) | (nextq(l) << 22) | kSweepValid |
+               (r.paired ? kSweepPaired : 0u) | (r.second ? kSweepSecond : 0u);
+      if (!fwd && !r.second) put<T>(rec, 1, T(1.0 / res.D[r.row]));
+      couplings(r.row, slots);
+      for (int q = r.c0; q < r.c1; ++q) {
+        const int pr = (q - r.c0) / 2, hi = (q - r.c0) % 2;
+        const int w0 = hw + pr * pw;
+        put<T>(rec, w0 + hi * int(sizeof(T)) / 4, T(res.L[size_t(r.row) * NS + slots[q]]));
+        const uint32_t o = uint32_t(uint16_t(int16_t(dl[slots[q]])));
+        rec[w0 + pw - 1] |= hi ? (o << 16) : o;
+      }
+      for (int qd = 0; qd < c.q; ++qd)
+        std::memcpy(out.data() + base + 16 * (int64_t(qd) * 64 + l), &rec[4 * qd], 16);
     }
     // lane 63: header of the next chunk
     const uint32_t hn = ci + 1 < chunks.size() ? header(chunks[ci + 1]) : 0u;
