@@ -168,6 +168,7 @@ __device__ __forceinline__ double pair_swap(double x) {
 }
 
 __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }  // lgkmcnt(0)
 
 // Loads this lane's record of a chunk (myq quads).  The loads are branch
 // free: quads the lane does not need read a zero quad of the block header, so
@@ -198,28 +199,24 @@ __device__ __forceinline__ void run_steps(const uint4 (&R)[QM], T *Y, int nsteps
       if (SPLIT) acc0 = second ? T(0) : acc0;
       T acc1 = T(0);
       // all LDS reads are issued before the FMAs, with no branch between them
-      // (padding pairs have zero values and offsets: they read the row itself)
-      constexpr int HALF = (NPP + 1) / 2;  // two halves bound the live registers
+      // (padding pairs have zero values and offsets: they read the row
+      // itself), so a step costs one LDS round trip
+      T y[2 * NPP + 2];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        T y[2 * HALF + 2];
+      for (int p = 0; p < NPP; ++p) {
+        const uint32_t o = wget(R, H + p * PW + PW - 1);
+        y[2 * p] = Y[row + int(short(o & 0xFFFF))];
+        y[2 * p + 1] = Y[row + int(short(o >> 16))];
+      }
+      // one wait for all of them (fewer instructions per step than a wait
+      // before every FMA); the scheduling barriers keep it in place
+      __builtin_amdgcn_sched_barrier(0);
+      wait_lds();
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int t = 0; t < HALF; ++t) {
-          const int p = h * HALF + t;
-          if (p < NPP) {
-            const uint32_t o = wget(R, H + p * PW + PW - 1);
-            y[2 * t] = Y[row + int(short(o & 0xFFFF))];
-            y[2 * t + 1] = Y[row + int(short(o >> 16))];
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < HALF; ++t) {
-          const int p = h * HALF + t;
-          if (p < NPP) {
-            acc0 -= word_get<T, QM>(R, H + p * PW) * y[2 * t];
-            acc1 -= word_get<T, QM>(R, H + p * PW + SZ) * y[2 * t + 1];
-          }
-        }
+      for (int p = 0; p < NPP; ++p) {
+        acc0 -= word_get<T, QM>(R, H + p * PW) * y[2 * p];
+        acc1 -= word_get<T, QM>(R, H + p * PW + SZ) * y[2 * p + 1];
       }
       if (SPLIT)
         part = acc0 + acc1;
