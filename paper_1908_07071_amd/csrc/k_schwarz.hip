@@ -342,9 +342,9 @@ __device__ __forceinline__ void residual_full(T *R, const T *B, const T *X, cons
                                               const ST *__restrict__ st, const int *lng,
                                               const double *__restrict__ rglob, const MeshDims &md) {
   constexpr int NS = DIM == 3 ? 27 : 9, W = rec_width<DIM, ST>();
-  constexpr int RB = 1;  // two rows per lane would cost the third wave per SIMD
+  constexpr int RB = 2;  // two record loads in flight per lane (a fourth wave per SIMD lost, worth it)
   const int mx = bx.m[0], my = bx.m[1], mz = bx.m[2];
-  Walk<DIM> w[RB] = {Walk<DIM>(bx, threadIdx.x, 64 * RB)};
+  Walk<DIM> w[RB] = {Walk<DIM>(bx, threadIdx.x, 64 * RB), Walk<DIM>(bx, threadIdx.x + 64, 64 * RB)};
   for (int i0 = threadIdx.x; i0 < bx.n; i0 += 64 * RB) {
     ST a[RB][NS];
     T acc[RB];
@@ -606,39 +606,51 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       const XferTab *tb0 = &pa.xfer[k * 3 + typ[0]];
       const XferTab *tb1 = &pa.xfer[k * 3 + typ[1]];
       const XferTab *tb2 = &pa.xfer[k * 3 + typ[DIM - 1]];
-      Walk<DIM> wf(fb, threadIdx.x, 64);
-      for (int i = threadIdx.x; i < fb.n; i += 64, wf.step()) {
-        const int fi[3] = {wf.x, wf.y, DIM == 3 ? wf.z : 0};
+      // two rows per lane and iteration (two rounds of table loads in
+      // flight); a row past the end uses row i0's coordinates, its store is
+      // skipped
+      constexpr int PB = 2;
+      Walk<DIM> wf[PB] = {Walk<DIM>(fb, threadIdx.x, 64 * PB), Walk<DIM>(fb, threadIdx.x + 64, 64 * PB)};
+      for (int i0 = threadIdx.x; i0 < fb.n; i0 += 64 * PB) {
         // fixed 2 x 2 (x 2) gather; sources on the patch boundary get weight 0
-        int cx[2], cy[2], cz[2];
-        T wx[2], wy[2], wz[2];
+        int cx[PB][2], cy[PB][2], cz[PB][2];
+        T wx[PB][2], wy[PB][2], wz[PB][2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          cx[a] = tb0->pc[fi[0]][a];
-          wx[a] = T(tb0->pw[fi[0]][a]);
-          cy[a] = tb1->pc[fi[1]][a];
-          wy[a] = T(tb1->pw[fi[1]][a]);
-          cz[a] = DIM == 3 ? tb2->pc[fi[2]][a] : 0;
-          wz[a] = DIM == 3 ? T(tb2->pw[fi[2]][a]) : T(a == 0 ? 1 : 0);
-          const bool okx = cx[a] >= 0 && cx[a] < cb.m[0];
-          const bool oky = cy[a] >= 0 && cy[a] < cb.m[1];
-          const bool okz = DIM == 2 || (cz[a] >= 0 && cz[a] < cb.m[2]);
-          wx[a] = okx ? wx[a] : T(0);
-          cx[a] = okx ? cx[a] : 0;
-          wy[a] = oky ? wy[a] : T(0);
-          cy[a] = oky ? cy[a] : 0;
-          wz[a] = okz ? wz[a] : T(0);
-          cz[a] = okz ? cz[a] : 0;
+        for (int r = 0; r < PB; ++r) {
+          const Walk<DIM> &wr = i0 + 64 * r < fb.n ? wf[r] : wf[0];
+          const int fi[3] = {wr.x, wr.y, DIM == 3 ? wr.z : 0};
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            cx[r][a] = tb0->pc[fi[0]][a];
+            wx[r][a] = T(tb0->pw[fi[0]][a]);
+            cy[r][a] = tb1->pc[fi[1]][a];
+            wy[r][a] = T(tb1->pw[fi[1]][a]);
+            cz[r][a] = DIM == 3 ? tb2->pc[fi[2]][a] : 0;
+            wz[r][a] = DIM == 3 ? T(tb2->pw[fi[2]][a]) : T(a == 0 ? 1 : 0);
+            const bool okx = cx[r][a] >= 0 && cx[r][a] < cb.m[0];
+            const bool oky = cy[r][a] >= 0 && cy[r][a] < cb.m[1];
+            const bool okz = DIM == 2 || (cz[r][a] >= 0 && cz[r][a] < cb.m[2]);
+            wx[r][a] = okx ? wx[r][a] : T(0);
+            cx[r][a] = okx ? cx[r][a] : 0;
+            wy[r][a] = oky ? wy[r][a] : T(0);
+            cy[r][a] = oky ? cy[r][a] : 0;
+            wz[r][a] = okz ? wz[r][a] : T(0);
+            cz[r][a] = okz ? cz[r][a] : 0;
+          }
         }
-        T acc = T(0);
 #pragma unroll
-        for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c)
+        for (int r = 0; r < PB; ++r) {
+          T acc = T(0);
 #pragma unroll
-          for (int b = 0; b < 2; ++b)
+          for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c)
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
-              acc += wx[a] * wy[b] * wz[c] * Xc[cx[a] + cb.m[0] * (cy[b] + cb.m[1] * cz[c])];
-        Xk[i] += acc;
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+              for (int a = 0; a < 2; ++a)
+                acc += wx[r][a] * wy[r][b] * wz[r][c] * Xc[cx[r][a] + cb.m[0] * (cy[r][b] + cb.m[1] * cz[r][c])];
+          if (i0 + 64 * r < fb.n) Xk[i0 + 64 * r] += acc;
+          wf[r].step();
+        }
       }
       wave_sync();
     }
