@@ -9,9 +9,12 @@
 //  * the wavefront synchronises with wave-scope fences only (no s_barrier,
 //    no waits on outstanding global loads);
 //  * each triangular sweep is stored in chunks of consecutive dependency
-//    levels, at most one row per lane and chunk, interleaved by lane so that
-//    a chunk arrives in a few coalesced loads; chunk c+1 is loaded into a
-//    second register buffer while the levels of chunk c run.
+//    levels, at most one row per lane and chunk (a row with many couplings
+//    takes a lane pair that adds its two partial sums), interleaved by lane
+//    so that a chunk arrives in a few coalesced loads; chunk c+1 is loaded
+//    into a second register buffer while the levels of chunk c run;
+//  * residuals and prolongations take two rows per lane, so that two
+//    stencil records or table lookups per lane are in flight.
 // Corrections of overlapping patches are added with FP64 atomics.
 #include <hip/hip_runtime.h>
 
