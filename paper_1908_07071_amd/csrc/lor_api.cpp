@@ -280,9 +280,30 @@ int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hi
   h.fac_bytes = total;
   HIPCHK(h.alloc(&h.d_fac, size_t(std::max<int64_t>(total, 16))));
   HIPCHK(h.alloc(&h.d_fac_off, off.size()));
-  for (size_t t = 0; t < blocks.size(); ++t)
-    if (!blocks[t].empty())
-      HIPCHK(hipMemcpyAsync(h.d_fac + off[t], blocks[t].data(), blocks[t].size(), hipMemcpyHostToDevice, st));
+  {
+    // upload through a staging buffer covering a contiguous range of the pool
+    // (one copy per ~64 MiB rather than one per block; each block is freed
+    // once staged)
+    constexpr size_t kStage = size_t(64) << 20;
+    std::vector<char> stage;
+    int64_t r0 = 0;  // pool offset of stage[0]
+    auto flush = [&]() -> hipError_t {
+      if (stage.empty()) return hipSuccess;
+      hipError_t e = hipMemcpyAsync(h.d_fac + r0, stage.data(), stage.size(), hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      r0 += int64_t(stage.size());
+      stage.clear();
+      return e;
+    };
+    for (size_t t = 0; t < blocks.size(); ++t) {
+      if (blocks[t].empty()) continue;
+      if (!stage.empty() && size_t(off[t] - r0) + blocks[t].size() > kStage) HIPCHK(flush());
+      stage.resize(size_t(off[t] - r0));  // alignment padding (zero)
+      stage.insert(stage.end(), blocks[t].begin(), blocks[t].end());
+      std::vector<char>().swap(blocks[t]);
+    }
+    HIPCHK(flush());
+  }
   HIPCHK(hipMemcpyAsync(h.d_fac_off, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));  // host blocks are freed on return
   // transfer tables

@@ -23,6 +23,8 @@ void put(std::vector<uint32_t> &rec, int word, T v) {
   std::memcpy(&rec[word], &v, sizeof(T));
 }
 
+static_assert(kMaxCouplings <= 2 * kLaneCouplings, "every row must fit a lane pair");
+
 // One lane's share of a row: couplings [c0, c1) of the row's list.
 struct LaneRec {
   int row = -1, step = 0, c0 = 0, c1 = 0;
