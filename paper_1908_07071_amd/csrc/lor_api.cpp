@@ -24,6 +24,11 @@ int hip_fail(hipError_t e, const char *what, int line) {
   return LOR_EHIP;
 }
 
+int invalid(const char *why, int line) {
+  std::snprintf(g_detail, sizeof(g_detail), "invalid at lor_api.cpp:%d: %s", line, why);
+  return LOR_EINVAL;
+}
+
 #define HIPCHK(x)                                          \
   do {                                                     \
     hipError_t e_ = (x);                                   \
@@ -354,13 +359,15 @@ int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hi
   for (int mask = 0; mask < (1 << dim); ++mask) {
     int coarse = L > 1 ? 2 * level_n(1, mask) : 0;
     for (int k = 2; k < L; ++k) coarse += 3 * level_n(k, mask);
-    if (coarse > level_n(0, mask)) return LOR_EINVAL;  // never for the kept-point rule
+    if (coarse > level_n(0, mask))  // never for the kept-point rule
+      return invalid("coarse patch levels do not fit the level-0 residual's LDS space", __LINE__);
   }
   const int full = (1 << dim) - 1;
   const int tot = 2 * level_n(0, full) + (L > 1 ? level_n(1, full) : 0);
   pa.lds_total = tot;
   pa.fp32 = mixed ? 1 : 0;
-  if (size_t(tot) * (mixed ? sizeof(float) : sizeof(double)) > 160 * 1024) return LOR_EINVAL;
+  if (size_t(tot) * (mixed ? sizeof(float) : sizeof(double)) > 160 * 1024)
+    return invalid("patch vectors exceed the 160 KiB LDS of a CU (polynomial degree too high)", __LINE__);
   HIPCHK(prepare_patch_vcycle(pa));
   return LOR_OK;
 }
