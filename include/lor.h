@@ -97,7 +97,8 @@ int lor_default_options(lor_options_t *opt);
 const char *lor_error_string(int code);
 
 /* Detail of the last LOR_EHIP failure on the calling thread (which HIP call
- * and its error string); empty if none.  Static thread-local storage. */
+ * and its error string) or of a set-up LOR_EINVAL that has a reason (patch
+ * too large for the LDS); empty if none.  Static thread-local storage. */
 const char *lor_last_error_detail(void);
 
 /* Set up the discretization and the preconditioner (Sections 2 and 3).
@@ -110,6 +111,10 @@ const char *lor_last_error_detail(void);
  *   face nodes (c = 1/2 inside, 1 on the boundary).  DG boundary conditions
  *   are imposed weakly through the boundary faces (Dirichlet) or not at all
  *   (Neumann: no boundary faces).
+ *   In 3D a patch's V-cycle vectors live in the 160 KiB LDS of one CU
+ *   (2 (2p-1)^3 + (2 s_1 - 1)^3 values, s_1 the sub-intervals of level 1),
+ *   which limits p to 11 with LOR_PREC_FP64 and to 13 with LOR_PREC_MIXED;
+ *   a larger p returns LOR_EINVAL with the reason in lor_last_error_detail.
  * opt: NULL for defaults.  stream: used for the device part of the set-up.
  * Allocates the device data the handle needs (geometric factors, LOR
  * stencils, patch factors, coarse inverse) and builds everything.
