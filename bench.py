@@ -444,7 +444,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver is "
-              "single-device, see DESIGN.md for how it would shard", file=sys.stderr)
+              "single-device (it would shard by element bricks with a halo exchange per "
+              "iteration and a redundant coarse solve)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
