@@ -184,7 +184,7 @@ def batch_measure(L, torch, nprob, nrhs, rtol, precision, seed=7):
 def learned_measure(L, torch, rtol, channels=32, train_seconds=90.0, n_test=32, p=6):
     """Learned patch correction: train the patch network on (patch residual,
     patch V-cycle) pairs the method generates on 16^3 meshes (seeds 10, 11;
-    residuals of PCG iterates and Gaussian right-hand sides), judge it against
+    residuals of PCG iterates and Gaussian right-hand sides), evaluate it against
     the V-cycle on held-out patches, then solve on the n_test^3 test mesh
     (seed 3) with flexible CG to rtol: V-cycles (the plain fallback) against
     the network standing in for every patch V-cycle and against the network's
@@ -246,7 +246,7 @@ def learned_measure(L, torch, rtol, channels=32, train_seconds=90.0, n_test=32, 
         if steps % 200 == 0:
             print(f"[bench] learned: step {steps} loss {np.mean(losses[-50:]):.4e}", file=sys.stderr, flush=True)
     train_s = time.perf_counter() - t0
-    # judge: network against the V-cycle on held-out patches
+    # evaluation: network against the V-cycle on held-out patches
     J, G = L.lor_nn_shape(nn)
     errs = []
     Y = torch.zeros((64, G ** 3), dtype=torch.float32, device=dev)
