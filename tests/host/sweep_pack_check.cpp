@@ -131,8 +131,9 @@ static bool replay(const std::vector<char> &blk, std::vector<T> &Y) {
   return true;
 }
 
-template <typename T>
-static void run_case(int dim, const int *m, unsigned seed) {
+// Random symmetric stencil rows with negative couplings, strictly
+// diagonally dominant (n x 3^dim, slot order, x fastest).
+static std::vector<double> random_rows(int dim, const int *m, unsigned seed) {
   const int NS = dim == 3 ? 27 : 9, C = NS / 2;
   const int mx = m[0], my = m[1], mz = dim == 3 ? m[2] : 1, n = mx * my * mz;
   auto nb = [&](int i, int s) {
@@ -141,7 +142,6 @@ static void run_case(int dim, const int *m, unsigned seed) {
     if (jx < 0 || jx >= mx || jy < 0 || jy >= my || jz < 0 || jz >= mz) return -1;
     return jx + mx * (jy + my * jz);
   };
-  // symmetric, negative couplings, strictly diagonally dominant
   std::mt19937 g(seed);
   std::uniform_real_distribution<double> U(0.2, 1.5);
   std::vector<double> rows(size_t(n) * NS, 0.0);
@@ -158,6 +158,21 @@ static void run_case(int dim, const int *m, unsigned seed) {
     for (int s = 0; s < NS; ++s) d -= rows[size_t(i) * NS + s];
     rows[size_t(i) * NS + C] = d;
   }
+  return rows;
+}
+
+template <typename T>
+static void run_case(int dim, const int *m, std::vector<double> rows, unsigned seed, const char *kind) {
+  const int NS = dim == 3 ? 27 : 9, C = NS / 2;
+  const int mx = m[0], my = m[1], mz = dim == 3 ? m[2] : 1, n = mx * my * mz;
+  auto nb = [&](int i, int s) {
+    const int ix = i % mx, iy = (i / mx) % my, iz = i / (mx * my);
+    const int jx = ix + s % 3 - 1, jy = iy + (s / 3) % 3 - 1, jz = iz + (dim == 3 ? s / 9 - 1 : 0);
+    if (jx < 0 || jx >= mx || jy < 0 || jy >= my || jz < 0 || jz >= mz) return -1;
+    return jx + mx * (jy + my * jz);
+  };
+  std::mt19937 g(seed + 1000);
+  std::uniform_real_distribution<double> U(0.2, 1.5);
   MdfResult res;
   if (mdf_factor(dim, m, rows, false, res) != LOR_OK) {
     std::printf("FAIL: MDF factorization\n");
@@ -207,18 +222,48 @@ static void run_case(int dim, const int *m, unsigned seed) {
   const double tol = sizeof(T) == 4 ? 2e-6 : 1e-13;
   const bool ok = okf && okb && failures == f0 && ef < tol && eb < tol;
   if (!ok && failures == f0) ++failures;
-  std::printf("%-6s %dD %2dx%2dx%2d depth %4d: forward %.1e backward %.1e %s\n", sizeof(T) == 4 ? "float" : "double",
-              dim, mx, my, mz, depth, ef, eb, ok ? "ok" : "FAILED");
+  std::printf("%-6s %-6s %dD %2dx%2dx%2d depth %4d: forward %.1e backward %.1e %s\n", kind,
+              sizeof(T) == 4 ? "float" : "double", dim, mx, my, mz, depth, ef, eb, ok ? "ok" : "FAILED");
 }
 
-int main() {
+// Usage: sweep_pack_check [file]; the optional file holds further cases as
+// text: the number of cases, then per case "dim m0 m1 m2" and the n x 3^dim
+// stencil rows (for example LOR patch stencils).
+int main(int argc, char **argv) {
   const int cases[][4] = {{3, 11, 11, 11}, {3, 11, 11, 5}, {3, 5, 11, 5}, {3, 5, 5, 5}, {3, 3, 3, 3}, {3, 1, 1, 1},
                           {3, 23, 23, 23}, {3, 13, 7, 9}, {2, 11, 11, 1}, {2, 29, 29, 1}, {2, 1, 3, 1}};
   unsigned seed = 1;
   for (const auto &c : cases) {
-    run_case<float>(c[0], c + 1, seed);
-    run_case<double>(c[0], c + 1, seed);
+    const std::vector<double> rows = random_rows(c[0], c + 1, seed);
+    run_case<float>(c[0], c + 1, rows, seed, "random");
+    run_case<double>(c[0], c + 1, rows, seed, "random");
     ++seed;
+  }
+  if (argc > 1) {
+    FILE *f = std::fopen(argv[1], "r");
+    int ncase = 0;
+    if (!f || std::fscanf(f, "%d", &ncase) != 1) {
+      std::printf("FAIL: cannot read %s\n", argv[1]);
+      return 1;
+    }
+    for (int c = 0; c < ncase; ++c) {
+      int dim, m[3];
+      if (std::fscanf(f, "%d %d %d %d", &dim, &m[0], &m[1], &m[2]) != 4) {
+        std::printf("FAIL: bad case header\n");
+        return 1;
+      }
+      const size_t cnt = size_t(m[0]) * m[1] * (dim == 3 ? m[2] : 1) * (dim == 3 ? 27 : 9);
+      std::vector<double> rows(cnt);
+      for (double &v : rows)
+        if (std::fscanf(f, "%lf", &v) != 1) {
+          std::printf("FAIL: short rows\n");
+          return 1;
+        }
+      run_case<float>(dim, m, rows, seed, "file");
+      run_case<double>(dim, m, rows, seed, "file");
+      ++seed;
+    }
+    std::fclose(f);
   }
   std::printf("%s (%d failures)\n", failures ? "FAILED" : "all ok", failures);
   return failures != 0;
