@@ -674,6 +674,7 @@ const char *lor_error_string(int code) {
 
 int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const lor_options_t *opt,
               void *stream, lor_handle_t **out) {
+  g_detail[0] = '\0';
   if (!out) return LOR_EINVAL;
   *out = nullptr;
   if (!mesh || !mesh->vertex_xyz) return LOR_EINVAL;

@@ -41,7 +41,7 @@ LOR_T_APPLY_A, LOR_T_PATCH, LOR_T_COARSE = 0, 1, 2
 class LorError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
-        detail = _lib.lor_last_error_detail().decode() if code == LOR_EHIP else ""
+        detail = _lib.lor_last_error_detail().decode() if code in (LOR_EHIP, LOR_EINVAL) else ""
         super().__init__(f"{where}: {error_string(code)} ({code}) {detail}")
 
 
