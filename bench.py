@@ -22,6 +22,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+STATUS_NAMES = {0: "ok", -4: "breakdown", -5: "no_convergence", -9: "accuracy_floor"}
 
 
 def patch_algorithmic_bytes(dim, n, p, prec_bytes=8):
@@ -98,7 +99,10 @@ def dg_measure(L, torch, dim, n, p, rtol, steps, precision):
             torch.cuda.synchronize()
             ms = 1e3 * (time.perf_counter() - t0) / steps
             run = {"method": meth, "eta": eta, "N": N, "iters": info.iters, "status": info.status,
-                   "rel_res_true": info.rel_res_true, "ms_per_solve": ms, "dofs_per_s": N / (ms * 1e-3)}
+                   "status_name": STATUS_NAMES.get(info.status, str(info.status)),
+                   "rel_res_true": info.rel_res_true, "reached_rtol": info.rel_res_true <= rtol,
+                   "replacements": info.replacements, "ms_per_solve": ms,
+                   "dofs_per_s": N / (ms * 1e-3)}
             if fac == 1:
                 xr = torch.tensor(inputs.uniform_vector(N, 3), device=dev)
                 y = torch.empty_like(xr)
@@ -117,7 +121,8 @@ def dg_measure(L, torch, dim, n, p, rtol, steps, precision):
                 run["operator_hbm_frac"] = ab / t_apply / (HBM_PEAK_GBS * 1e9)
             L.lor_free(h)
             print(f"[bench] DG {meth} eta={eta:g}: {ms:.2f} ms/solve, iters={info.iters}, "
-                  f"rel_res_true={info.rel_res_true:.2e}", file=sys.stderr, flush=True)
+                  f"rel_res_true={info.rel_res_true:.2e}, status={run['status_name']}, "
+                  f"replacements={info.replacements}", file=sys.stderr, flush=True)
             out["runs"].append(run)
     return out
 
@@ -398,11 +403,133 @@ def cpu_baseline(dim, p, iters_full, budget_s=25.0):
     t_iter = dt / k
     Ns = K.shape[0]
     value = Ns / (t_iter * iters_full)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": value, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "host_cpu_count": os.cpu_count(),
             "sample": (f"float64 NumPy/SciPy oracle, 1 thread: {k} PCG iterations on the same "
                        f"workload at 2^3 elements (N={Ns}), {t_iter * 1e3:.1f} ms/iteration; "
                        f"DOF/s = N_sample / (t_iter_sample * {iters_full} iterations of the full "
                        f"solve), i.e. per-iteration cost taken linear in N; setup excluded")}
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Measured HBM bandwidth of a plain device copy (read + write bytes per
+    second), the practical ceiling beside the 8 TB/s specification."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbs
+
+
+def solve_timed(L, torch, h, b, x, rtol, steps, maxit=1000):
+    """One untimed solve, then `steps` timed solves (host clock around
+    synchronized solves).  Returns (info, ms per solve)."""
+    info = L.lor_pcg_solve(h, b, x, rtol=rtol, maxit=maxit, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = L.lor_pcg_solve(h, b, x, rtol=rtol, maxit=maxit, check=False)
+    torch.cuda.synchronize()
+    return info, 1e3 * (time.perf_counter() - t0) / steps
+
+
+def p_sweep(L, torch, dim, n, degrees, rtol, steps):
+    """Iterations and DOF/s against p on the benchmark mesh (seed 1): float64
+    PCG and the float32-preconditioner flexible CG, f from the manufactured
+    solution."""
+    from paper_1908_07071_amd import inputs
+    V = inputs.structured_vertices(dim, n, 0.1, seed=1)
+    out = []
+    for p in degrees:
+        rec = {"p": p}
+        for prec, code in (("fp64", L.LOR_PREC_FP64), ("mixed", L.LOR_PREC_MIXED)):
+            opt = L.lor_default_options()
+            opt.precision = code
+            h = L.lor_setup(dim, n, V, p, options=opt)
+            N = L.lor_ndofs(h)
+            f = torch.tensor(inputs.manufactured_f(L.lor_dof_coords(h, dim)), device="cuda:0")
+            b = torch.empty_like(f)
+            L.lor_assemble_rhs(h, f, b)
+            x = torch.zeros_like(b)
+            info, ms = solve_timed(L, torch, h, b, x, rtol, steps)
+            rec["N"] = N
+            rec[prec] = {"iters": info.iters, "status": STATUS_NAMES.get(info.status, str(info.status)),
+                         "rel_res_true": info.rel_res_true, "ms_per_solve": ms,
+                         "dofs_per_s": N / (ms * 1e-3), "setup_s": info.t_setup}
+            L.lor_free(h)
+            del b, x, f
+        print(f"[bench] p={p}: N={rec['N']} fp64 {rec['fp64']['iters']} it "
+              f"{rec['fp64']['ms_per_solve']:.1f} ms, mixed {rec['mixed']['iters']} it "
+              f"{rec['mixed']['ms_per_solve']:.1f} ms", file=sys.stderr, flush=True)
+        out.append(rec)
+    return out
+
+
+def ordering_variants(L, torch, dim, n, p, rtol, steps, names):
+    """The float32-preconditioner solve of the benchmark workload with other
+    ILU(0) orderings: iterations, time per solve and per patch launch, and
+    the dependency depth of the level-0 sweeps (the chain of steps a patch
+    sweep must take one after another)."""
+    import numpy as np
+
+    from paper_1908_07071_amd import inputs
+    V = inputs.structured_vertices(dim, n, 0.1, seed=1)
+    codes = {"mdf": L.LOR_ORD_MDF, "natural": L.LOR_ORD_NATURAL}
+    if hasattr(L, "LOR_ORD_RCM"):
+        codes["rcm"] = L.LOR_ORD_RCM
+    out = {}
+    for name in names:
+        if name not in codes:
+            continue
+        opt = L.lor_default_options()
+        opt.precision = L.LOR_PREC_MIXED
+        opt.ordering = codes[name]
+        h = L.lor_setup(dim, n, V, p, options=opt)
+        N = L.lor_ndofs(h)
+        f = torch.tensor(inputs.manufactured_f(L.lor_dof_coords(h, dim)), device="cuda:0")
+        b = torch.empty_like(f)
+        L.lor_assemble_rhs(h, f, b)
+        x = torch.zeros_like(b)
+        L.lor_pcg_solve(h, b, x, rtol=rtol, maxit=1000, check=False)
+        torch.cuda.synchronize()
+        L.lor_timing(h, True)
+        info, ms = solve_timed(L, torch, h, b, x, rtol, steps)
+        tP, nP = L.lor_timing_read(h, L.LOR_T_PATCH)
+        L.lor_timing(h, False)
+        soff = L.lor_export_maps(h, L.LOR_MAP_SCHEDULE_OFFSET)
+        nlev = len(L.lor_export_maps(h, L.LOR_MAP_ORDER_OFFSET)) - 1
+        J = (n + 1) ** dim
+        nf = nlev // J
+        depth0 = np.diff(soff)[0::nf] - 1 if nf else np.zeros(0)
+        out[name] = {"iters": info.iters, "status": STATUS_NAMES.get(info.status, str(info.status)),
+                     "rel_res_true": info.rel_res_true, "ms_per_solve": ms,
+                     "dofs_per_s": N / (ms * 1e-3), "patch_launch_ms": tP / max(nP, 1),
+                     "level0_depth_max": int(depth0.max()) if len(depth0) else 0,
+                     "level0_depth_mean": float(depth0.mean()) if len(depth0) else 0.0,
+                     "setup_s": info.t_setup}
+        print(f"[bench] ordering {name}: {info.iters} it, {ms:.2f} ms/solve, patch launch "
+              f"{out[name]['patch_launch_ms']:.3f} ms, level-0 depth max {out[name]['level0_depth_max']}",
+              file=sys.stderr, flush=True)
+        L.lor_free(h)
+    return out
 
 
 def main():
@@ -419,6 +546,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dg", action="store_true", help="skip the DG (IP/BR2, 12^3, p=6) runs")
     ap.add_argument("--dg-n", type=int, default=12)
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the p sweep (p = 2, 4, 6, 8 on the benchmark mesh) and ordering variants")
+    ap.add_argument("--orderings", default="mdf,rcm,natural",
+                    help="ILU(0) orderings compared on the benchmark workload")
     ap.add_argument("--batch", type=int, default=0, metavar="NPROB",
                     help="only run the batched workload with NPROB problems (64 in the config)")
     ap.add_argument("--batch-rhs", type=int, default=4)
@@ -572,6 +703,7 @@ def main():
                          + ("FP64 flexible CG with FP32 " if args.precision == "mixed" else "FP64 PCG with FP64 ")
                          + f"LOR vertex-patch Schwarz (MDF-ILU(0) V-cycles, exact coarse) to {args.rtol:g}"),
             "N": N, "iters": info.iters, "rel_res_true": info.rel_res_true,
+            "status": STATUS_NAMES.get(info.status, str(info.status)),
             "precision": args.precision, "setup_s": round(setup_s, 3),
             "device_bytes": dev_bytes,
         },
@@ -589,6 +721,13 @@ def main():
             "algorithmic_bytes_per_launch": abytes, "avg_launch_ms": avg_ms,
         },
     }
+    out["hbm_copy_gbs"] = copy_bandwidth(torch)
+    out["roofline"]["frac_of_copy"] = achieved / out["hbm_copy_gbs"]
+    out["operator_hbm_frac"] = apply_algorithmic_bytes(dim, n, p) / t_apply / (HBM_PEAK_GBS * 1e9)
+    if not args.no_sweep:
+        out["p_sweep"] = p_sweep(L, torch, dim, n, (2, 4, 6, 8), args.rtol, 2)
+        out["orderings"] = ordering_variants(L, torch, dim, n, p, args.rtol, 3,
+                                             [o for o in args.orderings.split(",") if o])
     if not args.no_dg:
         out["dg"] = dg_measure(L, torch, dim, args.dg_n, p, args.rtol, 1, args.precision)
     if not args.no_cpu_baseline:

@@ -52,6 +52,11 @@ extern "C" {
 #define LOR_EHIP       -6  /* HIP runtime error                               */
 #define LOR_ENOMEM     -7  /* workspace missing or too small                  */
 #define LOR_ESTATE     -8  /* call not valid in the handle's current state    */
+#define LOR_EACCURACY  -9  /* the recursive residual reached rtol but the true
+                              residual ||b - A x|| stays above it after
+                              residual replacement: rtol lies below the
+                              accuracy float64 attains for this operator
+                              (x and info hold the best iterate)           */
 
 typedef struct lor_handle lor_handle_t;   /* opaque, owned by the library */
 
@@ -84,11 +89,14 @@ typedef struct {
 } lor_options_t;
 
 typedef struct {
-  int    iters;        /* CG iterations performed                          */
-  int    status;       /* LOR_OK, LOR_ENOCONV or LOR_EBREAKDOWN            */
+  int    iters;        /* CG iterations performed (all restarts together)  */
+  int    status;       /* LOR_OK, LOR_ENOCONV, LOR_EACCURACY, LOR_EBREAKDOWN */
   double rel_res;      /* ||r_k||_2 / ||b||_2 of the recursive residual    */
   double rel_res_true; /* ||b - A x||_2 / ||b||_2 recomputed at exit       */
   double t_solve;      /* seconds, measured with HIP events                */
+  double t_setup;      /* seconds lor_setup took for this handle (host clock) */
+  int    replacements; /* residual replacements (restarts from b - A x)    */
+  int    reserved;
 } lor_solve_info_t;
 
 /* Fill *opt with the defaults (FP64, MDF, PCG, all cores). */
@@ -150,11 +158,16 @@ int lor_apply_A(lor_handle_t *h, const double *x_dev, double *y_dev, void *strea
  * Neumann handle (no preconditioner). */
 int lor_apply_P(lor_handle_t *h, const double *r_dev, double *z_dev, void *stream);
 
-/* Solve A x = b by preconditioned (or flexible) CG from x = 0 until
- * ||r_k||_2 <= rtol ||b||_2 (recursive residual) or maxit iterations.
+/* Solve A x = b by preconditioned (or flexible) CG (Section 4) from x = 0
+ * until ||r_k||_2 <= rtol ||b||_2 (recursive residual) or maxit iterations.
+ * When the recursive residual meets rtol, the true residual b - A x is
+ * computed; if it is above rtol ||b||_2 the iteration restarts from it
+ * (residual replacement: r = b - A x, z = B r, p = z) while the true
+ * residual keeps falling by at least 4x per restart, at most 4 times.
  * b_dev: DEVICE in; x_dev: DEVICE out.  info: HOST out, may be NULL.
- * Returns LOR_OK, LOR_ENOCONV (x holds the last iterate) or
- * LOR_EBREAKDOWN. */
+ * Returns LOR_OK (true residual <= rtol ||b||_2), LOR_ENOCONV (maxit
+ * reached; x holds the last iterate), LOR_EACCURACY (true residual stuck
+ * above rtol) or LOR_EBREAKDOWN. */
 int lor_pcg_solve(lor_handle_t *h, const double *b_dev, double *x_dev,
                   double rtol, int maxit, lor_solve_info_t *info, void *stream);
 

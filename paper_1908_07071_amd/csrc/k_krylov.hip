@@ -75,14 +75,16 @@ __global__ __launch_bounds__(256) void k_p_update(double *__restrict__ p, double
   }
 }
 
-// partial sums of (b - y)^2
-__global__ __launch_bounds__(256) void k_sub_dot(const double *__restrict__ b,
-                                                 const double *__restrict__ y, int64_t n,
-                                                 double *__restrict__ partials) {
+// partial sums of (b - y)^2; with res != nullptr also res = b - y (res may
+// be y itself: every element is read before it is written by the same lane)
+__global__ __launch_bounds__(256) void k_sub_dot(const double *__restrict__ b, const double *y,
+                                                 int64_t n, double *__restrict__ partials,
+                                                 double *res) {
   double acc = 0.0;
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
     const double d = b[i] - y[i];
+    if (res) res[i] = d;
     acc += d * d;
   }
   const double s = block_sum(acc);
@@ -205,8 +207,8 @@ hipError_t launch_p_update(double *p, double *q, const double *z, int64_t n, con
 }
 
 hipError_t launch_sub_dot(const double *b, const double *y, int64_t n, double *partials,
-                          hipStream_t st) {
-  k_sub_dot<<<grid_for(n, 256), 256, 0, st>>>(b, y, n, partials);
+                          hipStream_t st, double *res) {
+  k_sub_dot<<<grid_for(n, 256), 256, 0, st>>>(b, y, n, partials, res);
   return hipGetLastError();
 }
 

@@ -605,25 +605,59 @@ int pcg_iterations(lor_handle *h, Work &w, double *x, int count, hipStream_t st)
   return LOR_OK;
 }
 
-// Enqueues the true residual ||b - A x||^2 and copies the scalars to w.h_scal
-// (synchronizes the stream).
-int pcg_finish(lor_handle *h, Work &w, const double *b, const double *x, double rtol,
-               hipStream_t st) {
-  (void)rtol;
+// Enqueues the true residual ||b - A x||^2 (w.tmp receives b - A x) and
+// copies the scalars to w.h_scal (synchronizes the stream).
+int pcg_finish(lor_handle *h, Work &w, const double *b, const double *x, hipStream_t st) {
   const int64_t N = h->ndofs;
   const bool zero_q = h->method == LOR_CG && !apply_cg_uses_skeleton(h->md);
   if (zero_q) HIPCHK(launch_fill(w.tmp, N, 0.0, st));
   int rc = apply_A_impl(h, w, x, w.tmp, nullptr, nullptr, st);
   if (rc != LOR_OK) return rc;
-  HIPCHK(launch_sub_dot(b, w.tmp, N, w.part, st));
+  HIPCHK(launch_sub_dot(b, w.tmp, N, w.part, st, w.tmp));
   HIPCHK(launch_finalize(w.scal, w.part, red_blocks(N), FIN_RRTRUE, nullptr, st));
   HIPCHK(hipMemcpyAsync(w.h_scal, w.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   return LOR_OK;
 }
 
+constexpr int kMaxReplace = 4;  // residual replacements per solve
+
+// Residual replacement after pcg_finish: decides from w.h_scal whether the
+// recursive residual met rtol while the true one did not, and if so enqueues
+// a restart from the true residual: r = b - A x (left in w.tmp by
+// pcg_finish), z = B r, rho = r.z, p = z, with the iteration count kept.
+// Restarts stop once the true residual no longer falls by 4x (the float64
+// attainable accuracy of the operator has been reached).  *restarted tells
+// the caller to run more iterations.
+int pcg_replace(lor_handle *h, Work &w, double rtol, int maxit, int &nrep, double &last_true,
+                bool *restarted, hipStream_t st) {
+  *restarted = false;
+  const double *hs = w.h_scal;
+  const double bb = hs[S_BB], rr = hs[S_RR], rt = hs[S_RRTRUE];
+  const double tol2 = rtol * rtol * bb;
+  if (hs[S_FAIL] != 0.0 || !(rr <= tol2) || rt <= tol2) return LOR_OK;
+  if (int(hs[S_ITERS]) >= maxit || nrep >= kMaxReplace || !(rt < 0.0625 * last_true))
+    return LOR_OK;
+  last_true = rt;
+  ++nrep;
+  const int64_t N = h->ndofs;
+  double *s = w.scal;
+  HIPCHK(launch_copy(w.r, w.tmp, N, st));
+  HIPCHK(launch_fill(s + S_DONE, 1, 0.0, st));
+  HIPCHK(launch_fill(s + S_RR, 1, rt, st));
+  int rc = apply_P_impl(h, w, w.r, w.z, s, st);
+  if (rc != LOR_OK) return rc;
+  HIPCHK(launch_dot_partials(w.r, w.z, N, w.part, s, st));
+  HIPCHK(launch_finalize(s, w.part, red_blocks(N), FIN_RHO, nullptr, st));
+  HIPCHK(launch_copy(w.p, w.z, N, st));
+  if (h->method == LOR_CG && !apply_cg_uses_skeleton(h->md)) HIPCHK(launch_fill(w.q, N, 0.0, st));
+  *restarted = true;
+  return LOR_OK;
+}
+
 // Status and info from the scalars in w.h_scal.
-int pcg_status(const Work &w, double rtol, double t_solve, lor_solve_info_t *info) {
+int pcg_status(const lor_handle *h, const Work &w, double rtol, double t_solve, int nrep,
+               lor_solve_info_t *info) {
   const double *hs = w.h_scal;
   const double bb = hs[S_BB], rr = hs[S_RR], rt = hs[S_RRTRUE], fail = hs[S_FAIL];
   int status = LOR_OK;
@@ -631,12 +665,17 @@ int pcg_status(const Work &w, double rtol, double t_solve, lor_solve_info_t *inf
     status = fail == 2.0 ? LOR_EINVAL : LOR_EBREAKDOWN;
   else if (!(rr <= rtol * rtol * bb))
     status = LOR_ENOCONV;
+  else if (!(rt <= rtol * rtol * bb))
+    status = LOR_EACCURACY;
   if (info) {
     info->iters = int(hs[S_ITERS]);
     info->status = status;
     info->rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
     info->rel_res_true = bb > 0 ? std::sqrt(rt / bb) : 0.0;
     info->t_solve = t_solve;
+    info->t_setup = h->t_setup;
+    info->replacements = nrep;
+    info->reserved = 0;
   }
   return status;
 }
@@ -668,6 +707,8 @@ const char *lor_error_string(int code) {
     case LOR_EHIP: return "HIP runtime error";
     case LOR_ENOMEM: return "workspace missing or too small";
     case LOR_ESTATE: return "call not valid in the current state";
+    case LOR_EACCURACY:
+      return "recursive residual converged but the true residual stays above the tolerance";
     default: return "unknown error";
   }
 }
@@ -677,6 +718,7 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const l
   g_detail[0] = '\0';
   if (!out) return LOR_EINVAL;
   *out = nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
   if (!mesh || !mesh->vertex_xyz) return LOR_EINVAL;
   if (mesh->dim != 2 && mesh->dim != 3) return LOR_EINVAL;
   if (p < 1 || p > kMaxP) return LOR_EINVAL;
@@ -707,10 +749,12 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const l
   for (double v : h->verts)
     if (!std::isfinite(v)) return LOR_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  HIPCHK(hipGetDevice(&h->device));
   int rc = setup_impl(*h, st);
   if (rc != LOR_OK) return rc;
   rc = work_alloc(*h, h->w, h->allocs, h->bytes);
   if (rc != LOR_OK) return rc;
+  h->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = h.release();
   return LOR_OK;
 }
@@ -786,23 +830,28 @@ int lor_pcg_solve(lor_handle_t *h, const double *b, double *x, double rtol, int 
   HIPCHK(hipEventRecord(h->ev0, st));
   int rc = pcg_init(h, w, b, x, rtol, maxit, st);
   if (rc != LOR_OK) return rc;
-  int it = 0;
-  bool done = maxit == 0;
-  while (!done) {
-    const int k = std::min(kChunk, maxit - it);
-    rc = pcg_iterations(h, w, x, k, st);
+  int nrep = 0;
+  double last_true = HUGE_VAL;
+  for (;;) {
+    bool done = maxit == 0;
+    while (!done) {
+      rc = pcg_iterations(h, w, x, kChunk, st);
+      if (rc != LOR_OK) return rc;
+      HIPCHK(hipMemcpyAsync(w.h_scal, w.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      done = w.h_scal[S_DONE] != 0.0;  // also set on the device at maxit
+    }
+    HIPCHK(hipEventRecord(h->ev1, st));
+    rc = pcg_finish(h, w, b, x, st);
     if (rc != LOR_OK) return rc;
-    it += k;
-    HIPCHK(hipMemcpyAsync(w.h_scal, w.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    done = w.h_scal[S_DONE] != 0.0 || it >= maxit;
+    bool again = false;
+    rc = pcg_replace(h, w, rtol, maxit, nrep, last_true, &again, st);
+    if (rc != LOR_OK) return rc;
+    if (!again) break;
   }
-  HIPCHK(hipEventRecord(h->ev1, st));
-  rc = pcg_finish(h, w, b, x, rtol, st);
-  if (rc != LOR_OK) return rc;
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-  return pcg_status(w, rtol, ms * 1e-3, info);
+  return pcg_status(h, w, rtol, ms * 1e-3, nrep, info);
 }
 
 int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const double *const *b,
@@ -823,8 +872,10 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
     Work w;
     hipStream_t st = nullptr;
     hipGraphExec_t chunk = nullptr;
-    int it = 0;
-    bool done = false;
+    int64_t it = 0;
+    bool done = false, final = false;
+    int nrep = 0;
+    double last_true = HUGE_VAL;
   };
   std::vector<Pair> pairs(npair);
   std::vector<void *> owned;
@@ -896,33 +947,55 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
     if (rc != LOR_OK) return fail(rc);
     q.done = maxit == 0;
   }
-  for (;;) {
-    bool any = false;
-    for (Pair &q : pairs) {
-      if (q.done) continue;
-      any = true;
-      BCHK(hipGraphLaunch(q.chunk, q.st));
-      BCHK(hipMemcpyAsync(q.w.h_scal, q.w.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
-                          q.st));
-      q.it += kChunk;
-    }
-    if (!any) break;
-    for (hipStream_t t : streams) BCHK(hipStreamSynchronize(t));
-    for (Pair &q : pairs)
-      if (!q.done) q.done = q.w.h_scal[S_DONE] != 0.0 || q.it >= maxit;
-  }
-  // every worker stream has been synchronized: stop marks the end of the
-  // iterations of all pairs
-  BCHK(hipEventRecord(stop, streams[0]));
-  BCHK(hipEventSynchronize(stop));
+  // the device sets each pair's flag at convergence or at maxit; the host
+  // bound only guards against a flag that never comes
+  const int64_t it_cap = int64_t(maxit + kChunk) * (kMaxReplace + 1);
   float ms = 0.f;
-  BCHK(hipEventElapsedTime(&ms, start, stop));
+  for (;;) {
+    for (;;) {
+      bool any = false;
+      for (Pair &q : pairs) {
+        if (q.done) continue;
+        any = true;
+        BCHK(hipGraphLaunch(q.chunk, q.st));
+        BCHK(hipMemcpyAsync(q.w.h_scal, q.w.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                            q.st));
+        q.it += kChunk;
+      }
+      if (!any) break;
+      for (hipStream_t t : streams) BCHK(hipStreamSynchronize(t));
+      for (Pair &q : pairs)
+        if (!q.done) q.done = q.w.h_scal[S_DONE] != 0.0 || q.it >= it_cap;
+    }
+    // every worker stream has been synchronized: stop marks the end of the
+    // iterations of all pairs
+    BCHK(hipEventRecord(stop, streams[0]));
+    BCHK(hipEventSynchronize(stop));
+    BCHK(hipEventElapsedTime(&ms, start, stop));
+    // true residuals; residual replacement for pairs whose recursive
+    // residual drifted below rtol ahead of the true one
+    bool again = false;
+    for (int k = 0; k < npair; ++k) {
+      Pair &q = pairs[k];
+      if (q.final) continue;
+      rc = pcg_finish(q.h, q.w, b[k], x[k], q.st);
+      if (rc != LOR_OK) return fail(rc);
+      bool restarted = false;
+      rc = pcg_replace(q.h, q.w, rtol, maxit, q.nrep, q.last_true, &restarted, q.st);
+      if (rc != LOR_OK) return fail(rc);
+      if (restarted) {
+        q.done = false;
+        again = true;
+      } else {
+        q.final = true;
+      }
+    }
+    if (!again) break;
+  }
   int status = LOR_OK;
   for (int k = 0; k < npair; ++k) {
     Pair &q = pairs[k];
-    rc = pcg_finish(q.h, q.w, b[k], x[k], rtol, q.st);
-    if (rc != LOR_OK) return fail(rc);
-    const int sk = pcg_status(q.w, rtol, ms * 1e-3, info ? info + k : nullptr);
+    const int sk = pcg_status(q.h, q.w, rtol, ms * 1e-3, q.nrep, info ? info + k : nullptr);
     if (status == LOR_OK) status = sk;
   }
 #undef BCHK

@@ -30,6 +30,8 @@ struct Work {
 struct lor_handle {
   int dim = 3, n[3] = {1, 1, 1}, p = 1, method = LOR_CG, bc = LOR_BC_DIRICHLET;
   double penalty = 0.0;
+  double t_setup = 0.0;  // seconds lor_setup took (host clock)
+  int device = 0;        // HIP device current at lor_setup (holds the handle's memory)
   lor_options_t opt{};
   MeshDims md{};
   std::vector<double> verts, gllx, gllw, D;

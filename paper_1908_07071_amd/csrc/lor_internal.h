@@ -274,7 +274,8 @@ hipError_t launch_cg_update(double *x, double *r, double *rold, const double *p,
 hipError_t launch_p_update(double *p, double *q, const double *z, int64_t n, const double *scal,
                            hipStream_t st);
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
+// partials of ||b - y||^2; res (optional, may equal y) receives b - y
 hipError_t launch_sub_dot(const double *b, const double *y, int64_t n, double *partials,
-                          hipStream_t st);
+                          hipStream_t st, double *res = nullptr);
 
 }  // namespace lor

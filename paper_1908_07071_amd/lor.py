@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblor.so")
 
 LOR_OK, LOR_EINVAL, LOR_EJACOBIAN, LOR_EPIVOT = 0, -1, -2, -3
 LOR_EBREAKDOWN, LOR_ENOCONV, LOR_EHIP, LOR_ENOMEM, LOR_ESTATE = -4, -5, -6, -7, -8
+LOR_EACCURACY = -9
 LOR_CG, LOR_IP, LOR_BR2 = 0, 1, 2
 LOR_BC_DIRICHLET, LOR_BC_NEUMANN = 0, 1
 LOR_PREC_FP64, LOR_PREC_MIXED = 0, 1
@@ -41,7 +42,8 @@ LOR_T_APPLY_A, LOR_T_PATCH, LOR_T_COARSE = 0, 1, 2
 class LorError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
-        detail = _lib.lor_last_error_detail().decode() if code in (LOR_EHIP, LOR_EINVAL) else ""
+        detail = (_lib.lor_last_error_detail().decode() if code in (LOR_EHIP, LOR_EINVAL, LOR_ENOMEM)
+                  else "")
         super().__init__(f"{where}: {error_string(code)} ({code}) {detail}")
 
 
@@ -57,7 +59,8 @@ class lor_options_t(C.Structure):
 
 class lor_solve_info_t(C.Structure):
     _fields_ = [("iters", C.c_int), ("status", C.c_int), ("rel_res", C.c_double),
-                ("rel_res_true", C.c_double), ("t_solve", C.c_double)]
+                ("rel_res_true", C.c_double), ("t_solve", C.c_double), ("t_setup", C.c_double),
+                ("replacements", C.c_int), ("reserved", C.c_int)]
 
 
 def _load():

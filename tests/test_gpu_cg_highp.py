@@ -1,0 +1,161 @@
+"""GPU parity of the 3D CG path at the degrees p = 5, 7 and 8 against the
+CPU oracle (the element kernel is instantiated per degree: the plane kernel
+for 5 <= p+1 <= 8, the column kernel above; p = 8 also gives the 15^3-row
+level-0 patches of the p = 8 runs).
+
+Integer results (node map, MDF orders, dependency schedules) bit for bit;
+operator and preconditioner within 1e-12 of the largest reference entry;
+solves to the solver tolerance with the iteration count inside the oracle's
+band (tests/golden/oracle_bands.json, written by make_oracle_bands.py).
+"""
+import functools
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import highorder as HO, mdf, mesh as M, schwarz as S
+from paper_1908_07071_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+with open(os.path.join(HERE, "golden", "oracle_bands.json")) as _f:
+    BANDS = json.load(_f)
+
+CASES = [
+    # dim, n, p, perturb, seed
+    (3, (2, 2, 2), 5, 0.1, 8),
+    (3, (2, 1, 2), 7, 0.1, 9),
+    (3, (1, 2, 2), 8, 0.1, 10),
+]
+
+
+def _ids(c):
+    return f"cg-d{c[0]}-n{'x'.join(map(str, c[1]))}-p{c[2]}"
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle(case):
+    dim, n, p, pert, seed = case
+    V = inputs.structured_vertices(dim, list(n), pert, seed=seed)
+    mesh = M.make_mesh(dim, list(n), V)
+    return V, mesh, HO.cg_stiffness(mesh, p), S.SchwarzLOR(mesh, p)
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "HIP device required"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1908_07071_amd import lor
+    return lor
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_highp_orders_operator_preconditioner(case, L, torch_dev):
+    torch = torch_dev
+    dim, n, p = case[0], list(case[1]), case[2]
+    print("case", case, flush=True)
+    V, mesh, K, B = _oracle(case)
+    h = L.lor_setup(dim, n, V, p)
+    try:
+        N = L.lor_ndofs(h)
+        assert N == K.shape[0]
+        num = M.interior_numbering(M.grid_shape(mesh, p))
+        assert np.array_equal(L.lor_export_maps(h, L.LOR_MAP_LDOF), np.flatnonzero(num >= 0))
+        # MDF orders and dependency schedules of every (patch, level)
+        order = L.lor_export_maps(h, L.LOR_MAP_ORDER)
+        ooff = L.lor_export_maps(h, L.LOR_MAP_ORDER_OFFSET)
+        sched = L.lor_export_maps(h, L.LOR_MAP_SCHEDULE)
+        soff = L.lor_export_maps(h, L.LOR_MAP_SCHEDULE_OFFSET)
+        nf = B.H.nlevels - 1
+        t = 0
+        for P in B.patches:
+            for k in range(nf):
+                lv = P.levels[k]
+                got = order[ooff[t]:ooff[t + 1]]
+                if lv["graph"] is None:
+                    assert len(got) == 0
+                else:
+                    assert np.array_equal(got, lv["order"]), (P.v, k)
+                    assert soff[t + 1] - soff[t] - 1 == mdf.dependency_depth(lv["graph"], lv["order"])
+                t += 1
+        xin = inputs.uniform_vector(N, 11)
+        x = torch.tensor(xin, device="cuda")
+        y = torch.empty_like(x)
+        L.lor_apply_A(h, x, y)
+        torch.cuda.synchronize()
+        ref = K @ xin
+        err = np.abs(y.cpu().numpy() - ref).max() / np.abs(ref).max()
+        assert err <= 1e-12, err
+        z = torch.empty_like(x)
+        L.lor_apply_P(h, x, z)
+        torch.cuda.synchronize()
+        zref = B.apply(xin)
+        err = np.abs(z.cpu().numpy() - zref).max() / np.abs(zref).max()
+        assert err <= 1e-12, err
+    finally:
+        L.lor_free(h)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_highp_pcg_solve(case, L, torch_dev):
+    torch = torch_dev
+    dim, n, p = case[0], list(case[1]), case[2]
+    print("case", case, flush=True)
+    V, mesh, K, _ = _oracle(case)
+    band = BANDS[_ids(case)]
+    h = L.lor_setup(dim, n, V, p)
+    try:
+        N = L.lor_ndofs(h)
+        bin_ = inputs.gaussian_rhs(N, 21)
+        b = torch.tensor(bin_, device="cuda")
+        x = torch.zeros_like(b)
+        info = L.lor_pcg_solve(h, b, x, rtol=band["rtol"], maxit=500)
+        assert band["lo"] - 1 <= info.iters <= band["hi"] + 1, (info.iters, band)
+        xs = x.cpu().numpy()
+        rt = np.linalg.norm(bin_ - K @ xs) / np.linalg.norm(bin_)
+        assert rt <= 1.05e-10, rt
+        xd = spla.spsolve(K.tocsc(), bin_)
+        assert np.abs(xs - xd).max() <= 1e-7 * np.abs(xd).max()
+    finally:
+        L.lor_free(h)
+
+
+def test_square_8x8_p3_manufactured(L, torch_dev):
+    """2D unit square, 8 x 8 uniform quads, p = 3, f from u = sin(pi x) sin(pi y),
+    float64 PCG to 1e-10: iteration count inside the oracle's band, solution
+    equal to the direct solve's and close to u at the nodes."""
+    torch = torch_dev
+    band = BANDS["cg-square-8x8-p3-manufactured"]
+    dim, n, p = 2, [8, 8], 3
+    V = inputs.structured_vertices(dim, n)
+    mesh = M.make_mesh(dim, n, V)
+    h = L.lor_setup(dim, n, V, p)
+    try:
+        N = L.lor_ndofs(h)
+        assert N == band["N"] == 529
+        xy = L.lor_dof_coords(h, dim)
+        f = torch.tensor(inputs.manufactured_f(xy), device="cuda")
+        b = torch.empty_like(f)
+        L.lor_assemble_rhs(h, f, b)
+        x = torch.zeros_like(b)
+        info = L.lor_pcg_solve(h, b, x, rtol=1e-10, maxit=200)
+        assert band["lo"] - 1 <= info.iters <= band["hi"] + 1, (info.iters, band)
+        K = HO.cg_stiffness(mesh, p)
+        bn = b.cpu().numpy()
+        xs = x.cpu().numpy()
+        assert np.linalg.norm(bn - K @ xs) <= 1.05e-10 * np.linalg.norm(bn)
+        xd = spla.spsolve(K.tocsc(), bn)
+        assert np.abs(xs - xd).max() <= 1e-8 * np.abs(xd).max()
+        # discretization error at the nodes: O(h^(p+1)) at p = 3, h = 1/8
+        assert np.abs(xs - inputs.manufactured_u(xy)).max() <= 1e-4
+    finally:
+        L.lor_free(h)

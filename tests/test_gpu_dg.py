@@ -185,16 +185,27 @@ def test_dg_mixed_precision(case, L, torch_dev):
         err = np.linalg.norm(z.cpu().numpy() - zref) / np.linalg.norm(zref)
         assert err <= 2e-5, err
         x = torch.zeros_like(r)
-        info = L.lor_pcg_solve(h, r, x, rtol=1e-10, maxit=2000)
+        info = L.lor_pcg_solve(h, r, x, rtol=1e-10, maxit=2000, check=False)
         xo, it, _ = krylov.pcg(A, rin, B.apply, tol=1e-10, flexible=True)
-        # the float32 Schwarz part costs flexible CG some iterations at this
-        # tight tolerance (the float64 oracle preconditioner is the reference)
-        assert it - 1 <= info.iters <= 1.3 * it + 3, (info.iters, it)
         xs = x.cpu().numpy()
-        # at very large penalties rounding in A x limits the attainable true
-        # residual (about eps * cond(A)); the bound is the float64 oracle's own
-        rt_o = np.linalg.norm(rin - A @ xo) / np.linalg.norm(rin)
         rt = np.linalg.norm(rin - A @ xs) / np.linalg.norm(rin)
-        assert rt <= max(1.05e-10, 10 * rt_o), (rt, rt_o)
+        # attainable accuracy: the residual of the direct solution, which at
+        # very large penalties (about eps cond(A)) lies above 1e-10
+        xd = spla.spsolve(A.tocsc(), rin)
+        floor = np.linalg.norm(rin - A @ xd) / np.linalg.norm(rin)
+        print("iterations", info.iters, "oracle", it, "status", info.status, "true", rt,
+              "direct", floor, "replacements", info.replacements, flush=True)
+        if info.status == L.LOR_EACCURACY:
+            # only where 1e-10 is within a decade of what the direct solve attains
+            assert 1e-10 < 10 * floor, (floor, rt)
+            assert rt <= 10 * floor, (rt, floor)
+            assert info.replacements >= 1
+        else:
+            assert info.status == L.LOR_OK, info.status
+            assert info.rel_res_true <= 1e-10 and rt <= 1.05e-10, (info.rel_res_true, rt)
+            # the float32 Schwarz part costs flexible CG some iterations at
+            # this tight tolerance (the float64 oracle preconditioner is the
+            # reference)
+            assert it - 1 <= info.iters <= 1.3 * it + 3, (info.iters, it)
     finally:
         L.lor_free(h)

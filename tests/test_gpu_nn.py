@@ -221,3 +221,55 @@ def test_training_and_replace_preconditioner(L, torch_dev):
     finally:
         L.lor_nn_free(nn)
         L.lor_free(h)
+
+
+@pytest.mark.parametrize("channels", [16, 32])
+def test_p6_grid_forward_replace_warmstart(channels, L, torch_dev):
+    """p = 6: the 11^3 patch grid (G = 11), where the fused convolution gives
+    each wavefront a second output tile of the plane (G^2 = 121 > 64).
+    Forward pass, the network in place of the patch V-cycles, and the warm
+    start, each against the float64 reference with the same weights."""
+    torch = torch_dev
+    h, mesh, p = _problem(L, n=2, p=6, seed=13)
+    params = inputs.nn_initial_params(channels, seed=7)
+    nn = L.lor_nn_create(h, channels, params, max_batch=32)
+    try:
+        J, G = L.lor_nn_shape(nn)
+        assert G == 11
+        r, X, T, sc = _data(L, torch, nn, h, 9)
+        Y = torch.zeros((J, G ** 3), dtype=torch.float32, device="cuda")
+        L.lor_nn_forward(nn, X, J, Y)
+        torch.cuda.synchronize()
+        shapes = ONN.layer_shapes(channels)
+        P = ONN.unflatten(params, shapes)
+        yref, _ = ONN.forward(P, X.cpu().numpy().astype(np.float64), G)
+        err = np.linalg.norm(Y.cpu().numpy() - yref) / np.linalg.norm(yref)
+        print("channels", channels, "G = 11 forward error", err, flush=True)
+        assert err <= 3e-2, err
+        # every patch's output, not just the norm over all of them
+        Yg = Y.cpu().numpy()
+        for j in range(J):
+            nj = np.linalg.norm(yref[j])
+            if nj > 0:
+                assert np.linalg.norm(Yg[j] - yref[j]) <= 5e-2 * nj, j
+        B = S.SchwarzLOR(mesh, p)
+        rin = r.cpu().numpy()
+        z = torch.empty_like(r)
+        L.lor_nn_attach(h, nn, L.LOR_NN_REPLACE)
+        L.lor_apply_P(h, r, z)
+        torch.cuda.synchronize()
+        zref = ONN.preconditioner_replace(B, P, rin)
+        err = np.linalg.norm(z.cpu().numpy() - zref) / np.linalg.norm(zref)
+        print("replace parity", err, flush=True)
+        assert err <= 3e-2, err
+        L.lor_nn_attach(h, nn, L.LOR_NN_WARMSTART)
+        L.lor_apply_P(h, r, z)
+        torch.cuda.synchronize()
+        zw = ONN.preconditioner_warmstart(B, P, rin)
+        errw = np.linalg.norm(z.cpu().numpy() - zw) / np.linalg.norm(zw)
+        print("warm start parity", errw, flush=True)
+        assert errw <= 3e-2, errw
+        L.lor_nn_attach(h, None, L.LOR_NN_OFF)
+    finally:
+        L.lor_nn_free(nn)
+        L.lor_free(h)
