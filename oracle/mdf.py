@@ -173,6 +173,62 @@ def mdf_factor(g: PatchGraph, brute_force: bool = False):
     return np.array(order), L, D
 
 
+def factor_in_order(g: PatchGraph, order):
+    """IC(0) factor (L, D as in :func:`mdf_factor`) for a given elimination
+    order: the same elimination steps, the order fixed in advance."""
+    a = g.rows.copy()
+    elim = np.zeros(g.n, dtype=bool)
+    L = np.zeros((g.n, 3 ** g.dim))
+    D = np.zeros(g.n)
+    for i in order:
+        _eliminate(g, a, elim, int(i), L, D)
+    return np.asarray(order, dtype=np.int64), L, D
+
+
+def rcm_order(shape) -> np.ndarray:
+    """Reverse Cuthill-McKee order of a box of grid points (Section 3.4 names
+    RCM beside MDF; Cuthill and McKee 1969, reversed as George proposed).
+
+    The graph is the structural pattern of the patch matrices: two points are
+    adjacent iff their offsets differ by at most one per direction (the
+    values play no part, so every box of one shape gets one order).  Reading
+    of the unspecified choices: the start is a node of minimum degree, the
+    smallest index among them; the breadth-first search visits the not yet
+    numbered neighbours of each node in increasing degree, ties to the
+    smallest index; the Cuthill-McKee sequence is then reversed."""
+    shape = tuple(int(s) for s in shape)
+    dim = len(shape)
+    n = int(np.prod(shape))
+    strides = [int(np.prod(shape[:t])) for t in range(dim)]
+    coords = [[(i // strides[t]) % shape[t] for t in range(dim)] for i in range(n)]
+    offs = [o for o in _slots(dim) if any(o)]
+    nbrs = []
+    for c in coords:
+        row = []
+        for o in offs:
+            q = [c[t] + o[t] for t in range(dim)]
+            if all(0 <= q[t] < shape[t] for t in range(dim)):
+                row.append(sum(q[t] * strides[t] for t in range(dim)))
+        nbrs.append(sorted(row))
+    deg = [len(r) for r in nbrs]
+    numbered = [False] * n
+    cm = []
+    while len(cm) < n:
+        start = min((i for i in range(n) if not numbered[i]), key=lambda i: (deg[i], i))
+        numbered[start] = True
+        queue = [start]
+        head = 0
+        while head < len(queue):
+            u = queue[head]
+            head += 1
+            cm.append(u)
+            nxt = sorted((v for v in nbrs[u] if not numbered[v]), key=lambda v: (deg[v], v))
+            for v in nxt:
+                numbered[v] = True
+                queue.append(v)
+    return np.array(cm[::-1], dtype=np.int64)
+
+
 def ic0_solve(g: PatchGraph, order, L, D, r: np.ndarray) -> np.ndarray:
     """y = (L D L^T)^{-1} r with the factor of :func:`mdf_factor`."""
     n = g.n

@@ -60,7 +60,7 @@ def vertices(mesh):
 class Patch:
     """All levels of one vertex patch: graphs, MDF factors, transfers."""
 
-    def __init__(self, H: _lor.LORHierarchy, v, exact_local: bool = False):
+    def __init__(self, H: _lor.LORHierarchy, v, exact_local: bool = False, ordering: str = "mdf"):
         mesh = H.mesh
         dim = mesh.dim
         self.v = v
@@ -85,8 +85,14 @@ class Patch:
             lv["A"] = g.dense()
             if k == nl - 1 or exact_local:
                 lv["Ainv"] = np.linalg.inv(lv["A"])
-            else:
+            elif ordering == "mdf":
                 lv["order"], lv["L"], lv["D"] = _mdf.mdf_factor(g)
+            elif ordering == "rcm":
+                lv["order"], lv["L"], lv["D"] = _mdf.factor_in_order(g, _mdf.rcm_order(lv["shape"]))
+            elif ordering == "natural":
+                lv["order"], lv["L"], lv["D"] = _mdf.factor_in_order(g, np.arange(g.n))
+            else:
+                raise ValueError(f"unknown ordering {ordering!r}")
         for k in range(nl - 1):
             f, c = self.levels[k], self.levels[k + 1]
             if f["graph"] is None or c["graph"] is None:
@@ -175,14 +181,31 @@ class CoarseSpace:
 
 
 class SchwarzLOR:
-    """z = B r for the conforming problem on the Dirichlet unknowns."""
+    """z = B r for the conforming problem on the Dirichlet unknowns.
 
-    def __init__(self, mesh, p: int, exact_local: bool = False, coarse: bool = True):
+    weights="sum": eq. as, the patch corrections added unweighted.
+    weights="pou": each patch correction multiplied by Theta_j = diag(1/c(i)),
+    c(i) the number of patches whose level-0 unknowns include i (the
+    counting-matrix weighting Section 4.1 names as a refinement; a partition
+    of unity, sum_j P_j^T Theta_j P_j = I; B is then not symmetric and needs
+    flexible CG).  ordering: "mdf" (Section 3.4), "rcm" or "natural" for the
+    IC(0) smoother of every patch level."""
+
+    def __init__(self, mesh, p: int, exact_local: bool = False, coarse: bool = True,
+                 ordering: str = "mdf", weights: str = "sum"):
         self.H = _lor.LORHierarchy(mesh, p)
         self.Kh = self.H.matrix(0)
         self.fnum = _mesh.interior_numbering(self.H.shapes[0])
         self.coarse = CoarseSpace(self.H, self.Kh) if coarse else None
-        self.patches = [Patch(self.H, v, exact_local) for v in vertices(mesh)]
+        self.patches = [Patch(self.H, v, exact_local, ordering) for v in vertices(mesh)]
+        if weights not in ("sum", "pou"):
+            raise ValueError(f"unknown weights {weights!r}")
+        self.weights = weights
+        self.count = np.zeros(self.Kh.shape[0])
+        for P in self.patches:
+            lv = P.levels[0]
+            if lv["graph"] is not None:
+                self.count[self.fnum[lv["flat"]]] += 1.0
 
     def apply(self, r: np.ndarray, with_coarse: bool = True, with_patches: bool = True) -> np.ndarray:
         z = np.zeros_like(r)
@@ -194,7 +217,8 @@ class SchwarzLOR:
                 if lv["graph"] is None:
                     continue
                 u = self.fnum[lv["flat"]]
-                z[u] += P.solve(r[u])
+                c = P.solve(r[u])
+                z[u] += c / self.count[u] if self.weights == "pou" else c
         return z
 
     def as_matrix(self, **kw) -> np.ndarray:
