@@ -77,15 +77,32 @@ typedef struct {
 #define LOR_PREC_FP64   0   /* every step in float64 */
 #define LOR_PREC_MIXED  1   /* preconditioner applied in float32 */
 
-#define LOR_ORD_MDF     0   /* minimum discarded fill (Section 3.4) */
-#define LOR_ORD_NATURAL 1   /* patch-local lexicographic */
+/* Elimination order of the IC(0) smoother on every patch level (Section 3.4
+ * compares MDF with reverse Cuthill-McKee and approximate minimum degree and
+ * finds MDF and RCM comparable). */
+#define LOR_ORD_MDF     0   /* minimum discarded fill (Section 3.4)           */
+#define LOR_ORD_NATURAL 1   /* patch-local lexicographic                      */
+#define LOR_ORD_RCM     2   /* reverse Cuthill-McKee on the stencil graph of
+                               the patch box: start at a node of minimum
+                               degree (smallest index), neighbours in
+                               increasing degree (ties by index), reversed   */
+
+/* Weights of the patch corrections in the Schwarz sum. */
+#define LOR_PROLONG_SUM 0   /* eq. as: corrections added unweighted           */
+#define LOR_PROLONG_POU 1   /* each correction scaled by 1/c(i), c(i) the
+                               number of patches holding unknown i (the
+                               counting-matrix weighting of Section 4.1; a
+                               partition of unity, not symmetric: flexible CG
+                               is used)                                      */
 
 typedef struct {
-  int precision;     /* LOR_PREC_*                                          */
-  int ordering;      /* LOR_ORD_*                                           */
-  int flexible;      /* 0: PCG, 1: flexible CG FCG(1); forced on for MIXED  */
-  int nthreads;      /* host threads for the ordering pass; 0 = all cores   */
-  int reserved[8];   /* must be zero                                        */
+  int precision;       /* LOR_PREC_*                                        */
+  int ordering;        /* LOR_ORD_*                                         */
+  int flexible;        /* 0: PCG, 1: flexible CG FCG(1); forced on for MIXED
+                          and for LOR_PROLONG_POU                           */
+  int nthreads;        /* host threads for the ordering pass; 0 = all cores */
+  int prolong_weights; /* LOR_PROLONG_*                                     */
+  int reserved[7];     /* must be zero                                      */
 } lor_options_t;
 
 typedef struct {
@@ -248,6 +265,7 @@ int lor_nn_train_step(lor_nn_t *nn, const float *X_dev, const float *T_dev, int 
                       double *loss, void *stream);
 /* Use nn in h's preconditioner (LOR_NN_REPLACE or LOR_NN_WARMSTART) or not
  * (LOR_NN_OFF, nn may be NULL).  The network must have been created for h.
+ * LOR_NN_REPLACE needs LOR_PROLONG_SUM (LOR_ESTATE otherwise).
  * Either mode makes the preconditioner nonlinear: lor_pcg_solve then runs
  * flexible CG.  The first warm-start attach allocates the predictions of
  * every patch, J (2p-1)^3 floats and J doubles (LOR_ENOMEM on failure). */
@@ -309,16 +327,16 @@ int lor_timing_read(const lor_handle_t *h, int which, double *total_ms, int64_t 
  * rounded to float64.  HOST outputs of p+1 doubles. 1 <= p <= 14. */
 int lor_gll(int p, double *x, double *w);
 
-/* MDF ordering and IC(0) factor of one patch matrix (Section 3.4).
+/* Ordering and IC(0) factor of one patch matrix (Section 3.4).
  * dim: 2 or 3; m: box extents (dim entries, each >= 1); rows: HOST,
  * n x 3^dim float64 stencil rows of the box points (n = prod m, x fastest;
  * slot as in lor_export_stencils; couplings leaving the box are ignored).
- * natural: 1 = eliminate in index order instead of MDF.
+ * ordering: LOR_ORD_MDF, LOR_ORD_NATURAL (index order) or LOR_ORD_RCM.
  * HOST outputs (any may be NULL): order[n] elimination order;
  * level_ptr[n+1] dependency-level starts of the forward sweep, *depth levels;
  * L[n x 3^dim] (row i: l_im at earlier neighbours m, l_mi at later ones);
  * D[n] pivots.  Returns LOR_EPIVOT for a pivot <= 0. */
-int lor_mdf_order(int dim, const int *m, const double *rows, int natural, int32_t *order,
+int lor_mdf_order(int dim, const int *m, const double *rows, int ordering, int32_t *order,
                   int32_t *level_ptr, int32_t *depth, double *L, double *D);
 
 /* Release every resource of the handle (NULL is accepted). */

@@ -114,6 +114,18 @@ __device__ __forceinline__ int64_t walk_uidx(const Box<DIM> &bx, const Walk<DIM>
   return int64_t(bx.lo[0] + w.x - ox) + int64_t(md.nu[0]) * t;
 }
 
+// Partition-of-unity weight 1/c(i) of the walk's current row (a level-0
+// box): a level-0 grid coordinate g lies in the patches of the vertices
+// around it, one in a direction where g is on a vertex line (g a multiple of
+// p) and two elsewhere, so c = prod_d c_d.
+template <int DIM>
+__device__ __forceinline__ double pou_weight(const Box<DIM> &bx, const Walk<DIM> &w, int p) {
+  const int g[3] = {bx.lo[0] + w.x, bx.lo[1] + w.y, DIM == 3 ? bx.lo[2] + w.z : 0};
+  double c = 1.0;
+  for (int d = 0; d < DIM; ++d) c *= (g[d] % p == 0) ? 1.0 : 0.5;
+  return c;
+}
+
 // LDS layout of one patch (values of T):
 //   X_0 | B_0 (warm start only) | R_0 | B_1
 // and, inside R_0's space, X_1, R_1, then X_k, B_k, R_k for k >= 2: R_0 is
@@ -681,11 +693,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       if (WARM) {
         const double sc = dscale[blockIdx.x];
         const float *yj = wy + int64_t(blockIdx.x) * G3;
-        for (int i = threadIdx.x; i < b0.n; i += 64, w.step())
-          unsafeAtomicAdd(z + walk_uidx<DIM>(b0, w, md), double(X0[i]) + double(yj[grid_q(w)]) * sc);
+        for (int i = threadIdx.x; i < b0.n; i += 64, w.step()) {
+          const double c = double(X0[i]) + double(yj[grid_q(w)]) * sc;
+          unsafeAtomicAdd(z + walk_uidx<DIM>(b0, w, md), pa.pou ? c * pou_weight<DIM>(b0, w, md.p) : c);
+        }
       } else {
-        for (int i = threadIdx.x; i < b0.n; i += 64, w.step())
-          unsafeAtomicAdd(z + walk_uidx<DIM>(b0, w, md), double(X0[i]));
+        for (int i = threadIdx.x; i < b0.n; i += 64, w.step()) {
+          const double c = double(X0[i]);
+          unsafeAtomicAdd(z + walk_uidx<DIM>(b0, w, md), pa.pou ? c * pou_weight<DIM>(b0, w, md.p) : c);
+        }
       }
     }
   }

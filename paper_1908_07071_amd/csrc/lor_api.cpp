@@ -14,6 +14,9 @@
 
 #include "lor_handle.h"
 
+static_assert(LOR_ORD_MDF == ORD_MDF && LOR_ORD_NATURAL == ORD_NATURAL && LOR_ORD_RCM == ORD_RCM,
+              "ordering codes of the C ABI and of the set-up agree");
+
 namespace {
 
 thread_local char g_detail[512] = "";
@@ -243,7 +246,7 @@ int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hi
                           int64_t(lng0) * (int64_t(b.lo[1] + iy) + (dim == 3 ? int64_t(lng1) * (b.lo[2] + iz) : 0));
         for (int s = 0; s < NS; ++s) rows[size_t(i) * NS + s] = hst[k][size_t(s) * np + g];
       }
-      int rc = mdf_factor(dim, b.m, rows, h.opt.ordering == LOR_ORD_NATURAL, res);
+      int rc = mdf_factor(dim, b.m, rows, h.opt.ordering, res);
       if (rc != LOR_OK) {
         err.store(rc);
         break;
@@ -366,6 +369,7 @@ int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hi
   const int tot = 2 * level_n(0, full) + (L > 1 ? level_n(1, full) : 0);
   pa.lds_total = tot;
   pa.fp32 = mixed ? 1 : 0;
+  pa.pou = h.opt.prolong_weights == LOR_PROLONG_POU ? 1 : 0;
   if (size_t(tot) * (mixed ? sizeof(float) : sizeof(double)) > 160 * 1024)
     return invalid("patch vectors exceed the 160 KiB LDS of a CU (polynomial degree too high)", __LINE__);
   HIPCHK(prepare_patch_vcycle(pa));
@@ -583,6 +587,7 @@ int pcg_iterations(lor_handle *h, Work &w, double *x, int count, hipStream_t st)
   // flexible CG whenever the preconditioner is not a fixed SPD operator
   // (float32 patch solves, or the nonlinear patch network)
   const bool fcg = h->opt.flexible != 0 || h->opt.precision == LOR_PREC_MIXED ||
+                   h->opt.prolong_weights == LOR_PROLONG_POU ||
                    (h->nn && h->nn_mode != LOR_NN_OFF);
   // the operator writes q completely (DG, or CG through the skeleton gather);
   // otherwise q is accumulated atomically and must be cleared each iteration
@@ -741,7 +746,13 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const l
   if (opt) {
     h->opt = *opt;
     if (opt->precision != LOR_PREC_FP64 && opt->precision != LOR_PREC_MIXED) return LOR_EINVAL;
-    if (opt->ordering != LOR_ORD_MDF && opt->ordering != LOR_ORD_NATURAL) return LOR_EINVAL;
+    if (opt->ordering != LOR_ORD_MDF && opt->ordering != LOR_ORD_NATURAL &&
+        opt->ordering != LOR_ORD_RCM)
+      return LOR_EINVAL;
+    if (opt->prolong_weights != LOR_PROLONG_SUM && opt->prolong_weights != LOR_PROLONG_POU)
+      return LOR_EINVAL;
+    for (int t = 0; t < 7; ++t)
+      if (opt->reserved[t] != 0) return LOR_EINVAL;
   } else {
     lor_default_options(&h->opt);
   }
@@ -1099,9 +1110,11 @@ int lor_gll(int p, double *x, double *w) {
   return LOR_OK;
 }
 
-int lor_mdf_order(int dim, const int *m, const double *rows, int natural, int32_t *order,
+int lor_mdf_order(int dim, const int *m, const double *rows, int ordering, int32_t *order,
                   int32_t *level_ptr, int32_t *depth, double *L, double *D) {
   if ((dim != 2 && dim != 3) || !m || !rows) return LOR_EINVAL;
+  if (ordering != LOR_ORD_MDF && ordering != LOR_ORD_NATURAL && ordering != LOR_ORD_RCM)
+    return LOR_EINVAL;
   int64_t n = 1;
   int mm[3] = {1, 1, 1};
   for (int d = 0; d < dim; ++d) {
@@ -1113,7 +1126,7 @@ int lor_mdf_order(int dim, const int *m, const double *rows, int natural, int32_
   const int NS = nslots(dim);
   std::vector<double> a(rows, rows + n * NS);
   MdfResult res;
-  const int rc = mdf_factor(dim, mm, a, natural != 0, res);
+  const int rc = mdf_factor(dim, mm, a, ordering, res);
   if (rc != LOR_OK) return rc;
   if (order) std::copy(res.order.begin(), res.order.end(), order);
   if (level_ptr) std::copy(res.level_ptr.begin(), res.level_ptr.end(), level_ptr);

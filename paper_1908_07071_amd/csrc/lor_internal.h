@@ -54,6 +54,7 @@ struct PatchArgs {
                                      // backward sweep blocks (-1: none)
   int lds_total;                     // LDS values per patch (largest patch)
   int fp32;                          // 1: stencils, factors and patch vectors in float
+  int pou;                           // 1: corrections scaled by 1/c(i) (partition of unity)
 };
 
 // Sweep block: the data of one ILU(0) triangular sweep (forward or backward)
@@ -133,9 +134,14 @@ struct MdfResult {
   std::vector<double> D;        // pivots
   std::vector<int> earlier;     // per row bit mask of slots holding earlier neighbours
 };
-// rows: n x nslots values (row-major), box shape m[0..dim-1].
-// Returns LOR_OK or LOR_EPIVOT.
-int mdf_factor(int dim, const int *m, std::vector<double> &rows, bool natural, MdfResult &out);
+// Elimination orders of a patch level's IC(0) smoother.
+enum PatchOrdering { ORD_MDF = 0, ORD_NATURAL = 1, ORD_RCM = 2 };
+// rows: n x nslots values (row-major), box shape m[0..dim-1]; ordering: a
+// PatchOrdering.  Returns LOR_OK or LOR_EPIVOT.
+int mdf_factor(int dim, const int *m, std::vector<double> &rows, int ordering, MdfResult &out);
+// Reverse Cuthill-McKee order of a box of grid points with the stencil
+// adjacency (offsets differing by at most one per direction).
+std::vector<int> rcm_order(int dim, const int *m);
 // Sweep block of one direction (layout at kChunkLanes).
 template <typename T>
 std::vector<char> pack_sweep(const MdfResult &res, int dim, const int *m, bool fwd);

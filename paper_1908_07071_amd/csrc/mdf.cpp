@@ -12,6 +12,7 @@
 // patch-local index.  Every float64 operation below is written in a fixed
 // order (and the file is compiled without contraction) so that an
 // independent implementation following the same order agrees bit for bit.
+#include <algorithm>
 #include <cmath>
 #include <queue>
 #include <vector>
@@ -73,7 +74,55 @@ struct HeapCmp {  // min-heap on (d, idx)
 
 }  // namespace
 
-int mdf_factor(int dim, const int *m, std::vector<double> &a, bool natural, MdfResult &out) {
+// Reverse Cuthill-McKee (Cuthill and McKee 1969, reversed), one of the
+// orderings Section 3.4 compares: on the stencil graph of the box (the values
+// play no part), start from a node of minimum degree (smallest index among
+// them), number the not yet numbered neighbours of each numbered node in
+// increasing degree (ties to the smallest index), breadth first, and reverse.
+std::vector<int> rcm_order(int dim, const int *m) {
+  const Stencil st(dim);
+  const int mx = m[0], my = m[1], mz = dim == 3 ? m[2] : 1;
+  const int n = mx * my * mz;
+  std::vector<int> deg(n, 0);
+  auto for_nbrs = [&](int i, auto &&fn) {
+    const int c[3] = {i % mx, (i / mx) % my, i / (mx * my)};
+    for (int s = 0; s < st.ns; ++s) {
+      if (s == st.center) continue;
+      const int q[3] = {c[0] + st.off[s][0], c[1] + st.off[s][1], c[2] + st.off[s][2]};
+      if (q[0] >= 0 && q[0] < mx && q[1] >= 0 && q[1] < my && q[2] >= 0 && q[2] < mz)
+        fn(q[0] + mx * (q[1] + my * q[2]));
+    }
+  };
+  for (int i = 0; i < n; ++i) for_nbrs(i, [&](int) { ++deg[i]; });
+  std::vector<char> numbered(n, 0);
+  std::vector<int> cm;
+  cm.reserve(n);
+  auto by_degree = [&](int a, int b) { return deg[a] != deg[b] ? deg[a] < deg[b] : a < b; };
+  while (int(cm.size()) < n) {
+    int start = -1;
+    for (int i = 0; i < n; ++i)
+      if (!numbered[i] && (start < 0 || by_degree(i, start))) start = i;
+    numbered[start] = 1;
+    size_t head = cm.size();
+    cm.push_back(start);
+    while (head < cm.size()) {
+      const int u = cm[head++];
+      int nxt[26], k = 0;
+      for_nbrs(u, [&](int v) {
+        if (!numbered[v]) nxt[k++] = v;
+      });
+      std::sort(nxt, nxt + k, by_degree);
+      for (int t = 0; t < k; ++t) {
+        numbered[nxt[t]] = 1;
+        cm.push_back(nxt[t]);
+      }
+    }
+  }
+  std::reverse(cm.begin(), cm.end());
+  return cm;
+}
+
+int mdf_factor(int dim, const int *m, std::vector<double> &a, int ordering, MdfResult &out) {
   const Stencil st(dim);
   const int ns = st.ns, C = st.center;
   const int mx = m[0], my = m[1], mz = dim == 3 ? m[2] : 1;
@@ -143,8 +192,11 @@ int mdf_factor(int dim, const int *m, std::vector<double> &a, bool natural, MdfR
   };
 
   int nbr[27];
-  if (natural) {
-    for (int i = 0; i < n; ++i) {
+  if (ordering == ORD_NATURAL || ordering == ORD_RCM) {
+    std::vector<int> fixed;
+    if (ordering == ORD_RCM) fixed = rcm_order(dim, m);
+    for (int t = 0; t < n; ++t) {
+      const int i = ordering == ORD_RCM ? fixed[t] : t;
       if (eliminate(i, nbr) < 0) return LOR_EPIVOT;
       out.order.push_back(i);
     }

@@ -22,7 +22,8 @@ LOR_EACCURACY = -9
 LOR_CG, LOR_IP, LOR_BR2 = 0, 1, 2
 LOR_BC_DIRICHLET, LOR_BC_NEUMANN = 0, 1
 LOR_PREC_FP64, LOR_PREC_MIXED = 0, 1
-LOR_ORD_MDF, LOR_ORD_NATURAL = 0, 1
+LOR_ORD_MDF, LOR_ORD_NATURAL, LOR_ORD_RCM = 0, 1, 2
+LOR_PROLONG_SUM, LOR_PROLONG_POU = 0, 1
 LOR_MAP_LDOF, LOR_MAP_ORDER, LOR_MAP_ORDER_OFFSET = 0, 1, 2
 LOR_MAP_SCHEDULE, LOR_MAP_SCHEDULE_OFFSET, LOR_MAP_E2L = 3, 4, 5
 
@@ -54,7 +55,7 @@ class lor_mesh_t(C.Structure):
 
 class lor_options_t(C.Structure):
     _fields_ = [("precision", C.c_int), ("ordering", C.c_int), ("flexible", C.c_int),
-                ("nthreads", C.c_int), ("reserved", C.c_int * 8)]
+                ("nthreads", C.c_int), ("prolong_weights", C.c_int), ("reserved", C.c_int * 7)]
 
 
 class lor_solve_info_t(C.Structure):
@@ -165,8 +166,11 @@ def lor_gll(p: int):
     return x, w
 
 
-def lor_mdf_order(dim: int, shape, rows: np.ndarray, natural: bool = False):
-    """(order, level_ptr, L, D) of one patch matrix given as (n, 3^dim) stencil rows."""
+def lor_mdf_order(dim: int, shape, rows: np.ndarray, natural: bool = False, ordering=None):
+    """(order, level_ptr, L, D) of one patch matrix given as (n, 3^dim) stencil rows;
+    ordering: LOR_ORD_* (default MDF, or natural order when natural is set)."""
+    if ordering is None:
+        ordering = LOR_ORD_NATURAL if natural else LOR_ORD_MDF
     m = np.ascontiguousarray(shape, dtype=np.int32)
     n = int(np.prod(m))
     ns = 3 ** dim
@@ -176,7 +180,7 @@ def lor_mdf_order(dim: int, shape, rows: np.ndarray, natural: bool = False):
     depth = np.zeros(1, np.int32)
     L = np.zeros((n, ns))
     D = np.zeros(n)
-    rc = _lib.lor_mdf_order(int(dim), _iptr(m), _dptr(rows), int(bool(natural)), _iptr(order),
+    rc = _lib.lor_mdf_order(int(dim), _iptr(m), _dptr(rows), int(ordering), _iptr(order),
                             _iptr(lvl), _iptr(depth), _dptr(L), _dptr(D))
     _check(rc, "lor_mdf_order")
     return order, lvl[:int(depth[0]) + 1].copy(), L, D

@@ -70,6 +70,24 @@ def test_mdf_bitexact(dim, n, p, pert):
             assert len(lvl) - 1 == mdf.dependency_depth(g, o1)
             on, _, _, _ = L.lor_mdf_order(dim, shape, rows, natural=True)
             assert np.array_equal(on, np.arange(g.n))
+            # reverse Cuthill-McKee and its factor, bit for bit
+            o3, L3, D3 = mdf.factor_in_order(g, mdf.rcm_order(shape))
+            o4, lvl4, L4, D4 = L.lor_mdf_order(dim, shape, rows, ordering=L.LOR_ORD_RCM)
+            assert np.array_equal(o3, o4)
+            assert np.array_equal(L3, L4) and np.array_equal(D3, D4)
+            assert len(lvl4) - 1 == mdf.dependency_depth(g, o3)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (7, 1), (4, 9), (11, 11, 11), (5, 1, 7), (15, 15, 7)])
+def test_rcm_order_bitexact(shape):
+    """The library's RCM permutation of a patch box equals the oracle's."""
+    from paper_1908_07071_amd import lor as L
+    dim = len(shape)
+    n = int(np.prod(shape))
+    rows = np.zeros((n, 3 ** dim))
+    rows[:, (3 ** dim) // 2] = 1.0  # identity: any order factors it
+    o, _, _, _ = L.lor_mdf_order(dim, shape, rows, ordering=L.LOR_ORD_RCM)
+    assert np.array_equal(o, mdf.rcm_order(shape))
 
 
 def test_mdf_pivot_error():
