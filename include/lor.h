@@ -175,6 +175,23 @@ int lor_apply_A(lor_handle_t *h, const double *x_dev, double *y_dev, void *strea
  * Neumann handle (no preconditioner). */
 int lor_apply_P(lor_handle_t *h, const double *r_dev, double *z_dev, void *stream);
 
+/* z = B r exactly as lor_apply_P computes it, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the call allocates, frees and memsets
+ * nothing and records no events.  Its scratch vectors (the coarse-space
+ * residual and correction, n_c values each, and for DG the conforming
+ * residual and correction, one conforming L-vector each) live in a static
+ * device array of 8 MiB per GPU, held until the process ends; a handle that
+ * needs more returns LOR_ENOMEM (reason in lor_last_error_detail).  Every
+ * call on one GPU shares that array: calls that overlap on one GPU (other
+ * streams or threads) race.  The handle's device must be current.
+ * r_dev, z_dev: DEVICE, ndofs float64, must not alias.  LOR_ESTATE for a
+ * handle without preconditioner or with a patch network attached. */
+int lor_apply_P_noalloc(lor_handle_t *h, const double *r_dev, double *z_dev, void *stream);
+
+/* Scratch bytes lor_apply_P_noalloc needs for h, and the static capacity. */
+int lor_noalloc_scratch_bytes(const lor_handle_t *h, size_t *needed, size_t *capacity);
+
 /* Solve A x = b by preconditioned (or flexible) CG (Section 4) from x = 0
  * until ||r_k||_2 <= rtol ||b||_2 (recursive residual) or maxit iterations.
  * When the recursive residual meets rtol, the true residual b - A x is

@@ -33,6 +33,7 @@ SOURCES = [
     ("k_nn.hip", []),
     ("k_nnconv.hip", []),
     ("nn_api.cpp", []),
+    ("noalloc.hip", []),
 ]
 
 ARCH = "gfx950"

@@ -543,6 +543,48 @@ int apply_P_impl(lor_handle *h, Work &w, const double *r, double *z, const doubl
   return LOR_OK;
 }
 
+}  // namespace
+
+size_t apply_P_scratch_doubles(const lor_handle *h) {
+  auto up = [](int64_t n) { return size_t((std::max<int64_t>(n, 0) + 31) / 32 * 32); };
+  size_t need = 2 * up(h->nc);
+  if (h->method != LOR_CG) need += 2 * up(h->ncg);
+  return need;
+}
+
+int apply_P_scratch(lor_handle *h, double *scratch, size_t cap, const double *r, double *z,
+                    hipStream_t st) {
+  const size_t need = apply_P_scratch_doubles(h);
+  if (need > cap) {
+    std::snprintf(g_detail, sizeof(g_detail),
+                  "lor_apply_P_noalloc: this handle needs %zu bytes of scratch, the static "
+                  "buffer holds %zu",
+                  need * sizeof(double), cap * sizeof(double));
+    return LOR_ENOMEM;
+  }
+  auto up = [](int64_t n) { return size_t((std::max<int64_t>(n, 0) + 31) / 32 * 32); };
+  Work w = h->w;  // operator buffers are not touched by B
+  double *c = scratch;
+  w.rc = c;
+  c += up(h->nc);
+  w.xc = c;
+  c += up(h->nc);
+  if (h->method != LOR_CG) {
+    w.rL = c;
+    c += up(h->ncg);
+    w.zL = c;
+  } else {
+    w.rL = w.zL = nullptr;
+  }
+  const bool was = h->capturing;
+  h->capturing = true;  // no timing events: nothing is created or recorded
+  const int rc = apply_P_impl(h, w, r, z, nullptr, st);
+  h->capturing = was;
+  return rc;
+}
+
+namespace {
+
 int apply_A_impl(lor_handle *h, Work &w, const double *x, double *y, double *partials,
                  const double *flag, hipStream_t st) {
   Span sp(h, LOR_T_APPLY_A, st);
@@ -762,6 +804,8 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const l
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIPCHK(hipGetDevice(&h->device));
   int rc = setup_impl(*h, st);
+  if (rc != LOR_OK) return rc;
+  rc = noalloc_register_device(h->device);
   if (rc != LOR_OK) return rc;
   rc = work_alloc(*h, h->w, h->allocs, h->bytes);
   if (rc != LOR_OK) return rc;

@@ -99,6 +99,17 @@ struct lor_handle {
 };
 
 
+// z = B r with the coarse-space vectors (and, for DG, the conforming vectors
+// of E B E^T) taken from `scratch` (device memory of `cap` doubles, 256-byte
+// aligned) instead of the handle's workspace; no allocation, no memset and no
+// event recording (lor_api.cpp).  LOR_ENOMEM if `cap` is too small.
+size_t apply_P_scratch_doubles(const lor_handle *h);
+int apply_P_scratch(lor_handle *h, double *scratch, size_t cap, const double *r, double *z,
+                    hipStream_t st);
+// Looks up, once per device, the device address of the static scratch array
+// of the no-allocation entry point on the current device (noalloc.hip).
+int noalloc_register_device(int device);
+
 // Patches of the Schwarz preconditioner through the attached network:
 // z += sum_j R_j^T s_j net(R_j r / s_j) (nn_api.cpp).
 int nn_apply_patches(lor_nn *nn, const double *r, double *z, const double *flag, hipStream_t st);

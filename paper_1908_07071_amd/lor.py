@@ -34,7 +34,7 @@ EXPORTED = [
     "lor_last_error_detail", "lor_timing", "lor_timing_read", "lor_pcg_solve_batch",
     "lor_nn_param_count", "lor_nn_create", "lor_nn_get_params", "lor_nn_shape", "lor_nn_patch_data",
     "lor_nn_forward", "lor_nn_gradients", "lor_nn_train_step", "lor_nn_attach", "lor_nn_free",
-    "lor_bf16_gemm",
+    "lor_bf16_gemm", "lor_apply_P_noalloc", "lor_noalloc_scratch_bytes",
 ]
 LOR_NN_OFF, LOR_NN_REPLACE, LOR_NN_WARMSTART = 0, 1, 2
 LOR_T_APPLY_A, LOR_T_PATCH, LOR_T_COARSE = 0, 1, 2
@@ -84,6 +84,8 @@ def _load():
         "lor_assemble_rhs": (C.c_int, [vp, vp, vp, vp]),
         "lor_apply_A": (C.c_int, [vp, vp, vp, vp]),
         "lor_apply_P": (C.c_int, [vp, vp, vp, vp]),
+        "lor_apply_P_noalloc": (C.c_int, [vp, vp, vp, vp]),
+        "lor_noalloc_scratch_bytes": (C.c_int, [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         "lor_pcg_solve": (C.c_int, [vp, vp, vp, C.c_double, C.c_int, C.POINTER(lor_solve_info_t), vp]),
         "lor_export_maps": (C.c_int, [vp, C.c_int, i32p, i64p]),
         "lor_export_stencils": (C.c_int, [vp, C.c_int, dp, i64p]),
@@ -240,6 +242,17 @@ def lor_apply_A(h, x, y, stream=None):
 
 def lor_apply_P(h, r, z, stream=None):
     _check(_lib.lor_apply_P(h, _dev(r, "r"), _dev(z, "z"), _stream(stream)), "lor_apply_P")
+
+
+def lor_apply_P_noalloc(h, r, z, stream=None):
+    _check(_lib.lor_apply_P_noalloc(h, _dev(r, "r"), _dev(z, "z"), _stream(stream)),
+           "lor_apply_P_noalloc")
+
+
+def lor_noalloc_scratch_bytes(h):
+    need, cap = C.c_size_t(), C.c_size_t()
+    _check(_lib.lor_noalloc_scratch_bytes(h, C.byref(need), C.byref(cap)), "lor_noalloc_scratch_bytes")
+    return need.value, cap.value
 
 
 def lor_pcg_solve(h, b, x, rtol: float = 1e-8, maxit: int = 1000, stream=None, check: bool = True):
