@@ -151,8 +151,25 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty,
 /* Number of unknowns: the L-vector length for CG, n_el (p+1)^d for DG. */
 int lor_ndofs(const lor_handle_t *h, int64_t *n);
 
-/* Bytes of device memory the handle holds. */
+/* Bytes of device memory the library holds for the handle (after
+ * lor_bind_workspace only the cached workspaces of batched solves). */
 int lor_device_bytes(const lor_handle_t *h, size_t *bytes);
+
+/* Caller-owned device memory (section 8 of the boundary: the caller's
+ * allocator, e.g. torch's, owns the device memory).  lor_setup builds the
+ * handle's device data (geometric factors, LOR stencils, patch factors,
+ * coarse inverse, solve workspace) in library allocations;
+ * lor_workspace_bytes gives their total size (each rounded up to 256 bytes),
+ * and lor_bind_workspace moves all of it into the caller's DEVICE buffer
+ * dev_ptr (256-byte aligned, at least that many bytes) on `stream`, then
+ * frees the library's copies.  Afterwards the buffer must outlive the
+ * handle, must not be touched by the caller, and lor_free leaves it alone.
+ * Results are unchanged.  Errors: LOR_EINVAL (NULL or misaligned pointer),
+ * LOR_ENOMEM (buffer too small; needed size in lor_last_error_detail),
+ * LOR_ESTATE (already bound).  Once bound, lor_workspace_bytes returns the
+ * bound size. */
+int lor_workspace_bytes(const lor_handle_t *h, size_t *bytes);
+int lor_bind_workspace(lor_handle_t *h, void *dev_ptr, size_t bytes, void *stream);
 
 /* Coordinates of the unknowns, HOST output of ndofs x dim float64.  CG: the
  * GLL grid node evaluated with the map of element min(g_i / p, n_i - 1) in
@@ -221,9 +238,13 @@ int lor_pcg_solve(lor_handle_t *h, const double *b_dev, double *x_dev,
  * b, x: HOST arrays of nprob*nrhs DEVICE pointers (ndofs of the pair's
  * handle each); stream: the caller's stream, ordered before and after the
  * batch.  info: HOST array of nprob*nrhs entries (may be NULL); t_solve is
- * the time of the whole batch.  Returns LOR_OK or the first failing pair's
- * status (LOR_ENOCONV, LOR_EBREAKDOWN, LOR_EINVAL); LOR_ESTATE for a handle
- * without preconditioner.  Allocates (and frees) the workspaces. */
+ * the time of the whole batch from the moment workspaces and graphs are
+ * ready.  Returns LOR_OK or the first failing pair's status (LOR_ENOCONV,
+ * LOR_EACCURACY, LOR_EBREAKDOWN, LOR_EINVAL); LOR_ESTATE for a handle
+ * without preconditioner.  Residual replacement as in lor_pcg_solve.  The
+ * pairs' workspaces are allocated the first time a handle serves that many
+ * pairs in one call and kept on the handle for later batches (counted by
+ * lor_device_bytes, released by lor_free); graphs are captured per call. */
 int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const double *const *b_dev,
                         double *const *x_dev, double rtol, int maxit, lor_solve_info_t *info,
                         void *stream);

@@ -459,13 +459,15 @@ int setup_impl(lor_handle &h, hipStream_t st) {
 // Allocates the device workspace of one solve for handle h.  Buffers are
 // appended to `owned` (hipMalloc'ed, freed by the owner) and counted in
 // `bytes`; the pinned scalar copy is returned in w.h_scal.
-int work_alloc(const lor_handle &h, Work &w, std::vector<void *> &owned, size_t &bytes) {
+int work_alloc(const lor_handle &h, Work &w, std::vector<void *> &owned, size_t &bytes,
+               std::vector<size_t> *sizes = nullptr) {
   auto get = [&](double **ptr, size_t count) -> hipError_t {
     void *p = nullptr;
     const size_t b = std::max<size_t>(count * sizeof(double), 16);
     hipError_t e = hipMalloc(&p, b);
     if (e != hipSuccess) return e;
     owned.push_back(p);
+    if (sizes) sizes->push_back(b);
     bytes += b;
     *ptr = static_cast<double *>(p);
     return hipSuccess;
@@ -807,7 +809,7 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const l
   if (rc != LOR_OK) return rc;
   rc = noalloc_register_device(h->device);
   if (rc != LOR_OK) return rc;
-  rc = work_alloc(*h, h->w, h->allocs, h->bytes);
+  rc = work_alloc(*h, h->w, h->allocs, h->bytes, &h->alloc_size);
   if (rc != LOR_OK) return rc;
   h->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = h.release();
@@ -822,7 +824,89 @@ int lor_ndofs(const lor_handle_t *h, int64_t *n) {
 
 int lor_device_bytes(const lor_handle_t *h, size_t *bytes) {
   if (!h || !bytes) return LOR_EINVAL;
-  *bytes = h->bytes;
+  *bytes = h->bytes + h->bbytes;
+  return LOR_OK;
+}
+
+namespace {
+constexpr size_t kWsAlign = 256;
+size_t ws_round(size_t b) { return (b + kWsAlign - 1) / kWsAlign * kWsAlign; }
+}  // namespace
+
+int lor_workspace_bytes(const lor_handle_t *h, size_t *bytes) {
+  if (!h || !bytes) return LOR_EINVAL;
+  if (h->bound) {
+    *bytes = h->bound_bytes;
+    return LOR_OK;
+  }
+  size_t t = 0;
+  for (size_t b : h->alloc_size) t += ws_round(b);
+  *bytes = t;
+  return LOR_OK;
+}
+
+int lor_bind_workspace(lor_handle_t *h, void *dev_ptr, size_t bytes, void *stream) {
+  if (!h || !dev_ptr) return LOR_EINVAL;
+  if (h->bound) return LOR_ESTATE;
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % kWsAlign) return LOR_EINVAL;
+  if (h->allocs.size() != h->alloc_size.size()) return LOR_ESTATE;
+  size_t need = 0;
+  lor_workspace_bytes(h, &need);
+  if (bytes < need) {
+    std::snprintf(g_detail, sizeof(g_detail), "lor_bind_workspace: %zu bytes given, %zu needed",
+                  bytes, need);
+    return LOR_ENOMEM;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char *base = static_cast<char *>(dev_ptr);
+  const size_t na = h->allocs.size();
+  std::vector<size_t> off(na);
+  size_t o = 0;
+  for (size_t a = 0; a < na; ++a) {
+    off[a] = o;
+    o += ws_round(h->alloc_size[a]);
+  }
+  // new address of a pointer into one of the handle's allocations; every
+  // device pointer the handle keeps must resolve, or nothing is changed
+  bool ok = true;
+  auto reloc = [&](auto *p) -> decltype(p) {
+    if (!p) return p;
+    const char *c = reinterpret_cast<const char *>(p);
+    for (size_t a = 0; a < na; ++a) {
+      const char *b0 = static_cast<const char *>(h->allocs[a]);
+      if (c >= b0 && c < b0 + h->alloc_size[a])
+        return reinterpret_cast<decltype(p)>(base + off[a] + (c - b0));
+    }
+    ok = false;
+    return p;
+  };
+  auto apply = [&](bool commit) {
+    auto set = [&](auto *&field) {
+      auto v = reloc(field);
+      if (commit) field = v;
+    };
+    set(h->d_verts), set(h->d_gllx), set(h->d_gllw), set(h->d_D), set(h->d_coords);
+    set(h->d_G), set(h->d_wdet), set(h->d_fac), set(h->d_fac_off), set(h->d_xfer);
+    set(h->d_A0inv), set(h->d_fg), set(h->d_dinv);
+    for (int k = 0; k < kMaxLevels; ++k) set(h->d_stencil[k]);
+    Work &w = h->w;
+    set(w.r), set(w.z), set(w.p), set(w.q), set(w.rold), set(w.tmp), set(w.scal), set(w.part);
+    set(w.part2), set(w.rc), set(w.xc), set(w.yE), set(w.fo), set(w.rL), set(w.zL);
+    for (int k = 0; k < kMaxLevels; ++k) set(h->pa.stencil[k]);
+    set(h->pa.xfer), set(h->pa.fac), set(h->pa.fac_off);
+  };
+  apply(false);  // dry run: resolve every pointer before anything changes
+  if (!ok) return LOR_ESTATE;
+  for (size_t a = 0; a < na; ++a)
+    HIPCHK(hipMemcpyAsync(base + off[a], h->allocs[a], h->alloc_size[a], hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  apply(true);
+  for (void *p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+  h->alloc_size.clear();
+  h->bytes = 0;
+  h->bound = true;
+  h->bound_bytes = need;
   return LOR_OK;
 }
 
@@ -933,19 +1017,17 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
     double last_true = HUGE_VAL;
   };
   std::vector<Pair> pairs(npair);
-  std::vector<void *> owned;
   std::vector<hipStream_t> streams;
-  hipEvent_t start = nullptr, stop = nullptr;
-  size_t bytes = 0;
+  hipEvent_t ready = nullptr, start = nullptr, stop = nullptr;
   int rc = LOR_OK;
-  // everything allocated here is released on every exit path
+  // graphs, streams and events are released on every exit path; the pairs'
+  // workspaces are cached on their handles (allocated the first time a
+  // handle needs that many, freed by lor_free)
   auto cleanup = [&]() {
-    for (Pair &q : pairs) {
+    for (Pair &q : pairs)
       if (q.chunk) (void)hipGraphExecDestroy(q.chunk);
-      if (q.w.h_scal) (void)hipHostFree(q.w.h_scal);
-    }
     for (hipStream_t t : streams) (void)hipStreamDestroy(t);
-    for (void *p : owned) (void)hipFree(p);
+    if (ready) (void)hipEventDestroy(ready);
     if (start) (void)hipEventDestroy(start);
     if (stop) (void)hipEventDestroy(stop);
     for (int i = 0; i < nprob; ++i) hs[i]->capturing = false;
@@ -965,17 +1047,36 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
     BCHK(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));  // default priority
     streams.push_back(t);
   }
+  BCHK(hipEventCreate(&ready));
   BCHK(hipEventCreate(&start));
   BCHK(hipEventCreate(&stop));
   // the caller's stream orders the inputs: every worker stream waits for it
-  BCHK(hipEventRecord(start, caller));
-  for (hipStream_t t : streams) BCHK(hipStreamWaitEvent(t, start, 0));
-  for (int k = 0; k < npair; ++k) {
-    Pair &q = pairs[k];
-    q.h = hs[k / nrhs];
-    q.st = streams[k % ns];
-    rc = work_alloc(*q.h, q.w, owned, bytes);
-    if (rc != LOR_OK) return fail(rc);
+  BCHK(hipEventRecord(ready, caller));
+  for (hipStream_t t : streams) BCHK(hipStreamWaitEvent(t, ready, 0));
+  {
+    // a handle may serve several problems: its pairs take consecutive
+    // cached workspaces
+    std::vector<std::pair<lor_handle *, int>> used;
+    for (int k = 0; k < npair; ++k) {
+      Pair &q = pairs[k];
+      q.h = hs[k / nrhs];
+      q.st = streams[k % ns];
+      int slot = 0;
+      bool found = false;
+      for (auto &u : used)
+        if (u.first == q.h) {
+          slot = u.second++;
+          found = true;
+        }
+      if (!found) used.push_back({q.h, 1});
+      while (int(q.h->bwork.size()) <= slot) {
+        Work nw;
+        rc = work_alloc(*q.h, nw, q.h->ballocs, q.h->bbytes);
+        if (nw.h_scal) q.h->bwork.push_back(nw);
+        if (rc != LOR_OK) return fail(rc);
+      }
+      q.w = q.h->bwork[slot];
+    }
   }
   // one captured chunk of iterations per pair (kernels become no-ops once the
   // pair has converged, so the chunk is replayed until its flag is set)
@@ -996,6 +1097,10 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
     (void)hipGraphDestroy(g);
     BCHK(e);
   }
+  // the timed span starts here: workspaces, streams and graphs are ready
+  BCHK(hipEventRecord(start, streams[0]));
+  for (hipStream_t t : streams)
+    if (t != streams[0]) BCHK(hipStreamWaitEvent(t, start, 0));
   for (int k = 0; k < npair; ++k) {
     Pair &q = pairs[k];
     rc = pcg_init(q.h, q.w, b[k], x[k], rtol, maxit, q.st);

@@ -43,7 +43,17 @@ struct lor_handle {
   int J = 0, nc = 0;
   // device memory (owned)
   std::vector<void *> allocs;
+  std::vector<size_t> alloc_size;  // bytes of each entry of allocs
   size_t bytes = 0;
+  // caller-owned device workspace (lor_bind_workspace): every allocation
+  // above moved into it; allocs is then empty
+  bool bound = false;
+  size_t bound_bytes = 0;
+  // cached workspaces of batched solves (one per concurrent pair of this
+  // handle), owned by the library and kept until lor_free
+  std::vector<Work> bwork;
+  std::vector<void *> ballocs;
+  size_t bbytes = 0;
   double *d_verts = nullptr, *d_gllx = nullptr, *d_gllw = nullptr, *d_D = nullptr;
   double *d_coords = nullptr, *d_G = nullptr, *d_wdet = nullptr;
   double *d_stencil[kMaxLevels] = {};
@@ -85,12 +95,16 @@ struct lor_handle {
     hipError_t e = hipMalloc(&p, b);
     if (e != hipSuccess) return e;
     allocs.push_back(p);
+    alloc_size.push_back(b);
     bytes += b;
     *ptr = static_cast<T *>(p);
     return hipSuccess;
   }
   ~lor_handle() {
     for (void *p : allocs) (void)hipFree(p);
+    for (void *p : ballocs) (void)hipFree(p);
+    for (Work &bw : bwork)
+      if (bw.h_scal) (void)hipHostFree(bw.h_scal);
     if (w.h_scal) (void)hipHostFree(w.h_scal);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);

@@ -34,7 +34,8 @@ EXPORTED = [
     "lor_last_error_detail", "lor_timing", "lor_timing_read", "lor_pcg_solve_batch",
     "lor_nn_param_count", "lor_nn_create", "lor_nn_get_params", "lor_nn_shape", "lor_nn_patch_data",
     "lor_nn_forward", "lor_nn_gradients", "lor_nn_train_step", "lor_nn_attach", "lor_nn_free",
-    "lor_bf16_gemm", "lor_apply_P_noalloc", "lor_noalloc_scratch_bytes",
+    "lor_bf16_gemm", "lor_apply_P_noalloc", "lor_noalloc_scratch_bytes", "lor_workspace_bytes",
+    "lor_bind_workspace",
 ]
 LOR_NN_OFF, LOR_NN_REPLACE, LOR_NN_WARMSTART = 0, 1, 2
 LOR_T_APPLY_A, LOR_T_PATCH, LOR_T_COARSE = 0, 1, 2
@@ -80,6 +81,8 @@ def _load():
                                 C.POINTER(lor_options_t), vp, C.POINTER(vp)]),
         "lor_ndofs": (C.c_int, [vp, i64p]),
         "lor_device_bytes": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
+        "lor_workspace_bytes": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
+        "lor_bind_workspace": (C.c_int, [vp, vp, C.c_size_t, vp]),
         "lor_dof_coords": (C.c_int, [vp, dp]),
         "lor_assemble_rhs": (C.c_int, [vp, vp, vp, vp]),
         "lor_apply_A": (C.c_int, [vp, vp, vp, vp]),
@@ -224,6 +227,24 @@ def lor_device_bytes(h) -> int:
     n = C.c_size_t()
     _check(_lib.lor_device_bytes(h, C.byref(n)), "lor_device_bytes")
     return n.value
+
+
+def lor_workspace_bytes(h) -> int:
+    n = C.c_size_t()
+    _check(_lib.lor_workspace_bytes(h, C.byref(n)), "lor_workspace_bytes")
+    return n.value
+
+
+def lor_bind_workspace(h, ws, stream=None):
+    """Moves the handle's device data into ``ws``, a contiguous device tensor
+    (any dtype) of at least lor_workspace_bytes(h) bytes, 256-byte aligned,
+    which must then outlive the handle and not be written by the caller."""
+    import torch
+    if not (isinstance(ws, torch.Tensor) and ws.is_cuda and ws.is_contiguous()):
+        raise TypeError("ws must be a contiguous device tensor")
+    nbytes = ws.numel() * ws.element_size()
+    _check(_lib.lor_bind_workspace(h, C.c_void_p(ws.data_ptr()), C.c_size_t(nbytes), _stream(stream)),
+           "lor_bind_workspace")
 
 
 def lor_dof_coords(h, dim: int) -> np.ndarray:

@@ -51,7 +51,7 @@ def _setup(L, prob):
     return L.lor_setup(dim, list(n), V, p, method=code, penalty=eta, options=opt)
 
 
-def test_batch_bitexact_vs_single_solves(L, torch_dev):
+def test_batch_matches_single_solves(L, torch_dev):
     torch = torch_dev
     nrhs = 3
     hs = [_setup(L, pr) for pr in PROBLEMS]
