@@ -92,13 +92,18 @@ def element_global_nodes(mesh, p: int, e) -> np.ndarray:
     return _mesh.lex_index(idx, shape)
 
 
-def cg_stiffness(mesh, p: int, dirichlet: bool = True) -> sp.csr_matrix:
-    """Assembled K_p over the unknowns (all grid nodes if not dirichlet)."""
+def cg_stiffness(mesh, p: int, dirichlet: bool = True, coef=None) -> sp.csr_matrix:
+    """Assembled K_p over the unknowns (all grid nodes if not dirichlet).
+
+    coef: the coefficient b of -div(b grad u) = f (Section 4.2) at every
+    element's GLL nodes, (n_el, (p+1)^d) with elements and local nodes
+    lexicographic (x fastest); None for b = 1.  With collocated quadrature b
+    enters as a factor of each node's weight."""
     shape = _mesh.grid_shape(mesh, p)
     num = _mesh.interior_numbering(shape) if dirichlet else np.arange(int(np.prod(shape)))
     rows, cols, vals = [], [], []
     for e in mesh.elements():
-        A = element_stiffness(mesh, p, e)
+        A = element_stiffness(mesh, p, e, None if coef is None else coef[_elem_flat(mesh, e)])
         g = num[element_global_nodes(mesh, p, e)]
         keep = g >= 0
         gi, gj = np.meshgrid(g[keep], g[keep], indexing="ij")
@@ -127,7 +132,7 @@ def cg_rhs(mesh, p: int, f_nodes: np.ndarray, dirichlet: bool = True) -> np.ndar
     return b
 
 
-def cg_apply_rows(mesh, p: int, x: np.ndarray, rows: np.ndarray) -> np.ndarray:
+def cg_apply_rows(mesh, p: int, x: np.ndarray, rows: np.ndarray, coef=None) -> np.ndarray:
     """(K_p x)[rows] for selected unknowns, assembling only the elements touching them."""
     dim = mesh.dim
     shape = _mesh.grid_shape(mesh, p)
@@ -146,7 +151,7 @@ def cg_apply_rows(mesh, p: int, x: np.ndarray, rows: np.ndarray) -> np.ndarray:
                 elems.add(tuple(e))
         acc = 0.0
         for e in sorted(elems):
-            A = element_stiffness(mesh, p, e)
+            A = element_stiffness(mesh, p, e, None if coef is None else coef[_elem_flat(mesh, e)])
             gl = element_global_nodes(mesh, p, e)
             li = int(np.flatnonzero(gl == inv[r])[0])
             u = num[gl]

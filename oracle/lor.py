@@ -178,16 +178,41 @@ def stencil_slots(dim: int):
     return [tuple(((sl // 3 ** i) % 3) - 1 for i in range(dim)) for sl in range(3 ** dim)]
 
 
-def level_stencils(coords: np.ndarray, shape) -> np.ndarray:
+def level_cell_coef(mesh, p: int, k: int, coef: np.ndarray) -> np.ndarray:
+    """Coefficient of every cell of the level-k grid (reading: a LOR
+    sub-element takes the mean of b at its 2^d corners, which are GLL nodes
+    of the element containing it): corners c = c_x + 2 c_y + 4 c_z summed
+    in ascending order from 0.0, then multiplied by 2^-d.  coef is
+    (n_el, (p+1)^d) as in highorder.cg_stiffness."""
+    dim = mesh.dim
+    X = kept_points(p)[k]
+    s = len(X) - 1
+    cshape = [mesh.n[i] * s for i in range(dim)]
+    cidx = np.indices(cshape).reshape(dim, -1, order="F")
+    e = [cidx[i] // s for i in range(dim)]
+    m = [cidx[i] - e[i] * s for i in range(dim)]
+    eflat = _mesh.lex_index(e, list(mesh.n))
+    acc = np.zeros(cidx.shape[1])
+    for c in range(2 ** dim):
+        loc = [np.array(X)[m[i] + ((c >> i) & 1)] for i in range(dim)]
+        lflat = _mesh.lex_index(loc, [p + 1] * dim)
+        acc = acc + coef[eflat, lflat]
+    return acc * (0.125 if dim == 3 else 0.25)
+
+
+def level_stencils(coords: np.ndarray, shape, cell_coef=None) -> np.ndarray:
     """Assembled Q1 stiffness of a grid as (num_points, 3^d) stencil values.
 
     Entry (g, slot o) = sum over the cells S adjacent to g, in the order
     s = s_x + 2 s_y + 4 s_z of S = g - 1 + s, of K_S[corner of g][corner of
-    g+o] whenever g+o is also a corner of S; accumulated from 0.0.
+    g+o] whenever g+o is also a corner of S; accumulated from 0.0.  With a
+    coefficient each K_S entry is first multiplied by the cell's b_S.
     Entries reaching outside the grid are zero.
     """
     dim = len(shape)
     K = q1_stiffness(subelement_corners(coords, shape))
+    if cell_coef is not None:
+        K = K * cell_coef[None, None, :]
     cshape = [s - 1 for s in shape]
     npts = int(np.prod(shape))
     gidx = np.indices(shape).reshape(dim, -1, order="F")
@@ -238,11 +263,12 @@ def stencil_matrix(stencils: np.ndarray, shape, rows_mask=None) -> sp.csr_matrix
 class LORHierarchy:
     """Global LOR level grids, coordinates and stencils for a mesh and degree p."""
 
-    def __init__(self, mesh, p: int, fine_coords=None):
+    def __init__(self, mesh, p: int, fine_coords=None, coef=None):
         """fine_coords: the GLL node coordinates of mesh (computed when None);
         given for a submesh, they keep the nodes on its boundary bitwise equal
         to the enclosing mesh's, which evaluates interface nodes with the
-        lower-indexed element's map."""
+        lower-indexed element's map.  coef: b at the elements' GLL nodes
+        (n_el, (p+1)^d), None for b = 1."""
         self.mesh, self.p = mesh, p
         self.ref_nodes, _ = _gll.gll(p)
         self.fine_coords = (_mesh.global_node_coords(mesh, self.ref_nodes, p) if fine_coords is None
@@ -252,7 +278,10 @@ class LORHierarchy:
         self.nlevels = len(self.kept)
         self.shapes = [_mesh.grid_shape(mesh, s) for s in self.sizes]
         self.coords = [level_coords(mesh, p, k, self.fine_coords) for k in range(self.nlevels)]
-        self.stencils = [level_stencils(self.coords[k], self.shapes[k]) for k in range(self.nlevels)]
+        self.coef = coef
+        self.stencils = [level_stencils(self.coords[k], self.shapes[k],
+                                        None if coef is None else level_cell_coef(mesh, p, k, coef))
+                         for k in range(self.nlevels)]
 
     def matrix(self, k: int) -> sp.csr_matrix:
         return stencil_matrix(self.stencils[k], self.shapes[k])

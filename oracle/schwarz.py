@@ -57,8 +57,17 @@ def vertices(mesh):
         yield tuple(v)
 
 
+def domain_ranges(mesh, s: int):
+    """Per-direction inclusive level-grid ranges of all interior points."""
+    return [(1, mesh.n[i] * s - 1) for i in range(mesh.dim)]
+
+
 class Patch:
-    """All levels of one vertex patch: graphs, MDF factors, transfers."""
+    """All levels of one vertex patch: graphs, MDF factors, transfers.
+
+    v = None gives the single patch of the whole domain (Section 4.1,
+    "single patch"): every interior point of every level grid, the V-cycle
+    running down to the original mesh T_p, whose level is solved exactly."""
 
     def __init__(self, H: _lor.LORHierarchy, v, exact_local: bool = False, ordering: str = "mdf"):
         mesh = H.mesh
@@ -66,7 +75,7 @@ class Patch:
         self.v = v
         self.levels = []
         for k in range(H.nlevels):
-            rng = patch_ranges(mesh, H.sizes[k], v)
+            rng = patch_ranges(mesh, H.sizes[k], v) if v is not None else domain_ranges(mesh, H.sizes[k])
             shape = [hi - lo + 1 for lo, hi in rng]
             if min(shape) <= 0:
                 shape = [0] * dim
@@ -183,6 +192,9 @@ class CoarseSpace:
 class SchwarzLOR:
     """z = B r for the conforming problem on the Dirichlet unknowns.
 
+    patch_mode="vertex": one patch per mesh vertex plus the coarse space
+    (eq. as); "single": B(1), the V-cycle over the whole domain (Section 4.1).
+    coef: the coefficient b at the elements' GLL nodes (Section 4.2).
     weights="sum": eq. as, the patch corrections added unweighted.
     weights="pou": each patch correction multiplied by Theta_j = diag(1/c(i)),
     c(i) the number of patches whose level-0 unknowns include i (the
@@ -192,12 +204,20 @@ class SchwarzLOR:
     IC(0) smoother of every patch level."""
 
     def __init__(self, mesh, p: int, exact_local: bool = False, coarse: bool = True,
-                 ordering: str = "mdf", weights: str = "sum"):
-        self.H = _lor.LORHierarchy(mesh, p)
+                 ordering: str = "mdf", weights: str = "sum", coef=None, patch_mode: str = "vertex"):
+        self.H = _lor.LORHierarchy(mesh, p, coef=coef)
         self.Kh = self.H.matrix(0)
         self.fnum = _mesh.interior_numbering(self.H.shapes[0])
-        self.coarse = CoarseSpace(self.H, self.Kh) if coarse else None
-        self.patches = [Patch(self.H, v, exact_local, ordering) for v in vertices(mesh)]
+        if patch_mode == "single":
+            # B(1): one V-cycle over the whole domain; its coarsest level is
+            # T_p itself, solved exactly, so no separate coarse space
+            self.coarse = None
+            self.patches = [Patch(self.H, None, exact_local, ordering)]
+        elif patch_mode == "vertex":
+            self.coarse = CoarseSpace(self.H, self.Kh) if coarse else None
+            self.patches = [Patch(self.H, v, exact_local, ordering) for v in vertices(mesh)]
+        else:
+            raise ValueError(f"unknown patch mode {patch_mode!r}")
         if weights not in ("sum", "pou"):
             raise ValueError(f"unknown weights {weights!r}")
         self.weights = weights

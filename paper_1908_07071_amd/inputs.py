@@ -89,3 +89,29 @@ def nn_initial_params(channels: int = 32, seed: int = 11, cin: int = 2, layers: 
         out.append(np.zeros(co))
         c = co
     return np.concatenate(out)
+
+
+def coefficient(name: str, x: np.ndarray, elem=None, seed: int = 0) -> np.ndarray:
+    """Variable coefficients b of -div(b grad u) = f shaped like the paper's
+    examples (Section 4.2, defined there on [-1,1]^2), evaluated at points x
+    of [0,1]^d through x' = 2x - 1 (extended to 3D with the same pattern):
+      b1 = 1e4 prod_i (1 - x'_i^2)        sharp gradients near the boundary
+      b2 = 100 x'_0^2 + sum_{i>0} x'_i^2 + 1   anisotropic
+      b3 = (1 + |x'|^2)^4
+      b4 = 10 or 1 per element, drawn at random (elem: the element index of
+           each point; numpy default_rng(seed), one draw per element)
+    Returns b at every row of x."""
+    xp = 2.0 * np.asarray(x, dtype=np.float64) - 1.0
+    if name == "b1":
+        return 1e4 * np.prod(1.0 - xp ** 2, axis=1)
+    if name == "b2":
+        return 100.0 * xp[:, 0] ** 2 + np.sum(xp[:, 1:] ** 2, axis=1) + 1.0
+    if name == "b3":
+        return (1.0 + np.sum(xp ** 2, axis=1)) ** 4
+    if name == "b4":
+        if elem is None:
+            raise ValueError("b4 needs the element index of every point")
+        elem = np.asarray(elem)
+        vals = np.where(np.random.default_rng(seed).random(int(elem.max()) + 1) < 0.5, 10.0, 1.0)
+        return vals[elem]
+    raise ValueError(f"unknown coefficient {name!r}")
