@@ -72,6 +72,15 @@ typedef struct {
   int n[3];                 /* elements per direction (n[2] ignored in 2D) */
   const double *vertex_xyz; /* host */
   int bc;                   /* lor_bc_t; Neumann only supports lor_apply_A */
+  /* Coefficient b of -div(b grad u) = f (Section 4.2), HOST, NULL for b = 1:
+   * b at every element's GLL nodes, n_el x (p+1)^d float64, elements and
+   * local nodes lexicographic (x fastest) -- the layout of a DG E-vector, so
+   * that b may jump across element faces.  b >= 0, not zero everywhere;
+   * CG only.  It multiplies the quadrature weight of each node in the
+   * high-order operator, and each LOR sub-element's Q1 stiffness is scaled
+   * by the mean of b over the sub-element's 2^d corners (GLL nodes of the
+   * element holding it).  Copied during lor_setup. */
+  const double *coef;
 } lor_mesh_t;
 
 #define LOR_PREC_FP64   0   /* every step in float64 */
@@ -95,6 +104,19 @@ typedef struct {
                                partition of unity, not symmetric: flexible CG
                                is used)                                      */
 
+/* Subdomains of the Schwarz preconditioner. */
+#define LOR_PATCH_VERTEX 0  /* one patch per mesh vertex plus the coarse
+                               space (eq. as, Section 3.2)                    */
+#define LOR_PATCH_SINGLE 1  /* B(1) of Section 4.1: a single patch, the whole
+                               domain: one V-cycle of the LOR hierarchy with
+                               IC(0) smoothing (in the chosen order) on every
+                               level and the exact solve on the last level,
+                               the original mesh T_p (its interior vertices,
+                               at most 40000, by a dense inverse).  Float64
+                               only; the sweeps follow the dependency levels
+                               of the elimination order over the whole
+                               domain, so they are far longer than a patch's */
+
 typedef struct {
   int precision;       /* LOR_PREC_*                                        */
   int ordering;        /* LOR_ORD_*                                         */
@@ -102,7 +124,12 @@ typedef struct {
                           and for LOR_PROLONG_POU                           */
   int nthreads;        /* host threads for the ordering pass; 0 = all cores */
   int prolong_weights; /* LOR_PROLONG_*                                     */
-  int reserved[7];     /* must be zero                                      */
+  int patch_mode;      /* LOR_PATCH_*                                       */
+  int sweep_grid_rows; /* LOR_PATCH_SINGLE: a dependency level with more rows
+                          than this is swept by a launch over the whole
+                          device, runs of smaller levels by one workgroup
+                          (a barrier between levels); 0 = 8192            */
+  int reserved[5];     /* must be zero                                      */
 } lor_options_t;
 
 typedef struct {
@@ -175,6 +202,12 @@ int lor_bind_workspace(lor_handle_t *h, void *dev_ptr, size_t bytes, void *strea
  * GLL grid node evaluated with the map of element min(g_i / p, n_i - 1) in
  * each direction.  DG: each element's own map at its GLL nodes. */
 int lor_dof_coords(const lor_handle_t *h, double *host_xyz);
+
+/* Coordinates of every element's GLL nodes (each element's own map), HOST
+ * output of n_el (p+1)^d x dim float64 in the E-vector layout: where a
+ * variable coefficient is evaluated (lor_mesh_t.coef).  Uses a temporary
+ * device buffer. */
+int lor_element_coords(const lor_handle_t *h, double *host_xyz);
 
 /* b = M_p f with the collocated GLL mass (eq. system right-hand side):
  * b_i = sum over elements containing node i of w_i |J_i| f_i.

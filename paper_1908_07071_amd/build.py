@@ -34,6 +34,8 @@ SOURCES = [
     ("k_nnconv.hip", []),
     ("nn_api.cpp", []),
     ("noalloc.hip", []),
+    ("single.cpp", []),
+    ("k_single.hip", []),
 ]
 
 ARCH = "gfx950"

@@ -94,7 +94,8 @@ __global__ void k_dg_coords(MeshDims md, const double *__restrict__ verts,
 template <int DIM>
 __global__ void k_geom(MeshDims md, const double *__restrict__ verts,
                        const double *__restrict__ gllx, const double *__restrict__ gllw,
-                       double *__restrict__ G, double *__restrict__ wdet, int *bad) {
+                       const double *__restrict__ coef, double *__restrict__ G,
+                       double *__restrict__ wdet, int *bad) {
   const int Q = md.p + 1;
   const int nq = DIM == 3 ? Q * Q * Q : Q * Q;
   const int64_t nel = int64_t(md.n[0]) * md.n[1] * (DIM == 3 ? md.n[2] : 1);
@@ -146,8 +147,9 @@ __global__ void k_geom(MeshDims md, const double *__restrict__ verts,
       det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
     }
     if (!(det > 0.0)) atomicOr(bad, 1);
-    // G = (w / det) * A A^T, with A = det * J^-1
-    const double f = w / det;
+    // G = (w / det) * A A^T, with A = det * J^-1 (times the coefficient b
+    // at the node: -div(b grad u), Section 4.2)
+    const double f = coef ? (w / det) * coef[e * nq + q] : w / det;
     double *Ge = G + e * ncomp * nq;
     int comp = 0;
     for (int r = 0; r < DIM; ++r)
@@ -172,7 +174,8 @@ struct KeptIdx {
 
 template <int DIM>
 __global__ void k_lor_stencil(MeshDims md, int s, KeptIdx kept, const double *__restrict__ fine,
-                              double g0, double g1, double *__restrict__ out) {
+                              double g0, double g1, const double *__restrict__ coef,
+                              double *__restrict__ out) {
   constexpr int NC = 1 << DIM;
   constexpr int NS = DIM == 3 ? 27 : 9;
   const int lng[3] = {md.n[0] * s + 1, md.n[1] * s + 1, DIM == 3 ? md.n[2] * s + 1 : 1};
@@ -272,6 +275,31 @@ __global__ void k_lor_stencil(MeshDims md, int s, KeptIdx kept, const double *__
           if constexpr (DIM == 3) dot = dot + u[ca][2] * u[b][2];
           K[b] = K[b] + coef * dot;
         }
+      }
+      if (coef) {
+        // the cell's coefficient: mean of b at its corners, GLL nodes of the
+        // element holding the cell (corners ascending from 0.0, then 2^-d)
+        const int Q = md.p + 1;
+        int64_t eflat = 0, estride = 1;
+        int mloc[3] = {0, 0, 0};
+        for (int i = 0; i < DIM; ++i) {
+          const int e = S[i] / s;
+          mloc[i] = S[i] - e * s;
+          eflat += int64_t(e) * estride;
+          estride *= md.n[i];
+        }
+        const double *ce = coef + eflat * (DIM == 3 ? Q * Q * Q : Q * Q);
+        double bs = 0.0;
+        for (int c = 0; c < NC; ++c) {
+          int lf = 0, ls = 1;
+          for (int i = 0; i < DIM; ++i) {
+            lf += kept.fine[mloc[i] + ((c >> i) & 1)] * ls;
+            ls *= Q;
+          }
+          bs = bs + ce[lf];
+        }
+        bs = bs * (DIM == 3 ? 0.125 : 0.25);
+        for (int b = 0; b < NC; ++b) K[b] = K[b] * bs;
       }
       for (int b = 0; b < NC; ++b) {
         int sl = 0, p3 = 1;
@@ -495,14 +523,15 @@ hipError_t launch_node_coords(const MeshDims &md, const double *verts, const dou
 }
 
 hipError_t launch_geom_cg(const MeshDims &md, const double *verts, const double *gllx,
-                          const double *gllw, double *G, double *wdet, int *bad, hipStream_t st) {
+                          const double *gllw, const double *coef, double *G, double *wdet, int *bad,
+                          hipStream_t st) {
   const int Q = md.p + 1;
   const int64_t nel = int64_t(md.n[0]) * md.n[1] * (md.dim == 3 ? md.n[2] : 1);
   const int64_t tot = nel * (md.dim == 3 ? Q * Q * Q : Q * Q);
   if (md.dim == 3)
-    k_geom<3><<<grid_for(tot, 256), 256, 0, st>>>(md, verts, gllx, gllw, G, wdet, bad);
+    k_geom<3><<<grid_for(tot, 256), 256, 0, st>>>(md, verts, gllx, gllw, coef, G, wdet, bad);
   else
-    k_geom<2><<<grid_for(tot, 256), 256, 0, st>>>(md, verts, gllx, gllw, G, wdet, bad);
+    k_geom<2><<<grid_for(tot, 256), 256, 0, st>>>(md, verts, gllx, gllw, coef, G, wdet, bad);
   return hipGetLastError();
 }
 
@@ -518,16 +547,16 @@ hipError_t launch_dg_coords(const MeshDims &md, const double *verts, const doubl
 }
 
 hipError_t launch_lor_stencil(const MeshDims &md, int s, const int *kept_fine_idx,
-                              const double *fine_coords, double g0, double g1, double *stencil,
-                              hipStream_t st) {
+                              const double *fine_coords, double g0, double g1, const double *coef,
+                              double *stencil, hipStream_t st) {
   KeptIdx k{};
   for (int i = 0; i <= s; ++i) k.fine[i] = kept_fine_idx[i];
   const int64_t npts = int64_t(md.n[0] * s + 1) * (md.n[1] * s + 1) *
                        (md.dim == 3 ? md.n[2] * s + 1 : 1);
   if (md.dim == 3)
-    k_lor_stencil<3><<<grid_for(npts, 128), 128, 0, st>>>(md, s, k, fine_coords, g0, g1, stencil);
+    k_lor_stencil<3><<<grid_for(npts, 128), 128, 0, st>>>(md, s, k, fine_coords, g0, g1, coef, stencil);
   else
-    k_lor_stencil<2><<<grid_for(npts, 128), 128, 0, st>>>(md, s, k, fine_coords, g0, g1, stencil);
+    k_lor_stencil<2><<<grid_for(npts, 128), 128, 0, st>>>(md, s, k, fine_coords, g0, g1, coef, stencil);
   return hipGetLastError();
 }
 

@@ -1,0 +1,243 @@
+// Kernels of the single-patch preconditioner B(1) (Section 4.1: one patch,
+// the whole domain): the element-structured V-cycle of Section 3.3 on the
+// global LOR level grids, with IC(0) smoothing in the chosen order and the
+// exact solve on T_p (a dense inverse applied by the coarse GEMV).
+//
+// Every vector is a level's interior box (all level-grid points not on the
+// Dirichlet boundary, x fastest); at level 0 that is the L-vector itself.
+// The triangular sweeps follow the dependency levels of the elimination
+// order (rows of one level are independent): a run of small levels goes to
+// one workgroup that walks through them with a barrier between levels; a
+// level with many rows gets a launch of its own over the whole GPU.
+#include <hip/hip_runtime.h>
+
+#include "lor_internal.h"
+
+namespace lor {
+
+namespace {
+
+struct BoxDims {
+  int m0, m1, m2;
+};
+
+// neighbour of row i at stencil slot s (the caller knows it is in the box)
+template <int DIM>
+__device__ __forceinline__ int nb_index(int i, int s, BoxDims b) {
+  const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = DIM == 3 ? s / 9 - 1 : 0;
+  return i + dx + b.m0 * (dy + b.m1 * dz);
+}
+
+// forward: x_i = b_i - sum_{earlier m} l_im x_m (x and b may alias);
+// backward: x_i = x_i / d_i - sum_{later m} l_mi x_m (in place).
+template <int DIM, bool FWD>
+__device__ __forceinline__ void sweep_row(int i, const double *__restrict__ Lv,
+                                          const double *__restrict__ invD, const int *__restrict__ mask,
+                                          const double *b, double *x, BoxDims bd) {
+  constexpr int NS = DIM == 3 ? 27 : 9;
+  unsigned mk = unsigned(mask[i]);
+  double acc = FWD ? b[i] : x[i] * invD[i];
+  const double *li = Lv + int64_t(i) * NS;
+  while (mk) {
+    const int s = __builtin_ctz(mk);
+    mk &= mk - 1;
+    acc -= li[s] * x[nb_index<DIM>(i, s, bd)];
+  }
+  x[i] = acc;
+}
+
+template <int DIM, bool FWD>
+__global__ __launch_bounds__(1024) void k_sweep_block(const int *__restrict__ sched,
+                                                      const int *__restrict__ lptr, int l0, int l1,
+                                                      const double *__restrict__ Lv,
+                                                      const double *__restrict__ invD,
+                                                      const int *__restrict__ mask, const double *b,
+                                                      double *x, BoxDims bd, const double *flag) {
+  if (flag && flag[S_DONE] != 0.0) return;
+  for (int t = 0; t < l1 - l0; ++t) {
+    const int l = FWD ? l0 + t : l1 - 1 - t;
+    for (int q = lptr[l] + int(threadIdx.x); q < lptr[l + 1]; q += blockDim.x)
+      sweep_row<DIM, FWD>(sched[q], Lv, invD, mask, b, x, bd);
+    __syncthreads();  // the next level reads this level's rows
+  }
+}
+
+template <int DIM, bool FWD>
+__global__ __launch_bounds__(256) void k_sweep_level(const int *__restrict__ sched, int q0, int q1,
+                                                     const double *__restrict__ Lv,
+                                                     const double *__restrict__ invD,
+                                                     const int *__restrict__ mask, const double *b,
+                                                     double *x, BoxDims bd, const double *flag) {
+  if (flag && flag[S_DONE] != 0.0) return;
+  const int q = q0 + int(blockIdx.x * blockDim.x + threadIdx.x);
+  if (q < q1) sweep_row<DIM, FWD>(sched[q], Lv, invD, mask, b, x, bd);
+}
+
+// r = b - A x on the interior box; A from the slot-major level stencil over
+// the whole level grid (lng points per direction, boundary points included)
+template <int DIM>
+__global__ __launch_bounds__(256) void k_box_residual(const double *__restrict__ stencil, int64_t npts,
+                                                      int lng0, int lng1, BoxDims bd,
+                                                      const double *__restrict__ b,
+                                                      const double *__restrict__ x,
+                                                      double *__restrict__ r, const double *flag) {
+  if (flag && flag[S_DONE] != 0.0) return;
+  constexpr int NS = DIM == 3 ? 27 : 9;
+  const int64_t n = int64_t(bd.m0) * bd.m1 * bd.m2;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int ix = int(i % bd.m0), iy = int((i / bd.m0) % bd.m1), iz = int(i / (int64_t(bd.m0) * bd.m1));
+    const int64_t g = (ix + 1) + int64_t(lng0) * ((iy + 1) + (DIM == 3 ? int64_t(lng1) * (iz + 1) : 0));
+    double acc = b[i];
+    for (int s = 0; s < NS; ++s) {
+      const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = DIM == 3 ? s / 9 - 1 : 0;
+      const int qx = ix + dx, qy = iy + dy, qz = iz + dz;
+      if (qx < 0 || qx >= bd.m0 || qy < 0 || qy >= bd.m1 || (DIM == 3 && (qz < 0 || qz >= bd.m2)))
+        continue;  // a Dirichlet boundary point: its value is zero
+      acc -= stencil[s * npts + g] * x[qx + int64_t(bd.m0) * (qy + int64_t(bd.m1) * qz)];
+    }
+    r[i] = acc;
+  }
+}
+
+// x_f += sum over the 2^d parents of P_f,c xc_c (1D tables per direction:
+// parent index in the coarse box or -1, and weight)
+template <int DIM>
+__global__ __launch_bounds__(256) void k_box_prolong(SingleXfer t, const double *__restrict__ xc,
+                                                     double *__restrict__ x, const double *flag) {
+  if (flag && flag[S_DONE] != 0.0) return;
+  const int64_t n = int64_t(t.mf[0]) * t.mf[1] * t.mf[2];
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int f[3] = {int(i % t.mf[0]), int((i / t.mf[0]) % t.mf[1]), int(i / (int64_t(t.mf[0]) * t.mf[1]))};
+    double acc = 0.0;
+    for (int c = 0; c < (1 << DIM); ++c) {
+      int64_t ci = 0, stride = 1;
+      double w = 1.0;
+      bool ok = true;
+      for (int d = 0; d < DIM; ++d) {
+        const int b = (c >> d) & 1;
+        const int pc = t.pc[d][2 * f[d] + b];
+        if (pc < 0) ok = false;
+        w *= t.pw[d][2 * f[d] + b];
+        ci += int64_t(pc) * stride;
+        stride *= t.mc[d];
+      }
+      if (ok) acc += w * xc[ci];
+    }
+    x[i] += acc;
+  }
+}
+
+// rc_c = sum over the fine points f with P_f,c != 0 of P_f,c r_f (R[d]
+// entries per coarse index and direction, f = -1 for unused entries)
+template <int DIM>
+__global__ __launch_bounds__(256) void k_box_restrict(SingleXfer t, const double *__restrict__ r,
+                                                      double *__restrict__ rc, const double *flag) {
+  if (flag && flag[S_DONE] != 0.0) return;
+  const int64_t n = int64_t(t.mc[0]) * t.mc[1] * t.mc[2];
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int c[3] = {int(i % t.mc[0]), int((i / t.mc[0]) % t.mc[1]), int(i / (int64_t(t.mc[0]) * t.mc[1]))};
+    const int R0 = t.R[0], R1 = DIM >= 2 ? t.R[1] : 1, R2 = DIM == 3 ? t.R[2] : 1;
+    double acc = 0.0;
+    for (int a2 = 0; a2 < R2; ++a2) {
+      const int f2 = DIM == 3 ? t.rf[2][c[2] * R2 + a2] : 0;
+      if (f2 < 0) continue;
+      const double w2 = DIM == 3 ? t.rw[2][c[2] * R2 + a2] : 1.0;
+      for (int a1 = 0; a1 < R1; ++a1) {
+        const int f1 = t.rf[1][c[1] * R1 + a1];
+        if (f1 < 0) continue;
+        const double w12 = w2 * t.rw[1][c[1] * R1 + a1];
+        for (int a0 = 0; a0 < R0; ++a0) {
+          const int f0 = t.rf[0][c[0] * R0 + a0];
+          if (f0 < 0) continue;
+          acc += w12 * t.rw[0][c[0] * R0 + a0] *
+                 r[f0 + int64_t(t.mf[0]) * (f1 + int64_t(t.mf[1]) * f2)];
+        }
+      }
+    }
+    rc[i] = acc;
+  }
+}
+
+__global__ void k_axpy1(double *__restrict__ x, const double *__restrict__ y, int64_t n,
+                        const double *flag) {
+  if (flag && flag[S_DONE] != 0.0) return;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    x[i] += y[i];
+}
+
+inline int blocks_for(int64_t n, int bs) {
+  int64_t g = (n + bs - 1) / bs;
+  return int(g > 4096 ? 4096 : (g < 1 ? 1 : g));
+}
+
+}  // namespace
+
+hipError_t launch_single_sweep(int dim, bool fwd, const SingleLevelDev &lv, const double *b, double *x,
+                               const double *flag, hipStream_t st) {
+  const BoxDims bd{lv.m[0], lv.m[1], lv.m[2]};
+  const int nseg = int(lv.segs.size());
+  for (int k = 0; k < nseg; ++k) {
+    const SingleSeg &sg = lv.segs[fwd ? k : nseg - 1 - k];
+    if (sg.grid) {
+      const int q0 = lv.lptr_host[sg.l0], q1 = lv.lptr_host[sg.l0 + 1];
+      const int nb = (q1 - q0 + 255) / 256;
+      if (dim == 3) {
+        if (fwd) k_sweep_level<3, true><<<nb, 256, 0, st>>>(lv.sched, q0, q1, lv.Lv, lv.invD, lv.emask, b, x, bd, flag);
+        else k_sweep_level<3, false><<<nb, 256, 0, st>>>(lv.sched, q0, q1, lv.Lv, lv.invD, lv.lmask, x, x, bd, flag);
+      } else {
+        if (fwd) k_sweep_level<2, true><<<nb, 256, 0, st>>>(lv.sched, q0, q1, lv.Lv, lv.invD, lv.emask, b, x, bd, flag);
+        else k_sweep_level<2, false><<<nb, 256, 0, st>>>(lv.sched, q0, q1, lv.Lv, lv.invD, lv.lmask, x, x, bd, flag);
+      }
+    } else {
+      if (dim == 3) {
+        if (fwd) k_sweep_block<3, true><<<1, 1024, 0, st>>>(lv.sched, lv.lptr, sg.l0, sg.l1, lv.Lv, lv.invD, lv.emask, b, x, bd, flag);
+        else k_sweep_block<3, false><<<1, 1024, 0, st>>>(lv.sched, lv.lptr, sg.l0, sg.l1, lv.Lv, lv.invD, lv.lmask, x, x, bd, flag);
+      } else {
+        if (fwd) k_sweep_block<2, true><<<1, 1024, 0, st>>>(lv.sched, lv.lptr, sg.l0, sg.l1, lv.Lv, lv.invD, lv.emask, b, x, bd, flag);
+        else k_sweep_block<2, false><<<1, 1024, 0, st>>>(lv.sched, lv.lptr, sg.l0, sg.l1, lv.Lv, lv.invD, lv.lmask, x, x, bd, flag);
+      }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_single_residual(int dim, const double *stencil, int64_t npts, const int *lng,
+                                  const int *m, const double *b, const double *x, double *r,
+                                  const double *flag, hipStream_t st) {
+  const BoxDims bd{m[0], m[1], m[2]};
+  const int64_t n = int64_t(m[0]) * m[1] * m[2];
+  if (n <= 0) return hipSuccess;
+  if (dim == 3)
+    k_box_residual<3><<<blocks_for(n, 256), 256, 0, st>>>(stencil, npts, lng[0], lng[1], bd, b, x, r, flag);
+  else
+    k_box_residual<2><<<blocks_for(n, 256), 256, 0, st>>>(stencil, npts, lng[0], lng[1], bd, b, x, r, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_single_transfer(int dim, bool prolong, const SingleXfer &t, const double *in,
+                                  double *out, const double *flag, hipStream_t st) {
+  const int64_t n = prolong ? int64_t(t.mf[0]) * t.mf[1] * t.mf[2] : int64_t(t.mc[0]) * t.mc[1] * t.mc[2];
+  if (n <= 0) return hipSuccess;
+  if (prolong) {
+    if (dim == 3) k_box_prolong<3><<<blocks_for(n, 256), 256, 0, st>>>(t, in, out, flag);
+    else k_box_prolong<2><<<blocks_for(n, 256), 256, 0, st>>>(t, in, out, flag);
+  } else {
+    if (dim == 3) k_box_restrict<3><<<blocks_for(n, 256), 256, 0, st>>>(t, in, out, flag);
+    else k_box_restrict<2><<<blocks_for(n, 256), 256, 0, st>>>(t, in, out, flag);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy1(double *x, const double *y, int64_t n, const double *flag, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_axpy1<<<blocks_for(n, 256), 256, 0, st>>>(x, y, n, flag);
+  return hipGetLastError();
+}
+
+}  // namespace lor

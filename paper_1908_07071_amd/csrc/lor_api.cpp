@@ -414,7 +414,11 @@ int setup_impl(lor_handle &h, hipStream_t st) {
   int *bad;
   HIPCHK(h.alloc(&bad, 1));
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), st));
-  HIPCHK(launch_geom_cg(md, h.d_verts, h.d_gllx, h.d_gllw, h.d_G, h.d_wdet, bad, st));
+  if (!h.coef.empty()) {
+    HIPCHK(h.alloc(&h.d_coef, h.coef.size()));
+    HIPCHK(hipMemcpyAsync(h.d_coef, h.coef.data(), h.coef.size() * 8, hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(launch_geom_cg(md, h.d_verts, h.d_gllx, h.d_gllw, h.d_coef, h.d_G, h.d_wdet, bad, st));
   int hb = 0;
   HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -442,11 +446,18 @@ int setup_impl(lor_handle &h, hipStream_t st) {
     const int s = int(h.kept[k].size()) - 1;
     h.npts[k] = int64_t(md.n[0] * s + 1) * (md.n[1] * s + 1) * (dim == 3 ? md.n[2] * s + 1 : 1);
     HIPCHK(h.alloc(&h.d_stencil[k], size_t(NS) * h.npts[k]));
-    HIPCHK(launch_lor_stencil(md, s, h.kept[k].data(), h.d_coords, g0, g1, h.d_stencil[k], st));
+    HIPCHK(launch_lor_stencil(md, s, h.kept[k].data(), h.d_coords, g0, g1, h.d_coef, h.d_stencil[k], st));
     hst[k].resize(size_t(NS) * h.npts[k]);
     HIPCHK(hipMemcpyAsync(hst[k].data(), h.d_stencil[k], hst[k].size() * 8, hipMemcpyDeviceToHost, st));
   }
   HIPCHK(hipStreamSynchronize(st));
+  if (h.opt.patch_mode == LOR_PATCH_SINGLE) {
+    const int rc = build_single(h, hst, st);
+    if (rc != LOR_OK) return rc;
+    HIPCHK(hipStreamSynchronize(st));
+    h.has_prec = true;
+    return LOR_OK;
+  }
   int rc = build_patches(h, hst, st);
   if (rc != LOR_OK) return rc;
   rc = build_coarse(h, hst[0], st);
@@ -518,6 +529,10 @@ struct Span {
 // Conforming Schwarz preconditioner on L-vectors (eq. as).
 int apply_P_cg(lor_handle *h, Work &w, const double *r, double *z, const double *flag,
                hipStream_t st) {
+  if (h->opt.patch_mode == LOR_PATCH_SINGLE) {
+    Span sp(h, LOR_T_PATCH, st);
+    return apply_single(h, r, z, flag, st);
+  }
   if (h->nc > 0) {
     Span sp(h, LOR_T_COARSE, st);
     HIPCHK(launch_coarse_restrict(h->md, h->d_gllx, r, w.rc, st));
@@ -795,7 +810,12 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const l
       return LOR_EINVAL;
     if (opt->prolong_weights != LOR_PROLONG_SUM && opt->prolong_weights != LOR_PROLONG_POU)
       return LOR_EINVAL;
-    for (int t = 0; t < 7; ++t)
+    if (opt->patch_mode != LOR_PATCH_VERTEX && opt->patch_mode != LOR_PATCH_SINGLE)
+      return LOR_EINVAL;
+    if (opt->patch_mode == LOR_PATCH_SINGLE && opt->precision != LOR_PREC_FP64)
+      return invalid("the single-patch preconditioner runs in float64 only", __LINE__);
+    if (opt->sweep_grid_rows < 0) return LOR_EINVAL;
+    for (int t = 0; t < 5; ++t)
       if (opt->reserved[t] != 0) return LOR_EINVAL;
   } else {
     lor_default_options(&h->opt);
@@ -803,6 +823,21 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const l
   h->verts.assign(mesh->vertex_xyz, mesh->vertex_xyz + nv * mesh->dim);
   for (double v : h->verts)
     if (!std::isfinite(v)) return LOR_EINVAL;
+  if (mesh->coef) {
+    if (method != LOR_CG) return invalid("a variable coefficient needs the CG discretization", __LINE__);
+    int64_t ne = 1, nq = 1;
+    for (int d = 0; d < mesh->dim; ++d) {
+      ne *= mesh->n[d];
+      nq *= p + 1;
+    }
+    h->coef.assign(mesh->coef, mesh->coef + ne * nq);
+    bool pos = false;
+    for (double v : h->coef) {
+      if (!(std::isfinite(v) && v >= 0.0)) return invalid("coefficient negative or not finite", __LINE__);
+      pos = pos || v > 0.0;
+    }
+    if (!pos) return invalid("coefficient zero everywhere", __LINE__);
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIPCHK(hipGetDevice(&h->device));
   int rc = setup_impl(*h, st);
@@ -887,13 +922,18 @@ int lor_bind_workspace(lor_handle_t *h, void *dev_ptr, size_t bytes, void *strea
     };
     set(h->d_verts), set(h->d_gllx), set(h->d_gllw), set(h->d_D), set(h->d_coords);
     set(h->d_G), set(h->d_wdet), set(h->d_fac), set(h->d_fac_off), set(h->d_xfer);
-    set(h->d_A0inv), set(h->d_fg), set(h->d_dinv);
+    set(h->d_A0inv), set(h->d_fg), set(h->d_dinv), set(h->d_coef);
     for (int k = 0; k < kMaxLevels; ++k) set(h->d_stencil[k]);
     Work &w = h->w;
     set(w.r), set(w.z), set(w.p), set(w.q), set(w.rold), set(w.tmp), set(w.scal), set(w.part);
     set(w.part2), set(w.rc), set(w.xc), set(w.yE), set(w.fo), set(w.rL), set(w.zL);
     for (int k = 0; k < kMaxLevels; ++k) set(h->pa.stencil[k]);
     set(h->pa.xfer), set(h->pa.fac), set(h->pa.fac_off);
+    for (SingleLevelDev &lv : h->single) {
+      set(lv.sched), set(lv.lptr), set(lv.Lv), set(lv.invD), set(lv.emask), set(lv.lmask);
+      set(lv.x), set(lv.b), set(lv.r), set(lv.ainv);
+      for (int d = 0; d < 3; ++d) set(lv.xf.pc[d]), set(lv.xf.pw[d]), set(lv.xf.rf[d]), set(lv.xf.rw[d]);
+    }
   };
   apply(false);  // dry run: resolve every pointer before anything changes
   if (!ok) return LOR_ESTATE;
@@ -910,18 +950,22 @@ int lor_bind_workspace(lor_handle_t *h, void *dev_ptr, size_t bytes, void *strea
   return LOR_OK;
 }
 
+int lor_element_coords(const lor_handle_t *h, double *host_xyz) {
+  if (!h || !host_xyz) return LOR_EINVAL;
+  const int Q = h->p + 1;
+  const size_t nb = size_t(h->nel) * (h->dim == 3 ? Q * Q * Q : Q * Q) * h->dim * sizeof(double);
+  double *tmp = nullptr;
+  if (hipMalloc(&tmp, nb) != hipSuccess) return LOR_EHIP;
+  hipError_t e = launch_dg_coords(h->md, h->d_verts, h->d_gllx, tmp, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(host_xyz, tmp, nb, hipMemcpyDeviceToHost);
+  (void)hipFree(tmp);
+  return e == hipSuccess ? LOR_OK : LOR_EHIP;
+}
+
 int lor_dof_coords(const lor_handle_t *h, double *host_xyz) {
   if (!h || !host_xyz) return LOR_EINVAL;
   const int dim = h->dim;
-  if (h->method != LOR_CG) {
-    double *tmp = nullptr;
-    const size_t nb = size_t(h->ndofs) * dim * sizeof(double);
-    if (hipMalloc(&tmp, nb) != hipSuccess) return LOR_EHIP;
-    hipError_t e = launch_dg_coords(h->md, h->d_verts, h->d_gllx, tmp, nullptr);
-    if (e == hipSuccess) e = hipMemcpy(host_xyz, tmp, nb, hipMemcpyDeviceToHost);
-    (void)hipFree(tmp);
-    return e == hipSuccess ? LOR_OK : LOR_EHIP;
-  }
+  if (h->method != LOR_CG) return lor_element_coords(h, host_xyz);
   std::vector<double> all(size_t(h->nfine) * dim);
   if (hipMemcpy(all.data(), h->d_coords, all.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
     return LOR_EHIP;

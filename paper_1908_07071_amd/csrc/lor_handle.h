@@ -35,6 +35,7 @@ struct lor_handle {
   lor_options_t opt{};
   MeshDims md{};
   std::vector<double> verts, gllx, gllw, D;
+  std::vector<double> coef;  // b at the elements' GLL nodes (empty: b = 1)
   std::vector<std::vector<int>> kept;
   int L = 1;
   int64_t ndofs = 0, nfine = 0, nel = 0;
@@ -64,12 +65,14 @@ struct lor_handle {
   XferTab *d_xfer = nullptr;
   double *d_A0inv = nullptr;
   double *d_fg = nullptr, *d_dinv = nullptr;
+  double *d_coef = nullptr;
   int npart = 0;
   Work w;                  // workspace of lor_pcg_solve / lor_apply_*
   lor_nn *nn = nullptr;    // patch network used instead of the V-cycles (LOR_NN_REPLACE)
   int nn_mode = 0;
   bool capturing = false;  // no event timing while a graph is captured
   PatchArgs pa{};
+  std::vector<SingleLevelDev> single;  // LOR_PATCH_SINGLE: B(1) levels
   // host copies for parity export
   std::vector<int32_t> order_all, order_off, sched_all, sched_off;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -123,6 +126,11 @@ int apply_P_scratch(lor_handle *h, double *scratch, size_t cap, const double *r,
 // Looks up, once per device, the device address of the static scratch array
 // of the no-allocation entry point on the current device (noalloc.hip).
 int noalloc_register_device(int device);
+
+// Single-patch preconditioner B(1) (single.cpp): set-up from the host copies
+// of the level stencils, and z = B(1) r.
+int build_single(lor_handle &h, const std::vector<std::vector<double>> &hst, hipStream_t st);
+int apply_single(lor_handle *h, const double *r, double *z, const double *flag, hipStream_t st);
 
 // Patches of the Schwarz preconditioner through the attached network:
 // z += sum_j R_j^T s_j net(R_j r / s_j) (nn_api.cpp).

@@ -151,11 +151,14 @@ std::vector<char> pack_sweep(const MdfResult &res, int dim, const int *m, bool f
 // when its S_DONE entry is set.
 hipError_t launch_node_coords(const MeshDims &md, const double *verts, const double *gllx,
                               double *coords, hipStream_t st);
+// coef: the coefficient b at every element's GLL nodes (n_el (p+1)^d), or
+// nullptr for b = 1
 hipError_t launch_geom_cg(const MeshDims &md, const double *verts, const double *gllx,
-                          const double *gllw, double *G, double *wdet, int *bad, hipStream_t st);
+                          const double *gllw, const double *coef, double *G, double *wdet, int *bad,
+                          hipStream_t st);
 hipError_t launch_lor_stencil(const MeshDims &md, int s, const int *kept_fine_idx,
-                              const double *fine_coords, double g0, double g1, double *stencil,
-                              hipStream_t st);
+                              const double *fine_coords, double g0, double g1, const double *coef,
+                              double *stencil, hipStream_t st);
 hipError_t launch_rhs_cg(const MeshDims &md, const double *wdet, const double *f, double *b,
                          hipStream_t st);
 // Blocks (= partial sums) of one operator launch.
@@ -218,6 +221,46 @@ hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r,
 hipError_t launch_patch_vcycle_warm(const PatchArgs &pa, int first, int count, const double *r,
                                     double *z, const float *y, const double *scale,
                                     const double *flag, hipStream_t st);
+// ---- single-patch preconditioner B(1) (k_single.hip, single.cpp)
+// 1D transfer tables between the interior boxes of levels k and k+1: for
+// every fine index its two parents (coarse index or -1) and weights, for
+// every coarse index R[d] (fine index or -1, weight) pairs.
+struct SingleXfer {
+  int mf[3], mc[3], R[3];
+  const int *pc[3];
+  const double *pw[3];
+  const int *rf[3];
+  const double *rw[3];
+};
+// a run of dependency levels [l0, l1) swept by one workgroup, or one large
+// level (grid = 1, l1 = l0 + 1) swept by a launch over the whole device
+struct SingleSeg {
+  int l0, l1, grid;
+};
+struct SingleLevelDev {
+  int m[3];                    // interior box extents
+  int64_t n;                   // rows
+  int *sched = nullptr;        // rows by dependency level
+  int *lptr = nullptr;         // level starts (depth + 1)
+  std::vector<int> lptr_host;
+  std::vector<SingleSeg> segs;
+  double *Lv = nullptr;        // n x 3^d factor values (row i: l_im earlier, l_mi later)
+  double *invD = nullptr;      // 1 / pivot
+  int *emask = nullptr;        // slots of earlier in-box neighbours
+  int *lmask = nullptr;        // slots of later in-box neighbours
+  double *x = nullptr, *b = nullptr, *r = nullptr;  // level vectors (level 0: r only)
+  SingleXfer xf{};             // to the next coarser level
+  double *ainv = nullptr;      // coarsest level: dense inverse
+};
+hipError_t launch_single_sweep(int dim, bool fwd, const SingleLevelDev &lv, const double *b, double *x,
+                               const double *flag, hipStream_t st);
+hipError_t launch_single_residual(int dim, const double *stencil, int64_t npts, const int *lng,
+                                  const int *m, const double *b, const double *x, double *r,
+                                  const double *flag, hipStream_t st);
+hipError_t launch_single_transfer(int dim, bool prolong, const SingleXfer &t, const double *in,
+                                  double *out, const double *flag, hipStream_t st);
+hipError_t launch_axpy1(double *x, const double *y, int64_t n, const double *flag, hipStream_t st);
+
 hipError_t launch_fill(double *x, int64_t n, double v, hipStream_t st);
 hipError_t launch_to_float(const double *src, float *dst, int64_t n, hipStream_t st);
 // slot-major float64 stencil (3^dim x npts) -> point-major records

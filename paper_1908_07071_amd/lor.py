@@ -24,6 +24,7 @@ LOR_BC_DIRICHLET, LOR_BC_NEUMANN = 0, 1
 LOR_PREC_FP64, LOR_PREC_MIXED = 0, 1
 LOR_ORD_MDF, LOR_ORD_NATURAL, LOR_ORD_RCM = 0, 1, 2
 LOR_PROLONG_SUM, LOR_PROLONG_POU = 0, 1
+LOR_PATCH_VERTEX, LOR_PATCH_SINGLE = 0, 1
 LOR_MAP_LDOF, LOR_MAP_ORDER, LOR_MAP_ORDER_OFFSET = 0, 1, 2
 LOR_MAP_SCHEDULE, LOR_MAP_SCHEDULE_OFFSET, LOR_MAP_E2L = 3, 4, 5
 
@@ -35,7 +36,7 @@ EXPORTED = [
     "lor_nn_param_count", "lor_nn_create", "lor_nn_get_params", "lor_nn_shape", "lor_nn_patch_data",
     "lor_nn_forward", "lor_nn_gradients", "lor_nn_train_step", "lor_nn_attach", "lor_nn_free",
     "lor_bf16_gemm", "lor_apply_P_noalloc", "lor_noalloc_scratch_bytes", "lor_workspace_bytes",
-    "lor_bind_workspace",
+    "lor_bind_workspace", "lor_element_coords",
 ]
 LOR_NN_OFF, LOR_NN_REPLACE, LOR_NN_WARMSTART = 0, 1, 2
 LOR_T_APPLY_A, LOR_T_PATCH, LOR_T_COARSE = 0, 1, 2
@@ -51,12 +52,13 @@ class LorError(RuntimeError):
 
 class lor_mesh_t(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("vertex_xyz", C.POINTER(C.c_double)),
-                ("bc", C.c_int)]
+                ("bc", C.c_int), ("coef", C.POINTER(C.c_double))]
 
 
 class lor_options_t(C.Structure):
     _fields_ = [("precision", C.c_int), ("ordering", C.c_int), ("flexible", C.c_int),
-                ("nthreads", C.c_int), ("prolong_weights", C.c_int), ("reserved", C.c_int * 7)]
+                ("nthreads", C.c_int), ("prolong_weights", C.c_int), ("patch_mode", C.c_int),
+                ("sweep_grid_rows", C.c_int), ("reserved", C.c_int * 5)]
 
 
 class lor_solve_info_t(C.Structure):
@@ -82,6 +84,7 @@ def _load():
         "lor_ndofs": (C.c_int, [vp, i64p]),
         "lor_device_bytes": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
         "lor_workspace_bytes": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
+        "lor_element_coords": (C.c_int, [vp, dp]),
         "lor_bind_workspace": (C.c_int, [vp, vp, C.c_size_t, vp]),
         "lor_dof_coords": (C.c_int, [vp, dp]),
         "lor_assemble_rhs": (C.c_int, [vp, vp, vp, vp]),
@@ -200,8 +203,9 @@ def lor_default_options():
 
 
 def lor_setup(dim: int, n, vertices: np.ndarray, p: int, method: int = LOR_CG, penalty: float = 0.0,
-              options: lor_options_t | None = None, bc: int = LOR_BC_DIRICHLET, stream=None):
-    """Returns an opaque handle (ctypes void pointer)."""
+              options: lor_options_t | None = None, bc: int = LOR_BC_DIRICHLET, stream=None, coef=None):
+    """Returns an opaque handle (ctypes void pointer).  coef: None or b at the
+    elements' GLL nodes, n_el x (p+1)^dim values (E-vector layout)."""
     n = [int(n)] * dim if np.isscalar(n) else [int(v) for v in n]
     verts = np.ascontiguousarray(vertices, dtype=np.float64)
     mesh = lor_mesh_t()
@@ -210,6 +214,11 @@ def lor_setup(dim: int, n, vertices: np.ndarray, p: int, method: int = LOR_CG, p
         mesh.n[i] = n[i] if i < dim else 1
     mesh.vertex_xyz = _dptr(verts)
     mesh.bc = bc
+    if coef is not None:
+        cf = np.ascontiguousarray(coef, dtype=np.float64).ravel()
+        if cf.size != int(np.prod(n)) * (p + 1) ** dim:
+            raise ValueError("coef needs n_el * (p+1)^dim values")
+        mesh.coef = _dptr(cf)
     h = C.c_void_p()
     opt = C.byref(options) if options is not None else None
     rc = _lib.lor_setup(C.byref(mesh), int(p), int(method), float(penalty), opt, _stream(stream), C.byref(h))
@@ -245,6 +254,12 @@ def lor_bind_workspace(h, ws, stream=None):
     nbytes = ws.numel() * ws.element_size()
     _check(_lib.lor_bind_workspace(h, C.c_void_p(ws.data_ptr()), C.c_size_t(nbytes), _stream(stream)),
            "lor_bind_workspace")
+
+
+def lor_element_coords(h, dim: int, nel: int, p: int) -> np.ndarray:
+    out = np.zeros((nel * (p + 1) ** dim, dim))
+    _check(_lib.lor_element_coords(h, _dptr(out)), "lor_element_coords")
+    return out
 
 
 def lor_dof_coords(h, dim: int) -> np.ndarray:
