@@ -532,6 +532,84 @@ def ordering_variants(L, torch, dim, n, p, rtol, steps, names):
     return out
 
 
+def _solve_case(L, torch, dim, n, p, V, opt, rtol, steps, coef=None, rhs="manufactured"):
+    from paper_1908_07071_amd import inputs
+    h = L.lor_setup(dim, n, V, p, options=opt, coef=coef)
+    N = L.lor_ndofs(h)
+    if rhs == "manufactured":
+        f = torch.tensor(inputs.manufactured_f(L.lor_dof_coords(h, dim)), device="cuda:0")
+        b = torch.empty_like(f)
+        L.lor_assemble_rhs(h, f, b)
+    else:
+        b = torch.tensor(inputs.gaussian_rhs(N, 5), device="cuda:0")
+    x = torch.zeros_like(b)
+    info, ms = solve_timed(L, torch, h, b, x, rtol, steps)
+    L.lor_free(h)
+    return {"N": N, "iters": info.iters, "status": STATUS_NAMES.get(info.status, str(info.status)),
+            "rel_res_true": info.rel_res_true, "ms_per_solve": ms, "dofs_per_s": N / (ms * 1e-3),
+            "setup_s": info.t_setup}
+
+
+def single_patch_measure(L, torch, rtol):
+    """B(1) (one patch, the whole domain, Section 4.1) against the vertex
+    patches B(V): the 2D 8 x 8 p = 3 unit-square problem (float64 PCG to
+    1e-10, f from sin(pi x) sin(pi y)) and the 16^3 p = 6 benchmark mesh
+    (float64 PCG to rtol, reverse Cuthill-McKee order for both)."""
+    from paper_1908_07071_amd import inputs
+    out = {}
+    V2 = inputs.structured_vertices(2, 8)
+    for mode, code in (("single", L.LOR_PATCH_SINGLE), ("vertex", L.LOR_PATCH_VERTEX)):
+        opt = L.lor_default_options()
+        opt.patch_mode = code
+        out[f"square_8x8_p3_{mode}"] = _solve_case(L, torch, 2, 8, 3, V2, opt, 1e-10, 3)
+    V3 = inputs.structured_vertices(3, 16, 0.1, seed=1)
+    for mode, code, ordname, ordcode in (("single", L.LOR_PATCH_SINGLE, "rcm", L.LOR_ORD_RCM),
+                                         ("single", L.LOR_PATCH_SINGLE, "natural", L.LOR_ORD_NATURAL),
+                                         ("vertex", L.LOR_PATCH_VERTEX, "rcm", L.LOR_ORD_RCM)):
+        opt = L.lor_default_options()
+        opt.patch_mode = code
+        opt.ordering = ordcode
+        rec = _solve_case(L, torch, 3, 16, 6, V3, opt, rtol, 1)
+        if mode == "single":
+            # dependency depth of the level-0 sweep over the whole domain
+            h = L.lor_setup(3, 16, V3, 6, options=opt)
+            soff = L.lor_export_maps(h, L.LOR_MAP_SCHEDULE_OFFSET)
+            rec["level0_depth"] = int(soff[1] - soff[0] - 1)
+            L.lor_free(h)
+        out[f"cube_16_p6_{ordname}_{mode}"] = rec
+    for k, v in out.items():
+        print(f"[bench] {k}: {v['iters']} it, {v['ms_per_solve']:.2f} ms/solve, setup {v['setup_s']:.1f} s",
+              file=sys.stderr, flush=True)
+    return out
+
+
+def coefficient_measure(L, torch, rtol, n=16, p=4):
+    """Iterations with the coefficients b1-b4 (Section 4.2 shapes) on a 2D
+    n x n perturbed mesh at degree p, for B(1) and B(V), Gaussian right side."""
+    import numpy as np
+
+    from paper_1908_07071_amd import inputs
+    V = inputs.structured_vertices(2, n, 0.1, seed=4)
+    out = {}
+    h0 = L.lor_setup(2, n, V, p)
+    X = L.lor_element_coords(h0, 2, n * n, p)
+    L.lor_free(h0)
+    elem = np.repeat(np.arange(n * n), (p + 1) ** 2)
+    for name in ("b1", "b2", "b3", "b4"):
+        coef = inputs.coefficient(name, X, elem=elem, seed=3)
+        rec = {}
+        for mode, code in (("single", L.LOR_PATCH_SINGLE), ("vertex", L.LOR_PATCH_VERTEX)):
+            opt = L.lor_default_options()
+            opt.patch_mode = code
+            r = _solve_case(L, torch, 2, n, p, V, opt, rtol, 2, coef=coef, rhs="gaussian")
+            rec[mode] = {"iters": r["iters"], "status": r["status"], "ms_per_solve": r["ms_per_solve"]}
+        out[name] = rec
+        print(f"[bench] coefficient {name}: B(1) {rec['single']['iters']} it, "
+              f"B(V) {rec['vertex']['iters']} it", file=sys.stderr, flush=True)
+    return {"workload": f"2D {n}x{n} perturbed (seed 4), p={p}, float64 PCG to {rtol:g}, Gaussian rhs",
+            "iters": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -730,6 +808,8 @@ def main():
     out["roofline"]["frac_of_copy"] = achieved / out["hbm_copy_gbs"]
     out["operator_hbm_frac"] = apply_algorithmic_bytes(dim, n, p) / t_apply / (HBM_PEAK_GBS * 1e9)
     if not args.no_sweep:
+        out["single_patch"] = single_patch_measure(L, torch, args.rtol)
+        out["coefficients"] = coefficient_measure(L, torch, args.rtol)
         out["p_sweep"] = p_sweep(L, torch, dim, n, (2, 4, 6, 8), args.rtol, 2)
         out["orderings"] = ordering_variants(L, torch, dim, n, p, args.rtol, 3,
                                              [o for o in args.orderings.split(",") if o])
