@@ -62,6 +62,76 @@ def domain_ranges(mesh, s: int):
     return [(1, mesh.n[i] * s - 1) for i in range(mesh.dim)]
 
 
+def box_ranges(s: int, box):
+    """Level-grid ranges of the points strictly inside an element box
+    [(a_d, b_d)] (elements a_d .. b_d - 1 in direction d)."""
+    return [(a * s + 1, b * s - 1) for a, b in box]
+
+
+def vertex_box(mesh, v):
+    """The elements around vertex v: its patch (eq. patch) as an element box."""
+    return [(max(v[i] - 1, 0), min(v[i] + 1, mesh.n[i])) for i in range(mesh.dim)]
+
+
+def isotropic_boxes(mesh):
+    """Vertex patches enlarged for isotropic overlap (Section 4.5: patches
+    holding anisotropic elements are extended so that the overlap stays
+    isotropic).  Reading: delta = the longest mesh edge at vertex v; in each
+    direction and sense the box grows from v, one element at a time, until
+    the vertex reached lies at least 0.9 delta away from v (so that edges
+    equal up to rounding or a small perturbation count as reached) or the
+    boundary is reached.  Distances compare squared Euclidean lengths,
+    summed over the coordinates in order, against 0.81 delta^2."""
+    X = mesh.vertices
+    out = []
+    for v in vertices(mesh):
+        xv = X[mesh.vertex_index(v)]
+
+        def d2(w):
+            diff = X[mesh.vertex_index(w)] - xv
+            acc = 0.0
+            for t in range(mesh.dim):
+                acc = acc + diff[t] * diff[t]
+            return acc
+
+        delta2 = 0.0
+        for i in range(mesh.dim):
+            for sgn in (-1, 1):
+                w = list(v)
+                w[i] += sgn
+                if 0 <= w[i] <= mesh.n[i]:
+                    delta2 = max(delta2, d2(w))
+        box = []
+        for i in range(mesh.dim):
+            ext = []
+            for sgn in (-1, 1):
+                k = 0
+                while True:
+                    k += 1
+                    w = list(v)
+                    w[i] += sgn * k
+                    if w[i] <= 0 or w[i] >= mesh.n[i] or d2(w) >= 0.81 * delta2:
+                        break
+                ext.append(k)
+            box.append((max(v[i] - ext[0], 0), min(v[i] + ext[1], mesh.n[i])))
+        out.append(box)
+    return out
+
+
+def slab_boxes(mesh, nslabs: int, axis: int = 0, overlap: int = 1):
+    """B(n) of Section 4.5: n subdomains, here slabs of nearly equal element
+    counts along one axis (bounds i n // nslabs), each widened by `overlap`
+    elements on its inner sides; the other directions span the domain."""
+    n = mesh.n[axis]
+    out = []
+    for i in range(nslabs):
+        a, b = i * n // nslabs, (i + 1) * n // nslabs
+        box = [(0, mesh.n[t]) for t in range(mesh.dim)]
+        box[axis] = (max(a - overlap, 0), min(b + overlap, n))
+        out.append(box)
+    return out
+
+
 class Patch:
     """All levels of one vertex patch: graphs, MDF factors, transfers.
 
@@ -69,13 +139,19 @@ class Patch:
     "single patch"): every interior point of every level grid, the V-cycle
     running down to the original mesh T_p, whose level is solved exactly."""
 
-    def __init__(self, H: _lor.LORHierarchy, v, exact_local: bool = False, ordering: str = "mdf"):
+    def __init__(self, H: _lor.LORHierarchy, v, exact_local: bool = False, ordering: str = "mdf",
+                 box=None):
         mesh = H.mesh
         dim = mesh.dim
         self.v = v
         self.levels = []
         for k in range(H.nlevels):
-            rng = patch_ranges(mesh, H.sizes[k], v) if v is not None else domain_ranges(mesh, H.sizes[k])
+            if box is not None:
+                rng = box_ranges(H.sizes[k], box)
+            elif v is not None:
+                rng = patch_ranges(mesh, H.sizes[k], v)
+            else:
+                rng = domain_ranges(mesh, H.sizes[k])
             shape = [hi - lo + 1 for lo, hi in rng]
             if min(shape) <= 0:
                 shape = [0] * dim
@@ -193,7 +269,10 @@ class SchwarzLOR:
     """z = B r for the conforming problem on the Dirichlet unknowns.
 
     patch_mode="vertex": one patch per mesh vertex plus the coarse space
-    (eq. as); "single": B(1), the V-cycle over the whole domain (Section 4.1).
+    (eq. as); "single": B(1), the V-cycle over the whole domain (Section 4.1);
+    "slabs": B(n), nslabs overlapping slabs (Section 4.5); "vertex_iso": the
+    vertex patches enlarged for isotropic overlap, plus the coarse space
+    (Section 4.5).
     coef: the coefficient b at the elements' GLL nodes (Section 4.2).
     weights="sum": eq. as, the patch corrections added unweighted.
     weights="pou": each patch correction multiplied by Theta_j = diag(1/c(i)),
@@ -204,7 +283,8 @@ class SchwarzLOR:
     IC(0) smoother of every patch level."""
 
     def __init__(self, mesh, p: int, exact_local: bool = False, coarse: bool = True,
-                 ordering: str = "mdf", weights: str = "sum", coef=None, patch_mode: str = "vertex"):
+                 ordering: str = "mdf", weights: str = "sum", coef=None, patch_mode: str = "vertex",
+                 nslabs: int = 2):
         self.H = _lor.LORHierarchy(mesh, p, coef=coef)
         self.Kh = self.H.matrix(0)
         self.fnum = _mesh.interior_numbering(self.H.shapes[0])
@@ -213,6 +293,16 @@ class SchwarzLOR:
             # T_p itself, solved exactly, so no separate coarse space
             self.coarse = None
             self.patches = [Patch(self.H, None, exact_local, ordering)]
+        elif patch_mode == "slabs":
+            # B(n): n overlapping subdomains, each V-cycle down to its own
+            # part of T_p, solved exactly there; no separate coarse space
+            self.coarse = None
+            self.patches = [Patch(self.H, None, exact_local, ordering, box=b)
+                            for b in slab_boxes(mesh, nslabs)]
+        elif patch_mode == "vertex_iso":
+            self.coarse = CoarseSpace(self.H, self.Kh) if coarse else None
+            self.patches = [Patch(self.H, v, exact_local, ordering, box=b)
+                            for v, b in zip(vertices(mesh), isotropic_boxes(mesh))]
         elif patch_mode == "vertex":
             self.coarse = CoarseSpace(self.H, self.Kh) if coarse else None
             self.patches = [Patch(self.H, v, exact_local, ordering) for v in vertices(mesh)]

@@ -115,3 +115,23 @@ def coefficient(name: str, x: np.ndarray, elem=None, seed: int = 0) -> np.ndarra
         vals = np.where(np.random.default_rng(seed).random(int(elem.max()) + 1) < 0.5, 10.0, 1.0)
         return vals[elem]
     raise ValueError(f"unknown coefficient {name!r}")
+
+
+def strip_vertices(n: int, aspect: float, strip_rows: int = 2, dim: int = 2) -> np.ndarray:
+    """An n^dim block of [0,1]^dim with a strip of thin elements (Section 4.5
+    shape): element width 1/n in x (and z); in y, `strip_rows` rows in the
+    middle have height (1/n)/aspect -- elements of aspect ratio `aspect` --
+    and the other rows share the rest of the height equally.  Vertices as in
+    structured_vertices (x fastest)."""
+    if not (1 <= strip_rows < n):
+        raise ValueError("need 1 <= strip_rows < n")
+    hs = (1.0 / n) / aspect
+    ho = (1.0 - strip_rows * hs) / (n - strip_rows)
+    first = (n - strip_rows) // 2
+    heights = [hs if first <= j < first + strip_rows else ho for j in range(n)]
+    y = np.concatenate([[0.0], np.cumsum(heights)])
+    y[-1] = 1.0
+    axes = [np.linspace(0.0, 1.0, n + 1) for _ in range(dim)]
+    axes[1] = y
+    grids = np.meshgrid(*axes, indexing="ij")
+    return np.stack([g.reshape(-1, order="F") for g in grids], axis=1).copy()
