@@ -583,6 +583,33 @@ def single_patch_measure(L, torch, rtol):
     return out
 
 
+def strip_measure(L, torch, rtol, n=8, degrees=(3, 7), aspects=(1.5, 15.0, 150.0, 1500.0)):
+    """Section 4.5 shape: a 2D n x n mesh with two strip rows of thin
+    elements (aspect ratio A), float64 PCG to rtol, Gaussian right side:
+    iterations of the plain vertex patches B(V), the isotropic-overlap
+    patches, B(1), B(2) and B(3)."""
+    from paper_1908_07071_amd import inputs
+    modes = (("vertex", L.LOR_PATCH_VERTEX, 0), ("vertex_iso", L.LOR_PATCH_VERTEX_ISO, 0),
+             ("single", L.LOR_PATCH_SINGLE, 0), ("slabs2", L.LOR_PATCH_SLABS, 2),
+             ("slabs3", L.LOR_PATCH_SLABS, 3))
+    out = {}
+    for p in degrees:
+        for A in aspects:
+            V = inputs.strip_vertices(n, A)
+            rec = {}
+            for name, code, ns in modes:
+                opt = L.lor_default_options()
+                opt.patch_mode = code
+                opt.nslabs = ns
+                r = _solve_case(L, torch, 2, n, p, V, opt, rtol, 1, rhs="gaussian")
+                rec[name] = {"iters": r["iters"], "status": r["status"], "ms_per_solve": r["ms_per_solve"]}
+            out[f"p{p}_A{A:g}"] = rec
+            print(f"[bench] strip p={p} A={A:g}: " +
+                  ", ".join(f"{k} {v['iters']}" for k, v in rec.items()), file=sys.stderr, flush=True)
+    return {"workload": f"2D {n}x{n} strip mesh (two rows of aspect A), float64 PCG to {rtol:g}, "
+                        "Gaussian rhs", "iters": out}
+
+
 def coefficient_measure(L, torch, rtol, n=16, p=4):
     """Iterations with the coefficients b1-b4 (Section 4.2 shapes) on a 2D
     n x n perturbed mesh at degree p, for B(1) and B(V), Gaussian right side."""
@@ -808,8 +835,21 @@ def main():
     out["roofline"]["frac_of_copy"] = achieved / out["hbm_copy_gbs"]
     out["operator_hbm_frac"] = apply_algorithmic_bytes(dim, n, p) / t_apply / (HBM_PEAK_GBS * 1e9)
     if not args.no_sweep:
+        # the 32^3 p = 6 mesh of the learned-correction workload, plain
+        # float32-preconditioner solve (N = 6,967,871)
+        V32 = inputs.structured_vertices(3, 32, 0.1, seed=3)
+        opt32 = L.lor_default_options()
+        opt32.precision = L.LOR_PREC_MIXED
+        rec32 = _solve_case(L, torch, 3, 32, 6, V32, opt32, args.rtol, 2)
+        rec32["workload"] = ("3D CG 32^3 perturbed (seed 3), p=6, f from the manufactured u, FP64 "
+                             "flexible CG with FP32 LOR vertex-patch Schwarz (MDF) to " + f"{args.rtol:g}")
+        out["cube_32_p6_mixed"] = rec32
+        print(f"[bench] 32^3 p=6 mixed: {rec32['iters']} it, {rec32['ms_per_solve']:.1f} ms/solve, "
+              f"{rec32['dofs_per_s'] / 1e6:.2f} M DOF/s, setup {rec32['setup_s']:.1f} s",
+              file=sys.stderr, flush=True)
         out["single_patch"] = single_patch_measure(L, torch, args.rtol)
         out["coefficients"] = coefficient_measure(L, torch, args.rtol)
+        out["strip"] = strip_measure(L, torch, args.rtol)
         out["p_sweep"] = p_sweep(L, torch, dim, n, (2, 4, 6, 8), args.rtol, 2)
         out["orderings"] = ordering_variants(L, torch, dim, n, p, args.rtol, 3,
                                              [o for o in args.orderings.split(",") if o])

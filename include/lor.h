@@ -112,10 +112,26 @@ typedef struct {
                                IC(0) smoothing (in the chosen order) on every
                                level and the exact solve on the last level,
                                the original mesh T_p (its interior vertices,
-                               at most 40000, by a dense inverse).  Float64
-                               only; the sweeps follow the dependency levels
-                               of the elimination order over the whole
+                               at most 40000, by a dense inverse); no separate
+                               coarse space.  The sweeps follow the dependency
+                               levels of the elimination order over the whole
                                domain, so they are far longer than a patch's */
+#define LOR_PATCH_SLABS  2  /* B(n) of Section 4.5: nslabs overlapping
+                               subdomains, slabs of elements along x (bounds
+                               i n[0] / nslabs, widened by one element on
+                               their inner sides), each solved like B(1) on
+                               its part of the hierarchy; no coarse space    */
+#define LOR_PATCH_VERTEX_ISO 3 /* vertex patches enlarged for isotropic overlap
+                               (Section 4.5): from each vertex the patch grows,
+                               per direction and sense, one element at a time
+                               until the vertex reached is at least 0.9 times
+                               the longest mesh edge at the vertex away (or
+                               the boundary is reached); each solved like B(1)
+                               on its box, plus the coarse space of eq. as.
+                               The box-patch modes (SINGLE, SLABS, VERTEX_ISO)
+                               run in float64 and apply their patches one
+                               after another: meant for the iteration shape
+                               of Sections 4.1 and 4.5, not for speed       */
 
 typedef struct {
   int precision;       /* LOR_PREC_*                                        */
@@ -125,11 +141,12 @@ typedef struct {
   int nthreads;        /* host threads for the ordering pass; 0 = all cores */
   int prolong_weights; /* LOR_PROLONG_*                                     */
   int patch_mode;      /* LOR_PATCH_*                                       */
-  int sweep_grid_rows; /* LOR_PATCH_SINGLE: a dependency level with more rows
+  int sweep_grid_rows; /* box-patch modes: a dependency level with more rows
                           than this is swept by a launch over the whole
                           device, runs of smaller levels by one workgroup
-                          (a barrier between levels); 0 = 8192            */
-  int reserved[5];     /* must be zero                                      */
+                          (a barrier between levels); 0 = 512             */
+  int nslabs;          /* LOR_PATCH_SLABS: number of subdomains, 1..n[0]    */
+  int reserved[4];     /* must be zero                                      */
 } lor_options_t;
 
 typedef struct {

@@ -34,7 +34,7 @@ SOURCES = [
     ("k_nnconv.hip", []),
     ("nn_api.cpp", []),
     ("noalloc.hip", []),
-    ("single.cpp", []),
+    ("box_patch.cpp", ["-ffp-contract=off"]),
     ("k_single.hip", []),
 ]
 

@@ -1,0 +1,437 @@
+// Box-patch Schwarz preconditioners (host set-up and application):
+//   B(1)  one patch, the whole domain (Section 4.1);
+//   B(n)  n overlapping slabs of elements (Section 4.5);
+//   vertex patches enlarged for isotropic overlap, plus the coarse space
+//         (Section 4.5).
+// A patch is a box of elements [a_d, b_d); its unknowns on level k are the
+// level-grid points strictly inside it.  Its solver is one V-cycle of the
+// element-structured LOR hierarchy (Section 3.3) restricted to the box: IC(0)
+// smoothing in the chosen elimination order on every level but the last, the
+// exact solve (a dense inverse) on the box's part of T_p.  Patches are applied
+// one after another on the caller's stream; B(1) writes z directly, the
+// others gather the patch residual and add the (optionally weighted)
+// correction back.  Float64.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "lor_handle.h"
+
+namespace {
+
+#define SCHK(x)                                 \
+  do {                                          \
+    hipError_t e_ = (x);                        \
+    if (e_ != hipSuccess) return LOR_EHIP;      \
+  } while (0)
+
+constexpr int kGridLevel = 512;    // default: levels with more rows get a launch of their own
+constexpr int kHostInverse = 512;  // coarsest box levels up to this size are inverted on the host
+
+template <class T>
+hipError_t upload(lor_handle &h, T **dst, const std::vector<T> &src, hipStream_t st) {
+  hipError_t e = h.alloc(dst, std::max<size_t>(src.size(), 1));
+  if (e != hipSuccess || src.empty()) return e;
+  return hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+// 1D interpolation from level k+1 to level k between the interior indices of
+// a box [a, b) in direction d (linear in reference coordinates, Section 3.3).
+struct Xfer1D {
+  std::vector<int> pc;  // 2 per fine index
+  std::vector<double> pw;
+  std::vector<int> rf;  // R per coarse index
+  std::vector<double> rw;
+  int mf = 0, mc = 0, R = 1;
+};
+
+Xfer1D xfer_1d(const lor_handle &h, int k, int d, int a, int b) {
+  Xfer1D t;
+  const std::vector<int> &Xf = h.kept[k], &Xc = h.kept[k + 1];
+  const int sf = int(Xf.size()) - 1, sc = int(Xc.size()) - 1, n = h.n[d];
+  const int lof = a * sf + 1, loc = a * sc + 1;
+  t.mf = std::max((b - a) * sf - 1, 0);
+  t.mc = std::max((b - a) * sc - 1, 0);
+  t.pc.assign(size_t(2) * t.mf, -1);
+  t.pw.assign(size_t(2) * t.mf, 0.0);
+  std::vector<std::vector<std::pair<int, double>>> lists(t.mc);
+  const std::vector<double> &x = h.gllx;
+  for (int f = 0; f < t.mf; ++f) {
+    const int G = lof + f;
+    const int e = std::min(G / sf, n - 1);
+    const int av = Xf[G - e * sf];
+    int C[2];
+    double w[2];
+    auto it = std::find(Xc.begin(), Xc.end(), av);
+    if (it != Xc.end()) {
+      C[0] = e * sc + int(it - Xc.begin());
+      w[0] = 1.0;
+      C[1] = -1;
+      w[1] = 0.0;
+    } else {
+      int hi = 0;
+      while (Xc[hi] < av) ++hi;
+      const int lo = hi - 1;
+      const double xl = x[Xc[lo]], xh = x[Xc[hi]];
+      C[0] = e * sc + lo;
+      C[1] = e * sc + hi;
+      w[0] = (xh - x[av]) / (xh - xl);
+      w[1] = (x[av] - xl) / (xh - xl);
+    }
+    for (int q = 0; q < 2; ++q) {
+      const int c = C[q] - loc;  // box-local coarse index; outside the box the value is zero
+      if (C[q] < 0 || c < 0 || c >= t.mc || w[q] == 0.0) continue;
+      t.pc[2 * f + q] = c;
+      t.pw[2 * f + q] = w[q];
+      lists[c].push_back({f, w[q]});
+    }
+  }
+  t.R = 1;
+  for (auto &l : lists) t.R = std::max<int>(t.R, int(l.size()));
+  t.rf.assign(size_t(t.R) * std::max(t.mc, 1), -1);
+  t.rw.assign(size_t(t.R) * std::max(t.mc, 1), 0.0);
+  for (int c = 0; c < t.mc; ++c)
+    for (size_t q = 0; q < lists[c].size(); ++q) {
+      t.rf[size_t(c) * t.R + q] = lists[c][q].first;
+      t.rw[size_t(c) * t.R + q] = lists[c][q].second;
+    }
+  return t;
+}
+
+// in-place inverse of a small SPD matrix (Gauss-Jordan, no pivoting)
+bool host_inverse(std::vector<double> &A, int n) {
+  for (int k = 0; k < n; ++k) {
+    const double piv = A[size_t(k) * n + k];
+    if (!(std::isfinite(piv) && piv > 0.0)) return false;
+    const double ip = 1.0 / piv;
+    for (int j = 0; j < n; ++j) A[size_t(k) * n + j] *= ip;
+    A[size_t(k) * n + k] = ip;
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const double f = A[size_t(i) * n + k];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) A[size_t(i) * n + j] -= f * A[size_t(k) * n + j];
+      A[size_t(i) * n + k] = -f * ip;
+    }
+  }
+  return true;
+}
+
+// squared distance between two vertices, coordinates summed in order
+double vdist2(const lor_handle &h, const int *v, const int *w) {
+  const int nv0 = h.n[0] + 1, nv1 = h.n[1] + 1;
+  const int64_t iv = v[0] + int64_t(nv0) * (v[1] + int64_t(nv1) * v[2]);
+  const int64_t iw = w[0] + int64_t(nv0) * (w[1] + int64_t(nv1) * w[2]);
+  double acc = 0.0;
+  for (int t = 0; t < h.dim; ++t) {
+    const double d = h.verts[size_t(iw) * h.dim + t] - h.verts[size_t(iv) * h.dim + t];
+    acc = acc + d * d;
+  }
+  return acc;
+}
+
+}  // namespace
+
+// The element boxes of the patch mode (see the oracle's readings): B(1) the
+// domain; B(n) slabs along x with bounds i n / nslabs widened by one element
+// on inner sides; isotropic vertex patches grown from each vertex, per
+// direction and sense, until the vertex reached is at least 0.9 times the
+// longest edge at the vertex away (squared lengths against 0.81 delta^2) or
+// the boundary is reached.
+std::vector<std::array<int, 6>> patch_boxes(const lor_handle &h) {
+  std::vector<std::array<int, 6>> out;
+  const int dim = h.dim;
+  auto full = [&]() {
+    std::array<int, 6> b{};
+    for (int d = 0; d < 3; ++d) {
+      b[d] = 0;
+      b[3 + d] = d < dim ? h.n[d] : 1;
+    }
+    return b;
+  };
+  if (h.opt.patch_mode == LOR_PATCH_SINGLE) {
+    out.push_back(full());
+  } else if (h.opt.patch_mode == LOR_PATCH_SLABS) {
+    const int ns = h.opt.nslabs, n = h.n[0];
+    for (int i = 0; i < ns; ++i) {
+      std::array<int, 6> b = full();
+      const int a0 = int(int64_t(i) * n / ns), b0 = int(int64_t(i + 1) * n / ns);
+      b[0] = std::max(a0 - 1, 0);
+      b[3] = std::min(b0 + 1, n);
+      out.push_back(b);
+    }
+  } else if (h.opt.patch_mode == LOR_PATCH_VERTEX_ISO) {
+    const int nv[3] = {h.n[0] + 1, h.n[1] + 1, dim == 3 ? h.n[2] + 1 : 1};
+    for (int j = 0; j < nv[0] * nv[1] * nv[2]; ++j) {
+      const int v[3] = {j % nv[0], (j / nv[0]) % nv[1], j / (nv[0] * nv[1])};
+      double delta2 = 0.0;
+      for (int d = 0; d < dim; ++d)
+        for (int sg = -1; sg <= 1; sg += 2) {
+          int w[3] = {v[0], v[1], v[2]};
+          w[d] += sg;
+          if (w[d] >= 0 && w[d] <= h.n[d]) delta2 = std::max(delta2, vdist2(h, v, w));
+        }
+      std::array<int, 6> b{};
+      for (int d = 0; d < 3; ++d) {
+        if (d >= dim) {
+          b[d] = 0;
+          b[3 + d] = 1;
+          continue;
+        }
+        int ext[2];
+        for (int q = 0; q < 2; ++q) {
+          const int sg = q == 0 ? -1 : 1;
+          int k = 0;
+          for (;;) {
+            ++k;
+            int w[3] = {v[0], v[1], v[2]};
+            w[d] += sg * k;
+            if (w[d] <= 0 || w[d] >= h.n[d] || vdist2(h, v, w) >= 0.81 * delta2) break;
+          }
+          ext[q] = k;
+        }
+        b[d] = std::max(v[d] - ext[0], 0);
+        b[3 + d] = std::min(v[d] + ext[1], h.n[d]);
+      }
+      out.push_back(b);
+    }
+  }
+  return out;
+}
+
+int build_boxes(lor_handle &h, const std::vector<std::vector<double>> &hst, hipStream_t st) {
+  const int dim = h.dim, NS = dim == 3 ? 27 : 9, C = NS / 2, L = h.L, nf = L - 1;
+  const std::vector<std::array<int, 6>> boxes = patch_boxes(h);
+  h.boxes.assign(boxes.size(), BoxPatchDev{});
+  h.J = int(boxes.size());
+  h.order_off.assign(size_t(h.J) * nf + 1, 0);
+  h.sched_off.assign(size_t(h.J) * nf + 1, 0);
+  h.order_all.clear();
+  h.sched_all.clear();
+  std::vector<int64_t> maxn(L, 0);
+  std::vector<double> count(size_t(h.ncg), 0.0);
+  int t = 0;
+  for (size_t j = 0; j < boxes.size(); ++j) {
+    BoxPatchDev &bp = h.boxes[j];
+    for (int d = 0; d < 3; ++d) {
+      bp.a[d] = boxes[j][d];
+      bp.b[d] = boxes[j][3 + d];
+    }
+    bp.lv.assign(L, SingleLevelDev{});
+    for (int k = 0; k < L; ++k) {
+      SingleLevelDev &lv = bp.lv[k];
+      const int s = int(h.kept[k].size()) - 1;
+      int lng[3] = {1, 1, 1};
+      lv.n = 1;
+      for (int d = 0; d < 3; ++d) {
+        lng[d] = d < dim ? h.n[d] * s + 1 : 1;
+        lv.lo[d] = d < dim ? bp.a[d] * s + 1 : 0;
+        lv.m[d] = d < dim ? std::max((bp.b[d] - bp.a[d]) * s - 1, 0) : 1;
+        lv.n *= lv.m[d];
+      }
+      maxn[k] = std::max(maxn[k], lv.n);
+      const int64_t np = h.npts[k];
+      auto grid_index = [&](int64_t i) {
+        const int ix = int(i % lv.m[0]), iy = int((i / lv.m[0]) % lv.m[1]),
+                  iz = int(i / (int64_t(lv.m[0]) * lv.m[1]));
+        return int64_t(ix + lv.lo[0]) +
+               int64_t(lng[0]) * (int64_t(iy + lv.lo[1]) + (dim == 3 ? int64_t(lng[1]) * (iz + lv.lo[2]) : 0));
+      };
+      auto in_box = [&](int64_t i, int sl, int64_t *jj) {
+        const int ix = int(i % lv.m[0]), iy = int((i / lv.m[0]) % lv.m[1]),
+                  iz = int(i / (int64_t(lv.m[0]) * lv.m[1]));
+        const int q[3] = {ix + sl % 3 - 1, iy + (sl / 3) % 3 - 1, dim == 3 ? iz + sl / 9 - 1 : 0};
+        for (int d = 0; d < 3; ++d)
+          if (q[d] < 0 || q[d] >= lv.m[d]) return false;
+        *jj = q[0] + int64_t(lv.m[0]) * (q[1] + int64_t(lv.m[1]) * q[2]);
+        return true;
+      };
+      if (k == 0 && lv.n > 0) {
+        for (int64_t i = 0; i < lv.n; ++i) {
+          const int ix = int(i % lv.m[0]), iy = int((i / lv.m[0]) % lv.m[1]),
+                    iz = int(i / (int64_t(lv.m[0]) * lv.m[1]));
+          const int64_t u = (ix + lv.lo[0] - 1) +
+                            int64_t(h.md.nu[0]) * ((iy + lv.lo[1] - 1) + (dim == 3 ? int64_t(h.md.nu[1]) * (iz + lv.lo[2] - 1) : 0));
+          count[u] += 1.0;
+        }
+      }
+      if (k < L - 1) {
+        h.order_off[t + 1] = h.order_off[t] + int32_t(lv.n);
+        if (lv.n <= 0) {
+          h.sched_off[t + 1] = h.sched_off[t];
+          ++t;
+          continue;
+        }
+        if (lv.n > (int64_t(1) << 30) / NS) return LOR_EINVAL;
+        std::vector<double> rows(size_t(lv.n) * NS);
+        for (int64_t i = 0; i < lv.n; ++i) {
+          const int64_t g = grid_index(i);
+          for (int sl = 0; sl < NS; ++sl) rows[size_t(i) * NS + sl] = hst[k][size_t(sl) * np + g];
+        }
+        MdfResult res;
+        const int rc = mdf_factor(dim, lv.m, rows, h.opt.ordering, res);
+        if (rc != LOR_OK) return rc;
+        h.order_all.insert(h.order_all.end(), res.order.begin(), res.order.end());
+        h.sched_all.insert(h.sched_all.end(), res.level_ptr.begin(), res.level_ptr.end());
+        h.sched_off[t + 1] = h.sched_off[t] + int32_t(res.level_ptr.size());
+        ++t;
+        std::vector<double> invD(lv.n);
+        std::vector<int> lmask(lv.n);
+        for (int64_t i = 0; i < lv.n; ++i) {
+          invD[i] = 1.0 / res.D[i];
+          int inbox = 0;
+          int64_t jj;
+          for (int sl = 0; sl < NS; ++sl)
+            if (sl != C && in_box(i, sl, &jj)) inbox |= 1 << sl;
+          lmask[i] = inbox & ~res.earlier[i];
+        }
+        lv.lptr_host = res.level_ptr;
+        const int depth = int(res.level_ptr.size()) - 1;
+        const int big = h.opt.sweep_grid_rows > 0 ? h.opt.sweep_grid_rows : kGridLevel;
+        for (int l = 0; l < depth;) {
+          const int cnt = res.level_ptr[l + 1] - res.level_ptr[l];
+          if (cnt > big) {
+            lv.segs.push_back({l, l + 1, 1});
+            ++l;
+            continue;
+          }
+          int l1 = l + 1;
+          while (l1 < depth && res.level_ptr[l1 + 1] - res.level_ptr[l1] <= big) ++l1;
+          lv.segs.push_back({l, l1, 0});
+          l = l1;
+        }
+        SCHK(upload(h, &lv.sched, res.sched, st));
+        SCHK(upload(h, &lv.lptr, res.level_ptr, st));
+        SCHK(upload(h, &lv.Lv, res.L, st));
+        SCHK(upload(h, &lv.invD, invD, st));
+        SCHK(upload(h, &lv.emask, res.earlier, st));
+        SCHK(upload(h, &lv.lmask, lmask, st));
+        SingleXfer &xf = lv.xf;
+        for (int d = 0; d < 3; ++d) {
+          xf.mf[d] = xf.mc[d] = xf.R[d] = 1;
+          xf.pc[d] = xf.rf[d] = nullptr;
+          xf.pw[d] = xf.rw[d] = nullptr;
+        }
+        for (int d = 0; d < dim; ++d) {
+          Xfer1D x1 = xfer_1d(h, k, d, bp.a[d], bp.b[d]);
+          xf.mf[d] = x1.mf;
+          xf.mc[d] = x1.mc;
+          xf.R[d] = x1.R;
+          int *pc, *rf;
+          double *pw, *rw;
+          SCHK(upload(h, &pc, x1.pc, st));
+          SCHK(upload(h, &pw, x1.pw, st));
+          SCHK(upload(h, &rf, x1.rf, st));
+          SCHK(upload(h, &rw, x1.rw, st));
+          xf.pc[d] = pc;
+          xf.pw[d] = pw;
+          xf.rf[d] = rf;
+          xf.rw[d] = rw;
+        }
+        SCHK(hipStreamSynchronize(st));  // the host vectors above go out of scope
+      } else if (lv.n > 0) {
+        // the box's part of T_p (its interior vertices), inverted
+        if (lv.n > 40000) return LOR_EINVAL;
+        const int n = int(lv.n);
+        std::vector<double> A(size_t(n) * n, 0.0);
+        for (int64_t i = 0; i < lv.n; ++i) {
+          const int64_t g = grid_index(i);
+          int64_t jj;
+          for (int sl = 0; sl < NS; ++sl)
+            if (in_box(i, sl, &jj)) A[size_t(i) * n + jj] = hst[k][size_t(sl) * np + g];
+        }
+        if (n <= kHostInverse) {
+          if (!host_inverse(A, n)) return LOR_EPIVOT;
+          SCHK(upload(h, &lv.ainv, A, st));
+        } else {
+          SCHK(h.alloc(&lv.ainv, A.size()));
+          SCHK(hipMemcpyAsync(lv.ainv, A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice, st));
+          const int rc = coarse_inverse(n, lv.ainv, st);
+          if (rc != LOR_OK) return rc;
+        }
+        SCHK(hipStreamSynchronize(st));
+      }
+    }
+  }
+  // level vectors shared by the patches (applied one after another)
+  h.box_x.assign(L, nullptr);
+  h.box_b.assign(L, nullptr);
+  h.box_r.assign(L, nullptr);
+  const bool single = h.opt.patch_mode == LOR_PATCH_SINGLE;
+  for (int k = 0; k < L; ++k) {
+    if (maxn[k] <= 0) continue;
+    if (!(single && k == 0)) {  // B(1) reads r and writes z directly on level 0
+      SCHK(h.alloc(&h.box_x[k], size_t(maxn[k])));
+      SCHK(h.alloc(&h.box_b[k], size_t(maxn[k])));
+    }
+    SCHK(h.alloc(&h.box_r[k], size_t(maxn[k])));
+  }
+  for (BoxPatchDev &bp : h.boxes)
+    for (int k = 0; k < L; ++k) {
+      bp.lv[k].x = h.box_x[k];
+      bp.lv[k].b = h.box_b[k];
+      bp.lv[k].r = h.box_r[k];
+    }
+  if (h.opt.prolong_weights == LOR_PROLONG_POU && h.opt.patch_mode != LOR_PATCH_SINGLE) {
+    std::vector<double> w(count.size());
+    for (size_t i = 0; i < count.size(); ++i) w[i] = count[i] > 0.0 ? 1.0 / count[i] : 0.0;
+    SCHK(upload(h, &h.d_box_w, w, st));
+    SCHK(hipStreamSynchronize(st));
+  }
+  return LOR_OK;
+}
+
+namespace {
+
+int vcycle(lor_handle *h, BoxPatchDev &bp, int k, const double *b, double *x, const double *flag,
+           hipStream_t st) {
+  SingleLevelDev &lv = bp.lv[k];
+  if (lv.n <= 0) return LOR_OK;
+  if (k == h->L - 1) {
+    SCHK(launch_gemv(int(lv.n), lv.ainv, b, x, flag, st));
+    return LOR_OK;
+  }
+  const int dim = h->dim, s = int(h->kept[k].size()) - 1;
+  const int lng[3] = {h->n[0] * s + 1, h->n[1] * s + 1, dim == 3 ? h->n[2] * s + 1 : 1};
+  const double *A = h->d_stencil[k];
+  // pre-smoothing from zero: x = M^-1 b
+  SCHK(launch_single_sweep(dim, true, lv, b, x, flag, st));
+  SCHK(launch_single_sweep(dim, false, lv, x, x, flag, st));
+  SCHK(launch_single_residual(dim, A, h->npts[k], lng, lv.lo, lv.m, b, x, lv.r, flag, st));
+  SingleLevelDev &cv = bp.lv[k + 1];
+  if (cv.n > 0) {
+    SCHK(launch_single_transfer(dim, false, lv.xf, lv.r, cv.b, flag, st));
+    const int rc = vcycle(h, bp, k + 1, cv.b, cv.x, flag, st);
+    if (rc != LOR_OK) return rc;
+    SCHK(launch_single_transfer(dim, true, lv.xf, cv.x, x, flag, st));
+    SCHK(launch_single_residual(dim, A, h->npts[k], lng, lv.lo, lv.m, b, x, lv.r, flag, st));
+  }
+  // post-smoothing: x += M^-1 r (in place on r)
+  SCHK(launch_single_sweep(dim, true, lv, lv.r, lv.r, flag, st));
+  SCHK(launch_single_sweep(dim, false, lv, lv.r, lv.r, flag, st));
+  SCHK(launch_axpy1(x, lv.r, lv.n, flag, st));
+  return LOR_OK;
+}
+
+}  // namespace
+
+int apply_boxes(lor_handle *h, const double *r, double *z, const double *flag, hipStream_t st) {
+  if (h->boxes.empty()) return LOR_ESTATE;
+  if (h->opt.patch_mode == LOR_PATCH_SINGLE) {
+    // one box, the whole domain: level 0 is the L-vector
+    if (h->boxes[0].lv[0].n <= 0) return LOR_OK;
+    return vcycle(h, h->boxes[0], 0, r, z, flag, st);
+  }
+  for (BoxPatchDev &bp : h->boxes) {
+    SingleLevelDev &l0 = bp.lv[0];
+    if (l0.n <= 0) continue;
+    double *b0 = h->box_b[0], *x0 = h->box_x[0];
+    SCHK(launch_box_gather(h->dim, h->md, l0.lo, l0.m, r, b0, flag, st));
+    const int rc = vcycle(h, bp, 0, b0, x0, flag, st);
+    if (rc != LOR_OK) return rc;
+    SCHK(launch_box_scatter(h->dim, h->md, l0.lo, l0.m, x0, h->d_box_w, z, flag, st));
+  }
+  return LOR_OK;
+}

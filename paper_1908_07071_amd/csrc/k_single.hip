@@ -1,10 +1,13 @@
-// Kernels of the single-patch preconditioner B(1) (Section 4.1: one patch,
-// the whole domain): the element-structured V-cycle of Section 3.3 on the
-// global LOR level grids, with IC(0) smoothing in the chosen order and the
-// exact solve on T_p (a dense inverse applied by the coarse GEMV).
+// Kernels of the box-patch preconditioners: B(1) (Section 4.1: one patch,
+// the whole domain), B(n) (n overlapping subdomains) and vertex patches
+// enlarged for isotropic overlap (Section 4.5).  Each patch is a box of
+// elements; its V-cycle is the element-structured one of Section 3.3 on the
+// box's part of the LOR level grids, with IC(0) smoothing in the chosen
+// order and the exact solve on its part of T_p (a dense inverse applied by
+// the coarse GEMV).
 //
-// Every vector is a level's interior box (all level-grid points not on the
-// Dirichlet boundary, x fastest); at level 0 that is the L-vector itself.
+// Every vector is the points strictly inside a patch's box on one level
+// (x fastest); for B(1) at level 0 that is the L-vector itself.
 // The triangular sweeps follow the dependency levels of the elimination
 // order (rows of one level are independent): a run of small levels goes to
 // one workgroup that walks through them with a barrier between levels; a
@@ -35,14 +38,22 @@ __device__ __forceinline__ void sweep_row(int i, const double *__restrict__ Lv,
                                           const double *__restrict__ invD, const int *__restrict__ mask,
                                           const double *b, double *x, BoxDims bd) {
   constexpr int NS = DIM == 3 ? 27 : 9;
-  unsigned mk = unsigned(mask[i]);
+  const unsigned mk = unsigned(mask[i]);
   double acc = FWD ? b[i] : x[i] * invD[i];
   const double *li = Lv + int64_t(i) * NS;
-  while (mk) {
-    const int s = __builtin_ctz(mk);
-    mk &= mk - 1;
-    acc -= li[s] * x[nb_index<DIM>(i, s, bd)];
+  // every slot's factor value and neighbour value is loaded unconditionally
+  // (the row itself stands in for a neighbour outside the mask), so that all
+  // loads of a row are in flight together; the mask then selects the terms
+  double lv[NS], xv[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const bool on = (mk >> s) & 1u;
+    lv[s] = li[s];
+    xv[s] = x[on ? nb_index<DIM>(i, s, bd) : i];
   }
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+    if ((mk >> s) & 1u) acc -= lv[s] * xv[s];
   x[i] = acc;
 }
 
@@ -77,7 +88,7 @@ __global__ __launch_bounds__(256) void k_sweep_level(const int *__restrict__ sch
 // the whole level grid (lng points per direction, boundary points included)
 template <int DIM>
 __global__ __launch_bounds__(256) void k_box_residual(const double *__restrict__ stencil, int64_t npts,
-                                                      int lng0, int lng1, BoxDims bd,
+                                                      int lng0, int lng1, BoxDims lo, BoxDims bd,
                                                       const double *__restrict__ b,
                                                       const double *__restrict__ x,
                                                       double *__restrict__ r, const double *flag) {
@@ -87,7 +98,7 @@ __global__ __launch_bounds__(256) void k_box_residual(const double *__restrict__
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
     const int ix = int(i % bd.m0), iy = int((i / bd.m0) % bd.m1), iz = int(i / (int64_t(bd.m0) * bd.m1));
-    const int64_t g = (ix + 1) + int64_t(lng0) * ((iy + 1) + (DIM == 3 ? int64_t(lng1) * (iz + 1) : 0));
+    const int64_t g = (ix + lo.m0) + int64_t(lng0) * ((iy + lo.m1) + (DIM == 3 ? int64_t(lng1) * (iz + lo.m2) : 0));
     double acc = b[i];
     for (int s = 0; s < NS; ++s) {
       const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = DIM == 3 ? s / 9 - 1 : 0;
@@ -161,6 +172,26 @@ __global__ __launch_bounds__(256) void k_box_restrict(SingleXfer t, const double
   }
 }
 
+// level-0 box <-> L-vector (Dirichlet numbering: grid index minus one)
+template <int DIM, bool SCATTER>
+__global__ __launch_bounds__(256) void k_box_move(MeshDims md, BoxDims lo, BoxDims bd,
+                                                  const double *__restrict__ src,
+                                                  const double *__restrict__ w,
+                                                  double *__restrict__ dst, const double *flag) {
+  if (flag && flag[S_DONE] != 0.0) return;
+  const int64_t n = int64_t(bd.m0) * bd.m1 * bd.m2;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int ix = int(i % bd.m0), iy = int((i / bd.m0) % bd.m1), iz = int(i / (int64_t(bd.m0) * bd.m1));
+    const int64_t u = (ix + lo.m0 - 1) +
+                      int64_t(md.nu[0]) * ((iy + lo.m1 - 1) + (DIM == 3 ? int64_t(md.nu[1]) * (iz + lo.m2 - 1) : 0));
+    if (SCATTER)
+      dst[u] += w ? w[u] * src[i] : src[i];
+    else
+      dst[i] = src[u];
+  }
+}
+
 __global__ void k_axpy1(double *__restrict__ x, const double *__restrict__ y, int64_t n,
                         const double *flag) {
   if (flag && flag[S_DONE] != 0.0) return;
@@ -208,15 +239,37 @@ hipError_t launch_single_sweep(int dim, bool fwd, const SingleLevelDev &lv, cons
 }
 
 hipError_t launch_single_residual(int dim, const double *stencil, int64_t npts, const int *lng,
-                                  const int *m, const double *b, const double *x, double *r,
-                                  const double *flag, hipStream_t st) {
+                                  const int *lo, const int *m, const double *b, const double *x,
+                                  double *r, const double *flag, hipStream_t st) {
   const BoxDims bd{m[0], m[1], m[2]};
+  const BoxDims bl{lo[0], lo[1], lo[2]};
   const int64_t n = int64_t(m[0]) * m[1] * m[2];
   if (n <= 0) return hipSuccess;
   if (dim == 3)
-    k_box_residual<3><<<blocks_for(n, 256), 256, 0, st>>>(stencil, npts, lng[0], lng[1], bd, b, x, r, flag);
+    k_box_residual<3><<<blocks_for(n, 256), 256, 0, st>>>(stencil, npts, lng[0], lng[1], bl, bd, b, x, r, flag);
   else
-    k_box_residual<2><<<blocks_for(n, 256), 256, 0, st>>>(stencil, npts, lng[0], lng[1], bd, b, x, r, flag);
+    k_box_residual<2><<<blocks_for(n, 256), 256, 0, st>>>(stencil, npts, lng[0], lng[1], bl, bd, b, x, r, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_box_gather(int dim, const MeshDims &md, const int *lo, const int *m,
+                             const double *r, double *out, const double *flag, hipStream_t st) {
+  const BoxDims bd{m[0], m[1], m[2]}, bl{lo[0], lo[1], lo[2]};
+  const int64_t n = int64_t(m[0]) * m[1] * m[2];
+  if (n <= 0) return hipSuccess;
+  if (dim == 3) k_box_move<3, false><<<blocks_for(n, 256), 256, 0, st>>>(md, bl, bd, r, nullptr, out, flag);
+  else k_box_move<2, false><<<blocks_for(n, 256), 256, 0, st>>>(md, bl, bd, r, nullptr, out, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_box_scatter(int dim, const MeshDims &md, const int *lo, const int *m,
+                              const double *x, const double *w, double *z, const double *flag,
+                              hipStream_t st) {
+  const BoxDims bd{m[0], m[1], m[2]}, bl{lo[0], lo[1], lo[2]};
+  const int64_t n = int64_t(m[0]) * m[1] * m[2];
+  if (n <= 0) return hipSuccess;
+  if (dim == 3) k_box_move<3, true><<<blocks_for(n, 256), 256, 0, st>>>(md, bl, bd, x, w, z, flag);
+  else k_box_move<2, true><<<blocks_for(n, 256), 256, 0, st>>>(md, bl, bd, x, w, z, flag);
   return hipGetLastError();
 }
 

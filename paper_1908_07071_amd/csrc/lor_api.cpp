@@ -451,9 +451,13 @@ int setup_impl(lor_handle &h, hipStream_t st) {
     HIPCHK(hipMemcpyAsync(hst[k].data(), h.d_stencil[k], hst[k].size() * 8, hipMemcpyDeviceToHost, st));
   }
   HIPCHK(hipStreamSynchronize(st));
-  if (h.opt.patch_mode == LOR_PATCH_SINGLE) {
-    const int rc = build_single(h, hst, st);
+  if (box_mode(h.opt.patch_mode)) {
+    int rc = build_boxes(h, hst, st);
     if (rc != LOR_OK) return rc;
+    if (h.opt.patch_mode == LOR_PATCH_VERTEX_ISO) {
+      rc = build_coarse(h, hst[0], st);
+      if (rc != LOR_OK) return rc;
+    }
     HIPCHK(hipStreamSynchronize(st));
     h.has_prec = true;
     return LOR_OK;
@@ -531,7 +535,7 @@ int apply_P_cg(lor_handle *h, Work &w, const double *r, double *z, const double 
                hipStream_t st) {
   if (h->opt.patch_mode == LOR_PATCH_SINGLE) {
     Span sp(h, LOR_T_PATCH, st);
-    return apply_single(h, r, z, flag, st);
+    return apply_boxes(h, r, z, flag, st);
   }
   if (h->nc > 0) {
     Span sp(h, LOR_T_COARSE, st);
@@ -542,6 +546,7 @@ int apply_P_cg(lor_handle *h, Work &w, const double *r, double *z, const double 
     HIPCHK(launch_fill(z, h->ncg, 0.0, st));
   }
   Span sp(h, LOR_T_PATCH, st);
+  if (box_mode(h->opt.patch_mode)) return apply_boxes(h, r, z, flag, st);
   if (h->nn && h->nn_mode == LOR_NN_REPLACE) return nn_apply_patches(h->nn, r, z, flag, st);
   if (h->nn && h->nn_mode == LOR_NN_WARMSTART) return nn_apply_patches_warm(h->nn, r, z, flag, st);
   HIPCHK(launch_patch_vcycle(h->pa, h->J, r, z, flag, st));
@@ -810,12 +815,13 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const l
       return LOR_EINVAL;
     if (opt->prolong_weights != LOR_PROLONG_SUM && opt->prolong_weights != LOR_PROLONG_POU)
       return LOR_EINVAL;
-    if (opt->patch_mode != LOR_PATCH_VERTEX && opt->patch_mode != LOR_PATCH_SINGLE)
-      return LOR_EINVAL;
-    if (opt->patch_mode == LOR_PATCH_SINGLE && opt->precision != LOR_PREC_FP64)
-      return invalid("the single-patch preconditioner runs in float64 only", __LINE__);
+    if (opt->patch_mode != LOR_PATCH_VERTEX && !box_mode(opt->patch_mode)) return LOR_EINVAL;
+    if (box_mode(opt->patch_mode) && opt->precision != LOR_PREC_FP64)
+      return invalid("the box-patch preconditioners run in float64 only", __LINE__);
+    if (opt->patch_mode == LOR_PATCH_SLABS && (opt->nslabs < 1 || opt->nslabs > mesh->n[0]))
+      return invalid("nslabs must lie in 1 .. n[0]", __LINE__);
     if (opt->sweep_grid_rows < 0) return LOR_EINVAL;
-    for (int t = 0; t < 5; ++t)
+    for (int t = 0; t < 4; ++t)
       if (opt->reserved[t] != 0) return LOR_EINVAL;
   } else {
     lor_default_options(&h->opt);
@@ -929,11 +935,16 @@ int lor_bind_workspace(lor_handle_t *h, void *dev_ptr, size_t bytes, void *strea
     set(w.part2), set(w.rc), set(w.xc), set(w.yE), set(w.fo), set(w.rL), set(w.zL);
     for (int k = 0; k < kMaxLevels; ++k) set(h->pa.stencil[k]);
     set(h->pa.xfer), set(h->pa.fac), set(h->pa.fac_off);
-    for (SingleLevelDev &lv : h->single) {
-      set(lv.sched), set(lv.lptr), set(lv.Lv), set(lv.invD), set(lv.emask), set(lv.lmask);
-      set(lv.x), set(lv.b), set(lv.r), set(lv.ainv);
-      for (int d = 0; d < 3; ++d) set(lv.xf.pc[d]), set(lv.xf.pw[d]), set(lv.xf.rf[d]), set(lv.xf.rw[d]);
-    }
+    for (BoxPatchDev &bp : h->boxes)
+      for (SingleLevelDev &lv : bp.lv) {
+        set(lv.sched), set(lv.lptr), set(lv.Lv), set(lv.invD), set(lv.emask), set(lv.lmask);
+        set(lv.x), set(lv.b), set(lv.r), set(lv.ainv);
+        for (int d = 0; d < 3; ++d) set(lv.xf.pc[d]), set(lv.xf.pw[d]), set(lv.xf.rf[d]), set(lv.xf.rw[d]);
+      }
+    for (double *&v : h->box_x) set(v);
+    for (double *&v : h->box_b) set(v);
+    for (double *&v : h->box_r) set(v);
+    set(h->d_box_w);
   };
   apply(false);  // dry run: resolve every pointer before anything changes
   if (!ok) return LOR_ESTATE;

@@ -14,6 +14,12 @@ using namespace lor;
 
 struct lor_nn;
 
+// One box patch: elements [a_d, b_d) and the data of each level.
+struct BoxPatchDev {
+  int a[3] = {0, 0, 0}, b[3] = {1, 1, 1};
+  std::vector<SingleLevelDev> lv;
+};
+
 // Device workspace of one solve.  The handle holds one; a batched solve holds
 // one per (problem, right-hand side) pair so that the pairs of one problem can
 // run concurrently.
@@ -72,7 +78,9 @@ struct lor_handle {
   int nn_mode = 0;
   bool capturing = false;  // no event timing while a graph is captured
   PatchArgs pa{};
-  std::vector<SingleLevelDev> single;  // LOR_PATCH_SINGLE: B(1) levels
+  std::vector<BoxPatchDev> boxes;  // box-patch modes: every patch's levels
+  std::vector<double *> box_x, box_b, box_r;  // level vectors shared by the box patches
+  double *d_box_w = nullptr;                  // partition-of-unity weights of the box patches
   // host copies for parity export
   std::vector<int32_t> order_all, order_off, sched_all, sched_off;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -127,10 +135,14 @@ int apply_P_scratch(lor_handle *h, double *scratch, size_t cap, const double *r,
 // of the no-allocation entry point on the current device (noalloc.hip).
 int noalloc_register_device(int device);
 
-// Single-patch preconditioner B(1) (single.cpp): set-up from the host copies
-// of the level stencils, and z = B(1) r.
-int build_single(lor_handle &h, const std::vector<std::vector<double>> &hst, hipStream_t st);
-int apply_single(lor_handle *h, const double *r, double *z, const double *flag, hipStream_t st);
+// Box-patch preconditioners (box_patch.cpp): B(1), B(n) slabs, isotropic
+// vertex patches.  Set-up from the host copies of the level stencils, and
+// the patch part of z = B r (B(1): all of it; the others add into z).
+int build_boxes(lor_handle &h, const std::vector<std::vector<double>> &hst, hipStream_t st);
+int apply_boxes(lor_handle *h, const double *r, double *z, const double *flag, hipStream_t st);
+inline bool box_mode(int m) {
+  return m == LOR_PATCH_SINGLE || m == LOR_PATCH_SLABS || m == LOR_PATCH_VERTEX_ISO;
+}
 
 // Patches of the Schwarz preconditioner through the attached network:
 // z += sum_j R_j^T s_j net(R_j r / s_j) (nn_api.cpp).

@@ -238,6 +238,7 @@ struct SingleSeg {
   int l0, l1, grid;
 };
 struct SingleLevelDev {
+  int lo[3];                   // first level-grid index of the box's points
   int m[3];                    // interior box extents
   int64_t n;                   // rows
   int *sched = nullptr;        // rows by dependency level
@@ -248,15 +249,22 @@ struct SingleLevelDev {
   double *invD = nullptr;      // 1 / pivot
   int *emask = nullptr;        // slots of earlier in-box neighbours
   int *lmask = nullptr;        // slots of later in-box neighbours
-  double *x = nullptr, *b = nullptr, *r = nullptr;  // level vectors (level 0: r only)
+  double *x = nullptr, *b = nullptr, *r = nullptr;  // level vectors (shared by the boxes)
   SingleXfer xf{};             // to the next coarser level
   double *ainv = nullptr;      // coarsest level: dense inverse
 };
 hipError_t launch_single_sweep(int dim, bool fwd, const SingleLevelDev &lv, const double *b, double *x,
                                const double *flag, hipStream_t st);
 hipError_t launch_single_residual(int dim, const double *stencil, int64_t npts, const int *lng,
-                                  const int *m, const double *b, const double *x, double *r,
-                                  const double *flag, hipStream_t st);
+                                  const int *lo, const int *m, const double *b, const double *x,
+                                  double *r, const double *flag, hipStream_t st);
+// level-0 box of a patch <-> L-vector: out = r[box] (gather) or
+// z[box] += w[box] * x (scatter, w may be nullptr for weight 1)
+hipError_t launch_box_gather(int dim, const MeshDims &md, const int *lo, const int *m,
+                             const double *r, double *out, const double *flag, hipStream_t st);
+hipError_t launch_box_scatter(int dim, const MeshDims &md, const int *lo, const int *m,
+                              const double *x, const double *w, double *z, const double *flag,
+                              hipStream_t st);
 hipError_t launch_single_transfer(int dim, bool prolong, const SingleXfer &t, const double *in,
                                   double *out, const double *flag, hipStream_t st);
 hipError_t launch_axpy1(double *x, const double *y, int64_t n, const double *flag, hipStream_t st);

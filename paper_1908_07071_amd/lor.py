@@ -24,7 +24,7 @@ LOR_BC_DIRICHLET, LOR_BC_NEUMANN = 0, 1
 LOR_PREC_FP64, LOR_PREC_MIXED = 0, 1
 LOR_ORD_MDF, LOR_ORD_NATURAL, LOR_ORD_RCM = 0, 1, 2
 LOR_PROLONG_SUM, LOR_PROLONG_POU = 0, 1
-LOR_PATCH_VERTEX, LOR_PATCH_SINGLE = 0, 1
+LOR_PATCH_VERTEX, LOR_PATCH_SINGLE, LOR_PATCH_SLABS, LOR_PATCH_VERTEX_ISO = 0, 1, 2, 3
 LOR_MAP_LDOF, LOR_MAP_ORDER, LOR_MAP_ORDER_OFFSET = 0, 1, 2
 LOR_MAP_SCHEDULE, LOR_MAP_SCHEDULE_OFFSET, LOR_MAP_E2L = 3, 4, 5
 
@@ -58,7 +58,7 @@ class lor_mesh_t(C.Structure):
 class lor_options_t(C.Structure):
     _fields_ = [("precision", C.c_int), ("ordering", C.c_int), ("flexible", C.c_int),
                 ("nthreads", C.c_int), ("prolong_weights", C.c_int), ("patch_mode", C.c_int),
-                ("sweep_grid_rows", C.c_int), ("reserved", C.c_int * 5)]
+                ("sweep_grid_rows", C.c_int), ("nslabs", C.c_int), ("reserved", C.c_int * 4)]
 
 
 class lor_solve_info_t(C.Structure):
