@@ -221,7 +221,7 @@ hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r,
 hipError_t launch_patch_vcycle_warm(const PatchArgs &pa, int first, int count, const double *r,
                                     double *z, const float *y, const double *scale,
                                     const double *flag, hipStream_t st);
-// ---- single-patch preconditioner B(1) (k_single.hip, single.cpp)
+// ---- box-patch preconditioners: B(1), B(n), isotropic vertex patches (k_single.hip, box_patch.cpp)
 // 1D transfer tables between the interior boxes of levels k and k+1: for
 // every fine index its two parents (coarse index or -1) and weights, for
 // every coarse index R[d] (fine index or -1, weight) pairs.
