@@ -146,7 +146,15 @@ typedef struct {
                           device, runs of smaller levels by one workgroup
                           (a barrier between levels); 0 = 512             */
   int nslabs;          /* LOR_PATCH_SLABS: number of subdomains, 1..n[0]    */
-  int reserved[4];     /* must be zero                                      */
+  int deterministic;   /* 1: the vertex patches' corrections are added
+                          without atomics, one vertex-parity class of
+                          patches (disjoint boxes) per launch, classes in a
+                          fixed order: B r is bit-reproducible (and so is
+                          the whole solve where the operator is: 3D with
+                          4 <= p <= 7), at about four times the patch
+                          kernel's time.  The box-patch modes are always
+                          bit-reproducible.  No patch network then.         */
+  int reserved[3];     /* must be zero                                      */
 } lor_options_t;
 
 typedef struct {
@@ -353,7 +361,8 @@ int lor_nn_train_step(lor_nn_t *nn, const float *X_dev, const float *T_dev, int 
                       double *loss, void *stream);
 /* Use nn in h's preconditioner (LOR_NN_REPLACE or LOR_NN_WARMSTART) or not
  * (LOR_NN_OFF, nn may be NULL).  The network must have been created for h.
- * LOR_NN_REPLACE needs LOR_PROLONG_SUM (LOR_ESTATE otherwise).
+ * LOR_NN_REPLACE needs LOR_PROLONG_SUM, and either mode vertex patches
+ * without `deterministic` (LOR_ESTATE otherwise).
  * Either mode makes the preconditioner nonlinear: lor_pcg_solve then runs
  * flexible CG.  The first warm-start attach allocates the predictions of
  * every patch, J (2p-1)^3 floats and J doubles (LOR_ENOMEM on failure). */

@@ -478,7 +478,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   if (flag && flag[S_DONE] != 0.0) return;
   extern __shared__ __align__(16) char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
-  const int j = jfirst + int(blockIdx.x);
+  int j = jfirst + int(blockIdx.x);
+  if (pa.color >= 0) {
+    // the patches of one vertex-parity class: their level-0 boxes are
+    // disjoint, so their corrections can be added without atomics
+    int nvc[3], c[3];
+    for (int d = 0; d < 3; ++d) {
+      c[d] = (pa.color >> d) & 1;
+      nvc[d] = d < DIM ? (pa.nv[d] - c[d] + 1) / 2 : 1;
+    }
+    const int i = int(blockIdx.x);
+    const int vx = 2 * (i % nvc[0]) + c[0], vy = 2 * ((i / nvc[0]) % nvc[1]) + c[1],
+              vz = DIM == 3 ? 2 * (i / (nvc[0] * nvc[1])) + c[2] : 0;
+    j = vx + pa.nv[0] * (vy + pa.nv[1] * vz);
+  }
   const int L = pa.nlev;
   const MeshDims &md = pa.md;
   const int v[3] = {j % pa.nv[0], (j / pa.nv[0]) % pa.nv[1],
@@ -700,7 +713,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       } else {
         for (int i = threadIdx.x; i < b0.n; i += 64, w.step()) {
           const double c = double(X0[i]);
-          unsafeAtomicAdd(z + walk_uidx<DIM>(b0, w, md), pa.pou ? c * pou_weight<DIM>(b0, w, md.p) : c);
+          const double v = pa.pou ? c * pou_weight<DIM>(b0, w, md.p) : c;
+          double *zu = z + walk_uidx<DIM>(b0, w, md);
+          if (pa.plain)
+            *zu += v;
+          else
+            unsafeAtomicAdd(zu, v);
         }
       }
     }
@@ -751,6 +769,27 @@ hipError_t prepare_patch_vcycle(const PatchArgs &pa) {
 hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r, double *z,
                                const double *flag, hipStream_t st, float *dense,
                                const double *dscale) {
+  if (pa.plain && !dense) {
+    // one launch per vertex-parity class, in class order
+    const int nclass = pa.md.dim == 3 ? 8 : 4;
+    for (int color = 0; color < nclass; ++color) {
+      PatchArgs pc = pa;
+      pc.plain = 0;
+      pc.color = color;
+      int cnt = 1;
+      for (int d = 0; d < pa.md.dim; ++d) cnt *= (pa.nv[d] - ((color >> d) & 1) + 1) / 2;
+      pc.plain = 1;
+      hipError_t e;
+      if (pa.fp32)
+        e = pa.md.dim == 3 ? launch_t<3, float, float, false>(pc, cnt, r, z, flag, nullptr, nullptr, nullptr, 0, st)
+                           : launch_t<2, float, float, false>(pc, cnt, r, z, flag, nullptr, nullptr, nullptr, 0, st);
+      else
+        e = pa.md.dim == 3 ? launch_t<3, double, double, false>(pc, cnt, r, z, flag, nullptr, nullptr, nullptr, 0, st)
+                           : launch_t<2, double, double, false>(pc, cnt, r, z, flag, nullptr, nullptr, nullptr, 0, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   if (pa.fp32) {
     if (pa.md.dim == 3)
       return launch_t<3, float, float, false>(pa, npatch, r, z, flag, dense, dscale, nullptr, 0, st);
@@ -764,7 +803,7 @@ hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r,
 hipError_t launch_patch_vcycle_warm(const PatchArgs &pa, int first, int count, const double *r,
                                     double *z, const float *y, const double *scale,
                                     const double *flag, hipStream_t st) {
-  if (pa.md.dim != 3 || !y || !scale || first < 0 || count < 0) return hipErrorInvalidValue;
+  if (pa.md.dim != 3 || !y || !scale || first < 0 || count < 0 || pa.plain) return hipErrorInvalidValue;
   if (pa.fp32)
     return launch_t<3, float, float, true>(pa, count, r, z, flag, nullptr, scale, y, first, st);
   return launch_t<3, double, double, true>(pa, count, r, z, flag, nullptr, scale, y, first, st);

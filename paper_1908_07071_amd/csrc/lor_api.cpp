@@ -370,6 +370,8 @@ int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hi
   pa.lds_total = tot;
   pa.fp32 = mixed ? 1 : 0;
   pa.pou = h.opt.prolong_weights == LOR_PROLONG_POU ? 1 : 0;
+  pa.plain = h.opt.deterministic ? 1 : 0;
+  pa.color = -1;
   if (size_t(tot) * (mixed ? sizeof(float) : sizeof(double)) > 160 * 1024)
     return invalid("patch vectors exceed the 160 KiB LDS of a CU (polynomial degree too high)", __LINE__);
   HIPCHK(prepare_patch_vcycle(pa));
@@ -821,7 +823,8 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const l
     if (opt->patch_mode == LOR_PATCH_SLABS && (opt->nslabs < 1 || opt->nslabs > mesh->n[0]))
       return invalid("nslabs must lie in 1 .. n[0]", __LINE__);
     if (opt->sweep_grid_rows < 0) return LOR_EINVAL;
-    for (int t = 0; t < 4; ++t)
+    if (opt->deterministic != 0 && opt->deterministic != 1) return LOR_EINVAL;
+    for (int t = 0; t < 3; ++t)
       if (opt->reserved[t] != 0) return LOR_EINVAL;
   } else {
     lor_default_options(&h->opt);

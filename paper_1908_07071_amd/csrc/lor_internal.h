@@ -55,6 +55,9 @@ struct PatchArgs {
   int lds_total;                     // LDS values per patch (largest patch)
   int fp32;                          // 1: stencils, factors and patch vectors in float
   int pou;                           // 1: corrections scaled by 1/c(i) (partition of unity)
+  int plain;                         // 1: corrections added without atomics, one
+                                     //    vertex-parity class of patches per launch
+  int color;                         // parity class of this launch, -1: every patch
 };
 
 // Sweep block: the data of one ILU(0) triangular sweep (forward or backward)

@@ -313,7 +313,8 @@ int lor_nn_attach(lor_handle_t *h, lor_nn_t *nn, int mode) {
   if (!h || (mode != LOR_NN_OFF && mode != LOR_NN_REPLACE && mode != LOR_NN_WARMSTART))
     return LOR_EINVAL;
   if (mode != LOR_NN_OFF && (!nn || nn->h != h)) return LOR_EINVAL;
-  if (mode != LOR_NN_OFF && h->opt.patch_mode != LOR_PATCH_VERTEX) return LOR_ESTATE;
+  if (mode != LOR_NN_OFF && (h->opt.patch_mode != LOR_PATCH_VERTEX || h->opt.deterministic))
+    return LOR_ESTATE;
   // the network's own scatter adds corrections unweighted
   if (mode == LOR_NN_REPLACE && h->opt.prolong_weights != LOR_PROLONG_SUM) return LOR_ESTATE;
   if (mode == LOR_NN_WARMSTART && !nn->yall) {

@@ -58,7 +58,8 @@ class lor_mesh_t(C.Structure):
 class lor_options_t(C.Structure):
     _fields_ = [("precision", C.c_int), ("ordering", C.c_int), ("flexible", C.c_int),
                 ("nthreads", C.c_int), ("prolong_weights", C.c_int), ("patch_mode", C.c_int),
-                ("sweep_grid_rows", C.c_int), ("nslabs", C.c_int), ("reserved", C.c_int * 4)]
+                ("sweep_grid_rows", C.c_int), ("nslabs", C.c_int),
+                ("deterministic", C.c_int), ("reserved", C.c_int * 3)]
 
 
 class lor_solve_info_t(C.Structure):

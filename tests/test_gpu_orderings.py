@@ -126,3 +126,47 @@ def test_pou_weights(case, precision, L, torch_dev):
         assert np.linalg.norm(rin - K @ x.cpu().numpy()) <= 1.05e-10 * np.linalg.norm(rin)
     finally:
         L.lor_free(h)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", [CASES[1], (3, (3, 2, 3), 4, 0.1, 34), (2, (4, 3), 5, 0.1, 35)],
+                         ids=_ids)
+def test_deterministic_patch_sum(case, precision, L, torch_dev):
+    """`deterministic`: B r bit-identical from call to call and between two
+    handles, equal to the atomic sum within rounding, and (3D, 4 <= p <= 7,
+    where the operator is also free of atomics) solves bit-identical."""
+    torch = torch_dev
+    dim, n, p = case[0], list(case[1]), case[2]
+    print("case", case, precision, flush=True)
+    V, mesh = _mesh(case)
+    opts = []
+    for det in (1, 1, 0):
+        o = L.lor_default_options()
+        o.deterministic = det
+        if precision == "mixed":
+            o.precision = L.LOR_PREC_MIXED
+        opts.append(o)
+    hs = [L.lor_setup(dim, n, V, p, options=o) for o in opts]
+    try:
+        N = L.lor_ndofs(hs[0])
+        r = torch.tensor(inputs.gaussian_rhs(N, 11), device="cuda")
+        zs = []
+        for h in hs + [hs[0]]:
+            z = torch.empty_like(r)
+            L.lor_apply_P(h, r, z)
+            torch.cuda.synchronize()
+            zs.append(z.cpu().numpy())
+        assert np.array_equal(zs[0], zs[1]) and np.array_equal(zs[0], zs[3])
+        # both sums run in float64 (a float32 patch solve's correction is
+        # widened first): only the order of the additions differs
+        assert np.abs(zs[0] - zs[2]).max() <= 1e-12 * np.abs(zs[2]).max()
+        if dim == 3 and 4 <= p <= 7:
+            xs = []
+            for h in hs[:2]:
+                x = torch.zeros_like(r)
+                info = L.lor_pcg_solve(h, r, x, rtol=1e-10, maxit=500)
+                xs.append((info.iters, x.cpu().numpy()))
+            assert xs[0][0] == xs[1][0] and np.array_equal(xs[0][1], xs[1][1])
+    finally:
+        for h in hs:
+            L.lor_free(h)
