@@ -47,11 +47,25 @@ def _local_multi(p: int, dim: int) -> np.ndarray:
 
 
 def element_geometry(mesh, p: int, e):
-    """Jacobian, determinant and inverse at the (p+1)^d GLL nodes of element e."""
+    """Jacobian, determinant and inverse at the (p+1)^d GLL nodes of element e.
+
+    Straight-sided elements: the Q1 map of the element's vertices.  Curved
+    (isoparametric) elements: J[q][r][s] = sum_j X_j[r] d phi_j/d xi_s (x_q)
+    from the element's own GLL node coordinates X_j."""
     x, w = _gll.gll(p)
     dim = mesh.dim
-    corners = mesh.element_corners(e)
     loc = _local_multi(p, dim)
+    if mesh.nodes is not None:
+        if p != mesh.nodes_p:
+            raise ValueError("a curved mesh carries its nodes for one degree")
+        Xe = mesh.nodes[element_global_nodes(mesh, p, e)]
+        Gs = _tensor_ref_grad(p, dim)
+        Js = np.stack([np.stack([Gs[s_] @ Xe[:, r] for s_ in range(dim)], axis=1) for r in range(dim)], axis=1)
+        dets = np.linalg.det(Js)
+        Jinv = np.linalg.inv(Js)
+        wq = np.prod(w[loc], axis=1)
+        return Js, dets, Jinv, wq
+    corners = mesh.element_corners(e)
     Js = np.array([_mesh.map_jacobian(corners, [x[q[i]] for i in range(dim)]) for q in loc])
     dets = np.linalg.det(Js)
     Jinv = np.linalg.inv(Js)
@@ -473,12 +487,32 @@ def dg_boundary_mask(mesh, p: int) -> np.ndarray:
     return np.tile(m, mesh.nel)
 
 
+def _interp_derivative(nodes: np.ndarray, pts: np.ndarray) -> np.ndarray:
+    """(len(pts), len(nodes)) derivatives of the Lagrange basis of `nodes` at
+    `pts` (the product rule on l_j(t) = prod_{m != j} (t - x_m)/(x_j - x_m))."""
+    n = len(nodes)
+    out = np.zeros((len(pts), n))
+    for j in range(n):
+        den = np.prod([nodes[j] - nodes[m] for m in range(n) if m != j])
+        for k in range(n):
+            if k == j:
+                continue
+            term = np.ones(len(pts))
+            for m in range(n):
+                if m != j and m != k:
+                    term = term * (pts - nodes[m])
+            out[:, j] += term
+        out[:, j] /= den
+    return out
+
+
 def l2_error_cg(mesh, p: int, u_grid: np.ndarray, u_exact, nq: int | None = None) -> float:
     """||u_h - u||_{L2} with u_h given at every GLL grid node (x fastest).
 
     Uses nq-point Gauss-Legendre quadrature per direction (default p + 3) on
     each element; u_h is evaluated by Lagrange interpolation of its nodal
-    values, points are mapped with the element's Q1 map.
+    values, points are mapped with the element's Q1 map (or, on a curved mesh,
+    the interpolant of its GLL node coordinates).
     """
     dim = mesh.dim
     nq = nq or p + 3
@@ -488,17 +522,33 @@ def l2_error_cg(mesh, p: int, u_grid: np.ndarray, u_exact, nq: int | None = None
     B = _gll.lagrange_eval_matrix(x, g)  # (nq, p+1)
     qloc = np.indices([nq] * dim).reshape(dim, -1, order="F").T
     err2 = 0.0
+    Bt = B
+    for _ in range(dim - 1):
+        Bt = np.kron(B, Bt)
+    if mesh.nodes is not None:
+        # derivative tables of the nodal interpolant at the Gauss points
+        Dq = _interp_derivative(x, g)
+        Bd = []
+        for s_ in range(dim):
+            f = [Dq if t == s_ else B for t in range(dim)]
+            M = f[dim - 1]
+            for t in range(dim - 2, -1, -1):
+                M = np.kron(M, f[t])
+            Bd.append(M)
     for e in mesh.elements():
-        corners = mesh.element_corners(e)
         ue = u_grid[element_global_nodes(mesh, p, e)]
-        # tensor interpolation: kron(B_z, B_y, B_x) acting on x-fastest values
-        Bt = B
-        for _ in range(dim - 1):
-            Bt = np.kron(B, Bt)
         uh = Bt @ ue
-        pts = [g[qloc[:, i]] for i in range(dim)]
-        X = np.stack(_mesh.map_point(corners[:, :, None] * np.ones(len(qloc)), pts), axis=1)
-        dets = np.array([np.linalg.det(_mesh.map_jacobian(corners, [g[q[i]] for i in range(dim)])) for q in qloc])
+        if mesh.nodes is not None:
+            Xe = mesh.nodes[element_global_nodes(mesh, p, e)]
+            X = Bt @ Xe
+            J = np.stack([np.stack([Bd[s_] @ Xe[:, r] for s_ in range(dim)], axis=1) for r in range(dim)], axis=1)
+            dets = np.linalg.det(J)
+        else:
+            corners = mesh.element_corners(e)
+            pts = [g[qloc[:, i]] for i in range(dim)]
+            X = np.stack(_mesh.map_point(corners[:, :, None] * np.ones(len(qloc)), pts), axis=1)
+            dets = np.array([np.linalg.det(_mesh.map_jacobian(corners, [g[q[i]] for i in range(dim)]))
+                             for q in qloc])
         w = np.prod(wg[qloc], axis=1)
         err2 += float(np.sum(w * dets * (uh - u_exact(X)) ** 2))
     return np.sqrt(err2)

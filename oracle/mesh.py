@@ -28,6 +28,11 @@ class Mesh:
     dim: int
     n: tuple  # elements per direction
     vertices: np.ndarray  # (prod(n+1), dim)
+    # curved (isoparametric) geometry: the coordinates of every global GLL
+    # node for degree nodes_p, x fastest; element e is then the image of
+    # [0,1]^d under the degree-nodes_p interpolant of its own nodes
+    nodes: np.ndarray | None = None
+    nodes_p: int | None = None
 
     @property
     def nel(self) -> int:
@@ -60,12 +65,16 @@ class Mesh:
             yield tuple(e)
 
 
-def make_mesh(dim: int, n, vertices: np.ndarray) -> Mesh:
+def make_mesh(dim: int, n, vertices: np.ndarray, nodes=None, nodes_p=None) -> Mesh:
     n = tuple([int(n)] * dim) if np.isscalar(n) else tuple(int(v) for v in n)
     vertices = np.asarray(vertices, dtype=np.float64)
     if vertices.shape != (int(np.prod([v + 1 for v in n])), dim):
         raise ValueError("vertex array has the wrong shape")
-    return Mesh(dim, n, vertices)
+    if nodes is not None:
+        nodes = np.asarray(nodes, dtype=np.float64)
+        if nodes.shape != (int(np.prod([v * nodes_p + 1 for v in n])), dim):
+            raise ValueError("node array has the wrong shape")
+    return Mesh(dim, n, vertices, nodes, nodes_p)
 
 
 def shape_q1(dim: int, xi) -> list:
@@ -127,6 +136,10 @@ def global_node_coords(mesh: Mesh, ref_nodes: np.ndarray, p: int) -> np.ndarray:
     neighbour (the element min(g // p, n - 1) in each direction).
     """
     dim = mesh.dim
+    if mesh.nodes is not None:
+        if p != mesh.nodes_p:
+            raise ValueError("a curved mesh carries its nodes for one degree")
+        return mesh.nodes.copy()
     ng = [mesh.n[i] * p + 1 for i in range(dim)]
     gidx = np.indices(ng).reshape(dim, -1, order="F")  # (dim, num), x fastest
     elem = [np.minimum(gidx[i] // p, mesh.n[i] - 1) for i in range(dim)]

@@ -135,3 +135,58 @@ def strip_vertices(n: int, aspect: float, strip_rows: int = 2, dim: int = 2) -> 
     axes[1] = y
     grids = np.meshgrid(*axes, indexing="ij")
     return np.stack([g.reshape(-1, order="F") for g in grids], axis=1).copy()
+
+
+def curved_nodes(dim: int, n, p: int, amp: float = 0.15, perturb: float = 0.0, seed=None) -> np.ndarray:
+    """GLL-grid node coordinates of a block of [0,1]^dim with curved elements:
+    the straight block (optionally with perturbed vertices, as in
+    structured_vertices) at the 1D GLL points of [0,1] given by `gll_x`
+    below, then moved by the smooth map x_i -> x_i + amp * 16 * prod_j
+    x_j (1 - x_j) (zero on the boundary, so the domain stays the unit cube
+    while element faces inside bend).  Nodes lexicographic with x fastest,
+    n_i p + 1 per direction.  The interior vertices of the block are the
+    images of the straight vertices, so structured_vertices(...) with the
+    same map applied gives the matching vertex array (curved_vertices)."""
+    n = [int(n)] * dim if np.isscalar(n) else [int(v) for v in n]
+    x = gll_x(p)
+    V = structured_vertices(dim, n, perturb, seed)
+    # straight nodes: each element's Q1 interpolation of its vertices
+    ng = [n[i] * p + 1 for i in range(dim)]
+    g = np.indices(ng).reshape(dim, -1, order="F")
+    e = [np.minimum(g[i] // p, n[i] - 1) for i in range(dim)]
+    t = [x[g[i] - p * e[i]] for i in range(dim)]
+    out = np.zeros((g.shape[1], dim))
+    for c in range(2 ** dim):
+        vidx = np.zeros(g.shape[1], dtype=np.int64)
+        stride = 1
+        wgt = np.ones(g.shape[1])
+        for i in range(dim):
+            b = (c >> i) & 1
+            vidx += (e[i] + b) * stride
+            stride *= n[i] + 1
+            wgt = wgt * (t[i] if b else 1.0 - t[i])
+        out += wgt[:, None] * V[vidx]
+    return _bend(out, amp)
+
+
+def curved_vertices(dim: int, n, amp: float = 0.15, perturb: float = 0.0, seed=None) -> np.ndarray:
+    """The vertices of the block of curved_nodes (the same bending map)."""
+    return _bend(structured_vertices(dim, n, perturb, seed), amp)
+
+
+def _bend(X: np.ndarray, amp: float) -> np.ndarray:
+    bump = 16.0 * np.prod(X * (1.0 - X), axis=1)
+    return X + amp * bump[:, None]
+
+
+def gll_x(p: int) -> np.ndarray:
+    """The p + 1 Gauss-Lobatto points of [0,1] in float64 (roots of the
+    derivative of the Legendre polynomial, from numpy), for placing curved
+    mesh nodes; the library and the oracle use their own correctly rounded
+    points for the discretization itself."""
+    if p == 1:
+        return np.array([0.0, 1.0])
+    c = np.zeros(p + 1)
+    c[p] = 1.0
+    r = np.polynomial.legendre.Legendre(c).deriv().roots()
+    return np.concatenate([[0.0], (np.sort(r.real) + 1.0) / 2.0, [1.0]])
