@@ -847,9 +847,36 @@ def main():
         print(f"[bench] 32^3 p=6 mixed: {rec32['iters']} it, {rec32['ms_per_solve']:.1f} ms/solve, "
               f"{rec32['dofs_per_s'] / 1e6:.2f} M DOF/s, setup {rec32['setup_s']:.1f} s",
               file=sys.stderr, flush=True)
+        # the benchmark mesh with bent (isoparametric) elements
+        Vc = inputs.curved_vertices(3, 16, 0.15, 0.1, 1)
+        Xc = inputs.curved_nodes(3, 16, 6, 0.15, 0.1, 1)
+        hc = L.lor_setup(3, 16, Vc, 6, options=opt32, nodes=Xc)
+        Nc = L.lor_ndofs(hc)
+        fc = torch.tensor(inputs.manufactured_f(L.lor_dof_coords(hc, 3)), device="cuda:0")
+        bc_ = torch.empty_like(fc)
+        L.lor_assemble_rhs(hc, fc, bc_)
+        xc = torch.zeros_like(bc_)
+        infc, msc = solve_timed(L, torch, hc, bc_, xc, args.rtol, 2)
+        L.lor_free(hc)
+        out["cube_16_p6_curved_mixed"] = {"N": Nc, "iters": infc.iters, "ms_per_solve": msc,
+                                          "dofs_per_s": Nc / (msc * 1e-3),
+                                          "status": STATUS_NAMES.get(infc.status, str(infc.status)),
+                                          "rel_res_true": infc.rel_res_true,
+                                          "workload": "16^3, p=6, elements bent by x + 0.15*16*prod x(1-x) "
+                                                      "(isoparametric, GLL node coordinates), vertices "
+                                                      "perturbed <=10% h (seed 1), mixed FCG"}
+        print(f"[bench] 16^3 p=6 curved mixed: {infc.iters} it, {msc:.1f} ms/solve", file=sys.stderr,
+              flush=True)
         out["single_patch"] = single_patch_measure(L, torch, args.rtol)
         out["coefficients"] = coefficient_measure(L, torch, args.rtol)
         out["strip"] = strip_measure(L, torch, args.rtol)
+        # a smaller instance of the batched workload (16 problems, 2 right
+        # sides each) so that the default line carries a batched measurement
+        bm = batch_measure(L, torch, 16, 2, args.rtol, "mixed")
+        out["batch16"] = {"value": bm["value"], "unit": bm["unit"], "ms": bm["ms_per_step"],
+                          "sequential_value": bm["sequential_value"],
+                          "speedup_vs_sequential": bm["speedup_vs_sequential"],
+                          "config": bm["config"]}
         out["p_sweep"] = p_sweep(L, torch, dim, n, (2, 4, 6, 8), args.rtol, 2)
         out["orderings"] = ordering_variants(L, torch, dim, n, p, args.rtol, 3,
                                              [o for o in args.orderings.split(",") if o])

@@ -81,6 +81,15 @@ typedef struct {
    * by the mean of b over the sub-element's 2^d corners (GLL nodes of the
    * element holding it).  Copied during lor_setup. */
   const double *coef;
+  /* Curved (isoparametric) elements, HOST, NULL for straight ones: the
+   * coordinates of every GLL grid node for the degree p of lor_setup,
+   * (n0 p+1)(n1 p+1)(n2 p+1) x dim float64, x fastest.  Element e is then
+   * the image of [0,1]^d under the degree-p interpolant of its own nodes
+   * (the geometric factors come from the derivatives of that interpolant at
+   * the GLL nodes), and the LOR sub-elements have these nodes as corners.
+   * vertex_xyz must hold the same points at the vertices (the nodes with
+   * every index a multiple of p).  CG only.  Copied during lor_setup. */
+  const double *node_xyz;
 } lor_mesh_t;
 
 #define LOR_PREC_FP64   0   /* every step in float64 */
@@ -228,7 +237,8 @@ int lor_bind_workspace(lor_handle_t *h, void *dev_ptr, size_t bytes, void *strea
  * each direction.  DG: each element's own map at its GLL nodes. */
 int lor_dof_coords(const lor_handle_t *h, double *host_xyz);
 
-/* Coordinates of every element's GLL nodes (each element's own map), HOST
+/* Coordinates of every element's GLL nodes (each element's own map, or its
+ * own nodes on a curved mesh), HOST
  * output of n_el (p+1)^d x dim float64 in the E-vector layout: where a
  * variable coefficient is evaluated (lor_mesh_t.coef).  Uses a temporary
  * device buffer. */

@@ -163,6 +163,72 @@ __global__ void k_geom(MeshDims md, const double *__restrict__ verts,
   }
 }
 
+// Curved (isoparametric) elements: the geometric factors from the GLL node
+// coordinates (SoA [dim][grid point]).  J[r][s] at node q of element e is the
+// derivative along reference direction s of the interpolant of the element's
+// node coordinates X_r: sum_a D[q_s][a] X_r(node q with its s-index set to a).
+template <int DIM>
+__global__ void k_geom_nodal(MeshDims md, const double *__restrict__ coords,
+                             const double *__restrict__ D, const double *__restrict__ gllw,
+                             const double *__restrict__ coef, double *__restrict__ G,
+                             double *__restrict__ wdet, int *bad) {
+  const int Q = md.p + 1;
+  const int nq = DIM == 3 ? Q * Q * Q : Q * Q;
+  const int64_t nel = int64_t(md.n[0]) * md.n[1] * (DIM == 3 ? md.n[2] : 1);
+  const int ncomp = DIM == 3 ? 6 : 3;
+  const int64_t fnp = int64_t(md.ng[0]) * md.ng[1] * md.ng[2];
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < nel * nq;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t e = t / nq;
+    const int q = int(t % nq);
+    const int e3[3] = {int(e % md.n[0]), int((e / md.n[0]) % md.n[1]),
+                       DIM == 3 ? int(e / (int64_t(md.n[0]) * md.n[1])) : 0};
+    const int qi[3] = {q % Q, (q / Q) % Q, DIM == 3 ? q / (Q * Q) : 0};
+    double w = 1.0;
+    for (int i = 0; i < DIM; ++i) w *= gllw[qi[i]];
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int sd = 0; sd < DIM; ++sd)
+      for (int a = 0; a < Q; ++a) {
+        int g[3];
+        for (int i = 0; i < 3; ++i) g[i] = e3[i] * md.p + (i == sd ? a : qi[i]);
+        const int64_t gi = g[0] + int64_t(md.ng[0]) * (g[1] + (DIM == 3 ? int64_t(md.ng[1]) * g[2] : 0));
+        const double dq = D[qi[sd] * Q + a];
+        for (int r = 0; r < DIM; ++r) J[r][sd] += dq * coords[r * fnp + gi];
+      }
+    double det, A[3][3];
+    if (DIM == 3) {
+      A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+      A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+      A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+      A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+      A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+      A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+      A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+      A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+      A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+    } else {
+      A[0][0] = J[1][1];
+      A[0][1] = -J[0][1];
+      A[1][0] = -J[1][0];
+      A[1][1] = J[0][0];
+      det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    }
+    if (!(det > 0.0)) atomicOr(bad, 1);
+    const double f = coef ? (w / det) * coef[e * nq + q] : w / det;
+    double *Ge = G + e * ncomp * nq;
+    int comp = 0;
+    for (int r = 0; r < DIM; ++r)
+      for (int c2 = r; c2 < DIM; ++c2) {
+        double acc = 0.0;
+        for (int sd = 0; sd < DIM; ++sd) acc += A[r][sd] * A[c2][sd];
+        Ge[comp * nq + q] = f * acc;
+        ++comp;
+      }
+    wdet[e * nq + q] = w * det;
+  }
+}
+
 // LOR stencil of one level of the element-structured hierarchy.  For grid
 // point g the 3^d slots are filled, in the order of the cells S = g - 1 + s
 // (s = s_x + 2 s_y + 4 s_z ascending), with the Q1 stiffness entries
@@ -532,6 +598,19 @@ hipError_t launch_geom_cg(const MeshDims &md, const double *verts, const double 
     k_geom<3><<<grid_for(tot, 256), 256, 0, st>>>(md, verts, gllx, gllw, coef, G, wdet, bad);
   else
     k_geom<2><<<grid_for(tot, 256), 256, 0, st>>>(md, verts, gllx, gllw, coef, G, wdet, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_geom_nodal(const MeshDims &md, const double *coords, const double *D,
+                             const double *gllw, const double *coef, double *G, double *wdet, int *bad,
+                             hipStream_t st) {
+  const int Q = md.p + 1;
+  const int64_t nel = int64_t(md.n[0]) * md.n[1] * (md.dim == 3 ? md.n[2] : 1);
+  const int64_t tot = nel * (md.dim == 3 ? Q * Q * Q : Q * Q);
+  if (md.dim == 3)
+    k_geom_nodal<3><<<grid_for(tot, 256), 256, 0, st>>>(md, coords, D, gllw, coef, G, wdet, bad);
+  else
+    k_geom_nodal<2><<<grid_for(tot, 256), 256, 0, st>>>(md, coords, D, gllw, coef, G, wdet, bad);
   return hipGetLastError();
 }
 

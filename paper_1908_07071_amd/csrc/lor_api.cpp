@@ -409,7 +409,17 @@ int setup_impl(lor_handle &h, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(h.d_gllw, h.gllw.data(), Q * 8, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(h.d_D, h.D.data(), Q * Q * 8, hipMemcpyHostToDevice, st));
   HIPCHK(h.alloc(&h.d_coords, size_t(h.nfine) * dim));
-  HIPCHK(launch_node_coords(md, h.d_verts, h.d_gllx, h.d_coords, st));
+  if (h.nodes.empty()) {
+    HIPCHK(launch_node_coords(md, h.d_verts, h.d_gllx, h.d_coords, st));
+  } else {
+    // curved elements: the caller's node coordinates (x fastest, dim per
+    // node) into the SoA layout
+    std::vector<double> soa(size_t(h.nfine) * dim);
+    for (int64_t g = 0; g < h.nfine; ++g)
+      for (int r = 0; r < dim; ++r) soa[size_t(r) * h.nfine + g] = h.nodes[size_t(g) * dim + r];
+    HIPCHK(hipMemcpyAsync(h.d_coords, soa.data(), soa.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   const int ncomp = dim == 3 ? 6 : 3;
   HIPCHK(h.alloc(&h.d_G, size_t(h.nel) * ncomp * nq));
   HIPCHK(h.alloc(&h.d_wdet, size_t(h.nel) * nq));
@@ -420,7 +430,10 @@ int setup_impl(lor_handle &h, hipStream_t st) {
     HIPCHK(h.alloc(&h.d_coef, h.coef.size()));
     HIPCHK(hipMemcpyAsync(h.d_coef, h.coef.data(), h.coef.size() * 8, hipMemcpyHostToDevice, st));
   }
-  HIPCHK(launch_geom_cg(md, h.d_verts, h.d_gllx, h.d_gllw, h.d_coef, h.d_G, h.d_wdet, bad, st));
+  if (h.nodes.empty())
+    HIPCHK(launch_geom_cg(md, h.d_verts, h.d_gllx, h.d_gllw, h.d_coef, h.d_G, h.d_wdet, bad, st));
+  else
+    HIPCHK(launch_geom_nodal(md, h.d_coords, h.d_D, h.d_gllw, h.d_coef, h.d_G, h.d_wdet, bad, st));
   int hb = 0;
   HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -832,6 +845,14 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const l
   h->verts.assign(mesh->vertex_xyz, mesh->vertex_xyz + nv * mesh->dim);
   for (double v : h->verts)
     if (!std::isfinite(v)) return LOR_EINVAL;
+  if (mesh->node_xyz) {
+    if (method != LOR_CG) return invalid("curved elements need the CG discretization", __LINE__);
+    int64_t nn = 1;
+    for (int d = 0; d < mesh->dim; ++d) nn *= int64_t(mesh->n[d]) * p + 1;
+    h->nodes.assign(mesh->node_xyz, mesh->node_xyz + nn * mesh->dim);
+    for (double v : h->nodes)
+      if (!std::isfinite(v)) return LOR_EINVAL;
+  }
   if (mesh->coef) {
     if (method != LOR_CG) return invalid("a variable coefficient needs the CG discretization", __LINE__);
     int64_t ne = 1, nq = 1;
@@ -967,6 +988,21 @@ int lor_bind_workspace(lor_handle_t *h, void *dev_ptr, size_t bytes, void *strea
 int lor_element_coords(const lor_handle_t *h, double *host_xyz) {
   if (!h || !host_xyz) return LOR_EINVAL;
   const int Q = h->p + 1;
+  if (!h->nodes.empty()) {
+    // curved elements: each element's own GLL nodes
+    const int dim = h->dim, nq = dim == 3 ? Q * Q * Q : Q * Q;
+    const int ng0 = h->md.ng[0], ng1 = h->md.ng[1];
+    for (int64_t e = 0; e < h->nel; ++e) {
+      const int e3[3] = {int(e % h->n[0]), int((e / h->n[0]) % h->n[1]), int(e / (int64_t(h->n[0]) * h->n[1]))};
+      for (int q = 0; q < nq; ++q) {
+        const int g[3] = {e3[0] * h->p + q % Q, e3[1] * h->p + (q / Q) % Q,
+                          dim == 3 ? e3[2] * h->p + q / (Q * Q) : 0};
+        const int64_t gi = g[0] + int64_t(ng0) * (g[1] + int64_t(ng1) * g[2]);
+        for (int r = 0; r < dim; ++r) host_xyz[(e * nq + q) * dim + r] = h->nodes[size_t(gi) * dim + r];
+      }
+    }
+    return LOR_OK;
+  }
   const size_t nb = size_t(h->nel) * (h->dim == 3 ? Q * Q * Q : Q * Q) * h->dim * sizeof(double);
   double *tmp = nullptr;
   if (hipMalloc(&tmp, nb) != hipSuccess) return LOR_EHIP;

@@ -42,6 +42,7 @@ struct lor_handle {
   MeshDims md{};
   std::vector<double> verts, gllx, gllw, D;
   std::vector<double> coef;  // b at the elements' GLL nodes (empty: b = 1)
+  std::vector<double> nodes; // curved elements: GLL-grid node coordinates (empty: Q1 maps)
   std::vector<std::vector<int>> kept;
   int L = 1;
   int64_t ndofs = 0, nfine = 0, nel = 0;

@@ -159,6 +159,10 @@ hipError_t launch_node_coords(const MeshDims &md, const double *verts, const dou
 hipError_t launch_geom_cg(const MeshDims &md, const double *verts, const double *gllx,
                           const double *gllw, const double *coef, double *G, double *wdet, int *bad,
                           hipStream_t st);
+// curved elements: the same factors from the GLL node coordinates (SoA)
+hipError_t launch_geom_nodal(const MeshDims &md, const double *coords, const double *D,
+                             const double *gllw, const double *coef, double *G, double *wdet, int *bad,
+                             hipStream_t st);
 hipError_t launch_lor_stencil(const MeshDims &md, int s, const int *kept_fine_idx,
                               const double *fine_coords, double g0, double g1, const double *coef,
                               double *stencil, hipStream_t st);

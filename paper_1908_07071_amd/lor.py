@@ -52,7 +52,7 @@ class LorError(RuntimeError):
 
 class lor_mesh_t(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("vertex_xyz", C.POINTER(C.c_double)),
-                ("bc", C.c_int), ("coef", C.POINTER(C.c_double))]
+                ("bc", C.c_int), ("coef", C.POINTER(C.c_double)), ("node_xyz", C.POINTER(C.c_double))]
 
 
 class lor_options_t(C.Structure):
@@ -204,9 +204,12 @@ def lor_default_options():
 
 
 def lor_setup(dim: int, n, vertices: np.ndarray, p: int, method: int = LOR_CG, penalty: float = 0.0,
-              options: lor_options_t | None = None, bc: int = LOR_BC_DIRICHLET, stream=None, coef=None):
+              options: lor_options_t | None = None, bc: int = LOR_BC_DIRICHLET, stream=None, coef=None,
+              nodes=None):
     """Returns an opaque handle (ctypes void pointer).  coef: None or b at the
-    elements' GLL nodes, n_el x (p+1)^dim values (E-vector layout)."""
+    elements' GLL nodes, n_el x (p+1)^dim values (E-vector layout).  nodes:
+    None or the GLL-grid node coordinates of a curved mesh, ((n_i p + 1)...)
+    x dim."""
     n = [int(n)] * dim if np.isscalar(n) else [int(v) for v in n]
     verts = np.ascontiguousarray(vertices, dtype=np.float64)
     mesh = lor_mesh_t()
@@ -220,6 +223,11 @@ def lor_setup(dim: int, n, vertices: np.ndarray, p: int, method: int = LOR_CG, p
         if cf.size != int(np.prod(n)) * (p + 1) ** dim:
             raise ValueError("coef needs n_el * (p+1)^dim values")
         mesh.coef = _dptr(cf)
+    if nodes is not None:
+        nd = np.ascontiguousarray(nodes, dtype=np.float64)
+        if nd.shape != (int(np.prod([v * p + 1 for v in n])), dim):
+            raise ValueError("nodes needs (prod(n_i p + 1), dim) values")
+        mesh.node_xyz = _dptr(nd)
     h = C.c_void_p()
     opt = C.byref(options) if options is not None else None
     rc = _lib.lor_setup(C.byref(mesh), int(p), int(method), float(penalty), opt, _stream(stream), C.byref(h))
