@@ -725,6 +725,9 @@ def main():
     N = L.lor_ndofs(h)
     # the device data moves into a torch-owned buffer (torch's caching
     # allocator owns the solver's device memory)
+    order_info = L.lor_launch_order(h)
+    print(f"[bench] patch launch order {order_info[0]} (autotuned: vertex order {order_info[1]:.3f} ms, "
+          f"buckets {order_info[2]:.3f} ms)", file=sys.stderr, flush=True)
     dev_bytes = L.lor_workspace_bytes(h)
     ws = torch.empty(dev_bytes, dtype=torch.uint8, device="cuda:0")
     L.lor_bind_workspace(h, ws)
@@ -816,6 +819,7 @@ def main():
             "status": STATUS_NAMES.get(info.status, str(info.status)),
             "precision": args.precision, "setup_s": round(setup_s, 3),
             "device_bytes": dev_bytes, "device_memory": "caller-owned torch buffer (lor_bind_workspace)",
+            "patch_launch_order": dict(zip(("used", "ms_vertex_order", "ms_buckets"), order_info)),
         },
         "fp64_preconditioner": fp64,
         "operator_gdofs": N / t_apply / 1e9,

@@ -163,8 +163,21 @@ typedef struct {
                           4 <= p <= 7), at about four times the patch
                           kernel's time.  The box-patch modes are always
                           bit-reproducible.  No patch network then.         */
-  int reserved[3];     /* must be zero                                      */
+  int launch_order;    /* LOR_LAUNCH_*: the order in which the vertex-patch
+                          kernel's workgroups take the patches            */
+  int reserved[2];     /* must be zero                                      */
 } lor_options_t;
+
+/* Launch order of the vertex-patch kernel.  LOR_LAUNCH_AUTO (the default)
+ * times both orders at set-up (a few launches on the handle's workspace)
+ * and keeps the faster; lor_launch_order reports the choice. */
+#define LOR_LAUNCH_AUTO    0
+#define LOR_LAUNCH_VERTEX  1  /* vertex order                                  */
+#define LOR_LAUNCH_BUCKETS 2  /* patches by decreasing work (rows over all
+                                 smoothed levels), vertex order among equals:
+                                 interior, face, edge and corner patches, so
+                                 the largest start first and the smallest fill
+                                 the launch's last round                      */
 
 typedef struct {
   int    iters;        /* CG iterations performed (all restarts together)  */
@@ -208,6 +221,11 @@ const char *lor_last_error_detail(void);
  * LOR_EHIP.  On error *out is NULL and nothing is leaked. */
 int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty,
               const lor_options_t *opt, void *stream, lor_handle_t **out);
+
+/* The launch order the handle uses (LOR_LAUNCH_VERTEX or _BUCKETS) and,
+ * after an autotuned set-up, the measured milliseconds per patch launch in
+ * each order (0 otherwise); either pointer may be NULL. */
+int lor_launch_order(const lor_handle_t *h, int *order, double *ms_vertex, double *ms_buckets);
 
 /* Number of unknowns: the L-vector length for CG, n_el (p+1)^d for DG. */
 int lor_ndofs(const lor_handle_t *h, int64_t *n);

@@ -479,6 +479,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   extern __shared__ __align__(16) char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
   int j = jfirst + int(blockIdx.x);
+  if (!WARM && pa.perm) j = pa.perm[j];
   if (pa.color >= 0) {
     // the patches of one vertex-parity class: their level-0 boxes are
     // disjoint, so their corrections can be added without atomics
@@ -776,6 +777,7 @@ hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r,
       PatchArgs pc = pa;
       pc.plain = 0;
       pc.color = color;
+      pc.perm = nullptr;
       int cnt = 1;
       for (int d = 0; d < pa.md.dim; ++d) cnt *= (pa.nv[d] - ((color >> d) & 1) + 1) / 2;
       pc.plain = 1;
@@ -804,9 +806,11 @@ hipError_t launch_patch_vcycle_warm(const PatchArgs &pa, int first, int count, c
                                     double *z, const float *y, const double *scale,
                                     const double *flag, hipStream_t st) {
   if (pa.md.dim != 3 || !y || !scale || first < 0 || count < 0 || pa.plain) return hipErrorInvalidValue;
+  PatchArgs pw = pa;
+  pw.perm = nullptr;  // predictions and scales are indexed by block
   if (pa.fp32)
-    return launch_t<3, float, float, true>(pa, count, r, z, flag, nullptr, scale, y, first, st);
-  return launch_t<3, double, double, true>(pa, count, r, z, flag, nullptr, scale, y, first, st);
+    return launch_t<3, float, float, true>(pw, count, r, z, flag, nullptr, scale, y, first, st);
+  return launch_t<3, double, double, true>(pw, count, r, z, flag, nullptr, scale, y, first, st);
 }
 
 }  // namespace lor

@@ -372,6 +372,22 @@ int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hi
   pa.pou = h.opt.prolong_weights == LOR_PROLONG_POU ? 1 : 0;
   pa.plain = h.opt.deterministic ? 1 : 0;
   pa.color = -1;
+  pa.perm = nullptr;
+  // patch buckets: patches by decreasing work (rows over all smoothed levels;
+  // interior patches, then face, edge and corner ones), so that the large
+  // patches start in the first round of the launch and the small ones fill
+  // its tail
+  {
+    std::vector<int64_t> work(h.J, 0);
+    for (int j = 0; j < h.J; ++j)
+      for (int k = 0; k < nf; ++k) work[j] += patch_box(h, j, k).n;
+    std::vector<int> perm(h.J);
+    for (int j = 0; j < h.J; ++j) perm[j] = j;
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return work[a] > work[b]; });
+    HIPCHK(h.alloc(&h.d_perm, size_t(std::max(h.J, 1))));
+    HIPCHK(hipMemcpyAsync(h.d_perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   if (size_t(tot) * (mixed ? sizeof(float) : sizeof(double)) > 160 * 1024)
     return invalid("patch vectors exceed the 160 KiB LDS of a CU (polynomial degree too high)", __LINE__);
   HIPCHK(prepare_patch_vcycle(pa));
@@ -764,6 +780,55 @@ int pcg_status(const lor_handle *h, const Work &w, double rtol, double t_solve, 
   return status;
 }
 
+// Launch-order autotuner of the vertex-patch kernel: vertex order against
+// patches by decreasing work (LOR_LAUNCH_AUTO), timed with HIP events over a
+// few launches on the handle's workspace; the faster order is kept.
+int tune_launch_order(lor_handle &h, hipStream_t st) {
+  h.tune_ms[0] = h.tune_ms[1] = 0.0;
+  if (!h.has_prec || box_mode(h.opt.patch_mode) || h.opt.deterministic || h.J <= 0) return LOR_OK;
+  const int mode = h.opt.launch_order;
+  if (mode == LOR_LAUNCH_VERTEX) {
+    h.pa.perm = nullptr;
+    h.order_used = LOR_LAUNCH_VERTEX;
+    return LOR_OK;
+  }
+  if (mode == LOR_LAUNCH_BUCKETS) {
+    h.pa.perm = h.d_perm;
+    h.order_used = LOR_LAUNCH_BUCKETS;
+    return LOR_OK;
+  }
+  const int64_t N = h.ncg;
+  HIPCHK(launch_fill(h.w.r, h.ndofs, 1.0, st));
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  double best[2] = {0.0, 0.0};
+  hipError_t e = hipSuccess;
+  for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)
+    for (int o = 0; o < 2 && e == hipSuccess; ++o) {
+      h.pa.perm = o ? h.d_perm : nullptr;
+      const double *rr = h.w.r;  // ones
+      e = launch_fill(h.w.z, N, 0.0, st);
+      if (e == hipSuccess) e = launch_patch_vcycle(h.pa, h.J, rr, h.w.z, nullptr, st);  // warm
+      if (e == hipSuccess) e = hipEventRecord(a, st);
+      for (int t = 0; t < 3 && e == hipSuccess; ++t) e = launch_patch_vcycle(h.pa, h.J, rr, h.w.z, nullptr, st);
+      if (e == hipSuccess) e = hipEventRecord(b, st);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (rep == 1) best[o] = ms / 3.0;
+    }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  HIPCHK(e);
+  h.tune_ms[0] = best[0];
+  h.tune_ms[1] = best[1];
+  const bool buckets = best[1] < best[0];
+  h.pa.perm = buckets ? h.d_perm : nullptr;
+  h.order_used = buckets ? LOR_LAUNCH_BUCKETS : LOR_LAUNCH_VERTEX;
+  return LOR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -837,7 +902,8 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const l
       return invalid("nslabs must lie in 1 .. n[0]", __LINE__);
     if (opt->sweep_grid_rows < 0) return LOR_EINVAL;
     if (opt->deterministic != 0 && opt->deterministic != 1) return LOR_EINVAL;
-    for (int t = 0; t < 3; ++t)
+    if (opt->launch_order < LOR_LAUNCH_AUTO || opt->launch_order > LOR_LAUNCH_BUCKETS) return LOR_EINVAL;
+    for (int t = 0; t < 2; ++t)
       if (opt->reserved[t] != 0) return LOR_EINVAL;
   } else {
     lor_default_options(&h->opt);
@@ -876,8 +942,18 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const l
   if (rc != LOR_OK) return rc;
   rc = work_alloc(*h, h->w, h->allocs, h->bytes, &h->alloc_size);
   if (rc != LOR_OK) return rc;
+  rc = tune_launch_order(*h, st);
+  if (rc != LOR_OK) return rc;
   h->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = h.release();
+  return LOR_OK;
+}
+
+int lor_launch_order(const lor_handle_t *h, int *order, double *ms_vertex, double *ms_buckets) {
+  if (!h || !order) return LOR_EINVAL;
+  *order = h->order_used;
+  if (ms_vertex) *ms_vertex = h->tune_ms[0];
+  if (ms_buckets) *ms_buckets = h->tune_ms[1];
   return LOR_OK;
 }
 
@@ -958,7 +1034,7 @@ int lor_bind_workspace(lor_handle_t *h, void *dev_ptr, size_t bytes, void *strea
     set(w.r), set(w.z), set(w.p), set(w.q), set(w.rold), set(w.tmp), set(w.scal), set(w.part);
     set(w.part2), set(w.rc), set(w.xc), set(w.yE), set(w.fo), set(w.rL), set(w.zL);
     for (int k = 0; k < kMaxLevels; ++k) set(h->pa.stencil[k]);
-    set(h->pa.xfer), set(h->pa.fac), set(h->pa.fac_off);
+    set(h->pa.xfer), set(h->pa.fac), set(h->pa.fac_off), set(h->pa.perm), set(h->d_perm);
     for (BoxPatchDev &bp : h->boxes)
       for (SingleLevelDev &lv : bp.lv) {
         set(lv.sched), set(lv.lptr), set(lv.Lv), set(lv.invD), set(lv.emask), set(lv.lmask);

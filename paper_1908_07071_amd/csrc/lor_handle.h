@@ -73,6 +73,9 @@ struct lor_handle {
   double *d_A0inv = nullptr;
   double *d_fg = nullptr, *d_dinv = nullptr;
   double *d_coef = nullptr;
+  int *d_perm = nullptr;       // patches by decreasing work (launch buckets)
+  int order_used = 0;          // LOR_LAUNCH_VERTEX or LOR_LAUNCH_BUCKETS
+  double tune_ms[2] = {0, 0};  // autotuner: patch launch in vertex order, in buckets
   int npart = 0;
   Work w;                  // workspace of lor_pcg_solve / lor_apply_*
   lor_nn *nn = nullptr;    // patch network used instead of the V-cycles (LOR_NN_REPLACE)

@@ -58,6 +58,8 @@ struct PatchArgs {
   int plain;                         // 1: corrections added without atomics, one
                                      //    vertex-parity class of patches per launch
   int color;                         // parity class of this launch, -1: every patch
+  const int *perm;                   // launch order: block b runs patch perm[b] (nullptr:
+                                     //    vertex order)
 };
 
 // Sweep block: the data of one ILU(0) triangular sweep (forward or backward)

@@ -25,6 +25,7 @@ LOR_PREC_FP64, LOR_PREC_MIXED = 0, 1
 LOR_ORD_MDF, LOR_ORD_NATURAL, LOR_ORD_RCM = 0, 1, 2
 LOR_PROLONG_SUM, LOR_PROLONG_POU = 0, 1
 LOR_PATCH_VERTEX, LOR_PATCH_SINGLE, LOR_PATCH_SLABS, LOR_PATCH_VERTEX_ISO = 0, 1, 2, 3
+LOR_LAUNCH_AUTO, LOR_LAUNCH_VERTEX, LOR_LAUNCH_BUCKETS = 0, 1, 2
 LOR_MAP_LDOF, LOR_MAP_ORDER, LOR_MAP_ORDER_OFFSET = 0, 1, 2
 LOR_MAP_SCHEDULE, LOR_MAP_SCHEDULE_OFFSET, LOR_MAP_E2L = 3, 4, 5
 
@@ -36,7 +37,7 @@ EXPORTED = [
     "lor_nn_param_count", "lor_nn_create", "lor_nn_get_params", "lor_nn_shape", "lor_nn_patch_data",
     "lor_nn_forward", "lor_nn_gradients", "lor_nn_train_step", "lor_nn_attach", "lor_nn_free",
     "lor_bf16_gemm", "lor_apply_P_noalloc", "lor_noalloc_scratch_bytes", "lor_workspace_bytes",
-    "lor_bind_workspace", "lor_element_coords",
+    "lor_bind_workspace", "lor_element_coords", "lor_launch_order",
 ]
 LOR_NN_OFF, LOR_NN_REPLACE, LOR_NN_WARMSTART = 0, 1, 2
 LOR_T_APPLY_A, LOR_T_PATCH, LOR_T_COARSE = 0, 1, 2
@@ -59,7 +60,7 @@ class lor_options_t(C.Structure):
     _fields_ = [("precision", C.c_int), ("ordering", C.c_int), ("flexible", C.c_int),
                 ("nthreads", C.c_int), ("prolong_weights", C.c_int), ("patch_mode", C.c_int),
                 ("sweep_grid_rows", C.c_int), ("nslabs", C.c_int),
-                ("deterministic", C.c_int), ("reserved", C.c_int * 3)]
+                ("deterministic", C.c_int), ("launch_order", C.c_int), ("reserved", C.c_int * 2)]
 
 
 class lor_solve_info_t(C.Structure):
@@ -86,6 +87,7 @@ def _load():
         "lor_device_bytes": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
         "lor_workspace_bytes": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
         "lor_element_coords": (C.c_int, [vp, dp]),
+        "lor_launch_order": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "lor_bind_workspace": (C.c_int, [vp, vp, C.c_size_t, vp]),
         "lor_dof_coords": (C.c_int, [vp, dp]),
         "lor_assemble_rhs": (C.c_int, [vp, vp, vp, vp]),
@@ -233,6 +235,13 @@ def lor_setup(dim: int, n, vertices: np.ndarray, p: int, method: int = LOR_CG, p
     rc = _lib.lor_setup(C.byref(mesh), int(p), int(method), float(penalty), opt, _stream(stream), C.byref(h))
     _check(rc, "lor_setup")
     return h
+
+
+def lor_launch_order(h):
+    """(order used, ms per patch launch in vertex order, in buckets)."""
+    o, a, b = C.c_int(), C.c_double(), C.c_double()
+    _check(_lib.lor_launch_order(h, C.byref(o), C.byref(a), C.byref(b)), "lor_launch_order")
+    return o.value, a.value, b.value
 
 
 def lor_ndofs(h) -> int:

@@ -170,3 +170,39 @@ def test_deterministic_patch_sum(case, precision, L, torch_dev):
     finally:
         for h in hs:
             L.lor_free(h)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_launch_orders_agree(precision, L, torch_dev):
+    """Vertex order and patch buckets (largest first) give the same B r up to
+    the order of the float64 additions; the autotuned set-up reports both
+    timings and uses the faster order."""
+    torch = torch_dev
+    case = (3, (4, 3, 3), 4, 0.1, 36)
+    dim, n, p = case[0], list(case[1]), case[2]
+    V, mesh = _mesh(case)
+    zs, hs = [], []
+    try:
+        for order in (L.LOR_LAUNCH_VERTEX, L.LOR_LAUNCH_BUCKETS, L.LOR_LAUNCH_AUTO):
+            o = L.lor_default_options()
+            o.launch_order = order
+            if precision == "mixed":
+                o.precision = L.LOR_PREC_MIXED
+            hs.append(L.lor_setup(dim, n, V, p, options=o))
+            N = L.lor_ndofs(hs[-1])
+            r = torch.tensor(inputs.gaussian_rhs(N, 12), device="cuda")
+            z = torch.empty_like(r)
+            L.lor_apply_P(hs[-1], r, z)
+            torch.cuda.synchronize()
+            zs.append(z.cpu().numpy())
+        assert L.lor_launch_order(hs[0])[0] == L.LOR_LAUNCH_VERTEX
+        assert L.lor_launch_order(hs[1])[0] == L.LOR_LAUNCH_BUCKETS
+        used, t_v, t_b = L.lor_launch_order(hs[2])
+        print("autotuned order", used, "ms vertex", t_v, "ms buckets", t_b, flush=True)
+        assert t_v > 0 and t_b > 0
+        assert used == (L.LOR_LAUNCH_BUCKETS if t_b < t_v else L.LOR_LAUNCH_VERTEX)
+        for z in zs[1:]:
+            assert np.abs(z - zs[0]).max() <= 1e-12 * np.abs(zs[0]).max()
+    finally:
+        for h in hs:
+            L.lor_free(h)
