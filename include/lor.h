@@ -165,8 +165,20 @@ typedef struct {
                           bit-reproducible.  No patch network then.         */
   int launch_order;    /* LOR_LAUNCH_*: the order in which the vertex-patch
                           kernel's workgroups take the patches            */
-  int reserved[2];     /* must be zero                                      */
+  int operator_geometry; /* LOR_GEOM_*                                      */
+  int reserved[1];     /* must be zero                                      */
 } lor_options_t;
+
+/* Geometric factors of the operator.  LOR_GEOM_STORED (default): computed
+ * once at set-up and streamed by every application (48 bytes per element
+ * node).  LOR_GEOM_ONFLY: in 3D CG with straight elements, b = 1 and
+ * 4 <= p <= 7 the operator recomputes G = w|J| J^-1 J^-T at every node from
+ * the element's vertices instead, and G is not stored (ignored otherwise):
+ * less memory, but measured slower (16^3, p = 6: 33 us against 23 us for
+ * the element kernel; equal at 32^3), as the kernel is not bound by the
+ * stream of G. */
+#define LOR_GEOM_STORED 0
+#define LOR_GEOM_ONFLY  1
 
 /* Launch order of the vertex-patch kernel.  LOR_LAUNCH_AUTO (the default)
  * times both orders at set-up (a few launches on the handle's workspace)

@@ -235,12 +235,17 @@ __global__ __launch_bounds__(256) void k_apply_cg3(MeshDims md, const double *G,
 // with one coalesced access per wavefront and array; the three flux
 // components go through LDS for the transposed contractions.  Same results
 // as the column kernel up to the order of the floating-point sums.
-template <int Q, bool DG>
+//
+// GEO: the geometric factors are recomputed at each node from the element's
+// 8 vertices (the same trilinear map and formulas as the set-up kernel that
+// stores them) instead of being streamed: 48 bytes per node less to read and
+// to hold, for about 200 float64 operations more per node.
+template <int Q, bool DG, bool GEO = false>
 __global__ __launch_bounds__(Q * 64) __attribute__((amdgpu_waves_per_eu(7)))
 void k_apply_pw3(MeshDims md, const double *__restrict__ G, const double *__restrict__ Dg,
                  const double *__restrict__ x, double *__restrict__ y,
                  double *__restrict__ partials, const double *flag,
-                 const double *__restrict__ fo, double *__restrict__ yE) {
+                 const double *__restrict__ fo, double *__restrict__ yE, GeoArgs geo = GeoArgs{}) {
   if (flag && flag[S_DONE] != 0.0) return;
   constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
   static_assert(Q2 <= 64, "one plane per wavefront");
@@ -257,13 +262,55 @@ void k_apply_pw3(MeshDims md, const double *__restrict__ G, const double *__rest
   const int64_t e = xcd_tile(blockIdx.x, gridDim.x);
   const bool active = valid && e < nel;
   const int p = Q - 1;
-  // streamed data first: G (6 per node) and x
-  const double *Ge = G + (e < nel ? e : 0) * 6 * Q3 + node;
-  double g[6];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) g[i] = active ? Ge[i * Q3] : 0.0;
   const int ex = int(e % md.n[0]), ey = int((e / md.n[0]) % md.n[1]),
             ez = int(e / (int64_t(md.n[0]) * md.n[1]));
+  double g[6];
+  if constexpr (GEO) {
+    // G = (w / det) A A^T with A = adj(J), J from the element's trilinear map
+    const double xi[3] = {geo.gllx[a], geo.gllx[b], geo.gllx[c]};
+    const double om[3] = {1.0 - xi[0], 1.0 - xi[1], 1.0 - xi[2]};
+    const double w = geo.gllw[a] * geo.gllw[b] * geo.gllw[c];
+    const int nv0 = md.n[0] + 1, nv1 = md.n[1] + 1;
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      const int bx = cc & 1, by = (cc >> 1) & 1, bz = (cc >> 2) & 1;
+      const int64_t vi = (ex + bx) + int64_t(nv0) * ((ey + by) + int64_t(nv1) * (ez + bz));
+      const double gs0 = (bx ? 1.0 : -1.0) * (by ? xi[1] : om[1]) * (bz ? xi[2] : om[2]);
+      const double gs1 = (by ? 1.0 : -1.0) * (bx ? xi[0] : om[0]) * (bz ? xi[2] : om[2]);
+      const double gs2 = (bz ? 1.0 : -1.0) * (bx ? xi[0] : om[0]) * (by ? xi[1] : om[1]);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const double X = geo.verts[vi * 3 + r];
+        J[r][0] += X * gs0;
+        J[r][1] += X * gs1;
+        J[r][2] += X * gs2;
+      }
+    }
+    double A[3][3];
+    A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+    const double f = active ? w / det : 0.0;
+    g[0] = f * (A[0][0] * A[0][0] + A[0][1] * A[0][1] + A[0][2] * A[0][2]);
+    g[1] = f * (A[0][0] * A[1][0] + A[0][1] * A[1][1] + A[0][2] * A[1][2]);
+    g[2] = f * (A[0][0] * A[2][0] + A[0][1] * A[2][1] + A[0][2] * A[2][2]);
+    g[3] = f * (A[1][0] * A[1][0] + A[1][1] * A[1][1] + A[1][2] * A[1][2]);
+    g[4] = f * (A[1][0] * A[2][0] + A[1][1] * A[2][1] + A[1][2] * A[2][2]);
+    g[5] = f * (A[2][0] * A[2][0] + A[2][1] * A[2][1] + A[2][2] * A[2][2]);
+  } else {
+    // streamed data first: G (6 per node) and x
+    const double *Ge = G + (e < nel ? e : 0) * 6 * Q3 + node;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) g[i] = active ? Ge[i * Q3] : 0.0;
+  }
   const int gx = ex * p + a, gy = ey * p + b, gz = ez * p + c;
   const bool dir = md.dirichlet;
   const int ox = dir ? 1 : 0;
@@ -357,12 +404,15 @@ __global__ void k_skeleton_gather(MeshDims md, const double *__restrict__ yE,
   constexpr int Q3 = Q * Q * Q;
   const int p = Q - 1;
   const int ox = md.dirichlet ? 1 : 0;
-  const int64_t N = int64_t(md.nu[0]) * md.nu[1] * md.nu[2];
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int g[3] = {int(i % md.nu[0]) + ox, int((i / md.nu[0]) % md.nu[1]) + ox,
-                      int(i / (int64_t(md.nu[0]) * md.nu[1])) + ox};
-    if (g[0] % p != 0 && g[1] % p != 0 && g[2] % p != 0) continue;
+  // one block row per grid line (y, z): the line index is uniform, so the
+  // only division by a run-time extent is done once per block
+  const int line = int(blockIdx.y);
+  const int ly = line % md.nu[1], lz = line / md.nu[1];
+  const int ix = int(blockIdx.x * blockDim.x + threadIdx.x);
+  if (ix < md.nu[0]) {
+    const int64_t i = ix + int64_t(md.nu[0]) * line;
+    const int g[3] = {ix + ox, ly + ox, lz + ox};
+    if (g[0] % p != 0 && g[1] % p != 0 && g[2] % p != 0) return;
     double acc = 0.0;
     for (int cb = 0; cb < 8; ++cb) {
       int e[3], l[3];
@@ -520,7 +570,7 @@ inline int grid_for(int64_t n, int bs) {
 template <int Q>
 hipError_t apply_q(const MeshDims &md, const double *G, const double *D, const double *x,
                    double *y, double *partials, const double *flag, const double *fo, double *yE,
-                   hipStream_t st) {
+                   const GeoArgs *geo, hipStream_t st) {
   constexpr int Q2 = Q * Q;
   constexpr int EPB = 256 / Q2;
   const int64_t nel = int64_t(md.n[0]) * md.n[1] * (md.dim == 3 ? md.n[2] : 1);
@@ -532,10 +582,15 @@ hipError_t apply_q(const MeshDims &md, const double *G, const double *D, const d
                                                           nullptr);
       } else {
         if (!yE) return hipErrorInvalidValue;
-        k_apply_pw3<Q, false><<<int(nel), Q * 64, 0, st>>>(md, G, D, x, y, partials, flag,
-                                                           nullptr, yE);
-        const int64_t N = int64_t(md.nu[0]) * md.nu[1] * md.nu[2];
-        k_skeleton_gather<Q><<<grid_for(N, 256), 256, 0, st>>>(md, yE, y, flag);
+        if (geo)
+          k_apply_pw3<Q, false, true><<<int(nel), Q * 64, 0, st>>>(md, nullptr, D, x, y, partials, flag,
+                                                                   nullptr, yE, *geo);
+        else
+          k_apply_pw3<Q, false><<<int(nel), Q * 64, 0, st>>>(md, G, D, x, y, partials, flag,
+                                                             nullptr, yE);
+        const dim3 grid((md.nu[0] + 127) / 128, unsigned(md.nu[1]) * unsigned(md.nu[2]));
+        if (md.nu[0] > 0 && md.nu[1] > 0 && md.nu[2] > 0)
+          k_skeleton_gather<Q><<<grid, 128, 0, st>>>(md, yE, y, flag);
       }
       return hipGetLastError();
     }
@@ -571,23 +626,24 @@ int apply_cg_blocks(const MeshDims &md, bool dg) {
 
 hipError_t launch_apply_cg(const MeshDims &md, const double *G, const double *D, const double *x,
                            double *y, double *partials, const double *flag, hipStream_t st,
-                           const double *fo, double *yE) {
+                           const double *fo, double *yE, const GeoArgs *geo) {
+  if (geo && !(md.dim == 3 && md.p + 1 >= 5 && md.p + 1 <= 8 && !fo)) return hipErrorInvalidValue;
   switch (md.p + 1) {
-    case 2: return apply_q<2>(md, G, D, x, y, partials, flag, fo, yE, st);
-    case 3: return apply_q<3>(md, G, D, x, y, partials, flag, fo, yE, st);
-    case 4: return apply_q<4>(md, G, D, x, y, partials, flag, fo, yE, st);
-    case 5: return apply_q<5>(md, G, D, x, y, partials, flag, fo, yE, st);
-    case 6: return apply_q<6>(md, G, D, x, y, partials, flag, fo, yE, st);
-    case 7: return apply_q<7>(md, G, D, x, y, partials, flag, fo, yE, st);
-    case 8: return apply_q<8>(md, G, D, x, y, partials, flag, fo, yE, st);
-    case 9: return apply_q<9>(md, G, D, x, y, partials, flag, fo, yE, st);
-    case 10: return apply_q<10>(md, G, D, x, y, partials, flag, fo, yE, st);
-    case 11: return apply_q<11>(md, G, D, x, y, partials, flag, fo, yE, st);
-    case 12: return apply_q<12>(md, G, D, x, y, partials, flag, fo, yE, st);
-    case 13: return apply_q<13>(md, G, D, x, y, partials, flag, fo, yE, st);
-    case 14: return apply_q<14>(md, G, D, x, y, partials, flag, fo, yE, st);
-    case 15: return apply_q<15>(md, G, D, x, y, partials, flag, fo, yE, st);
-    case 16: return apply_q<16>(md, G, D, x, y, partials, flag, fo, yE, st);
+    case 2: return apply_q<2>(md, G, D, x, y, partials, flag, fo, yE, geo, st);
+    case 3: return apply_q<3>(md, G, D, x, y, partials, flag, fo, yE, geo, st);
+    case 4: return apply_q<4>(md, G, D, x, y, partials, flag, fo, yE, geo, st);
+    case 5: return apply_q<5>(md, G, D, x, y, partials, flag, fo, yE, geo, st);
+    case 6: return apply_q<6>(md, G, D, x, y, partials, flag, fo, yE, geo, st);
+    case 7: return apply_q<7>(md, G, D, x, y, partials, flag, fo, yE, geo, st);
+    case 8: return apply_q<8>(md, G, D, x, y, partials, flag, fo, yE, geo, st);
+    case 9: return apply_q<9>(md, G, D, x, y, partials, flag, fo, yE, geo, st);
+    case 10: return apply_q<10>(md, G, D, x, y, partials, flag, fo, yE, geo, st);
+    case 11: return apply_q<11>(md, G, D, x, y, partials, flag, fo, yE, geo, st);
+    case 12: return apply_q<12>(md, G, D, x, y, partials, flag, fo, yE, geo, st);
+    case 13: return apply_q<13>(md, G, D, x, y, partials, flag, fo, yE, geo, st);
+    case 14: return apply_q<14>(md, G, D, x, y, partials, flag, fo, yE, geo, st);
+    case 15: return apply_q<15>(md, G, D, x, y, partials, flag, fo, yE, geo, st);
+    case 16: return apply_q<16>(md, G, D, x, y, partials, flag, fo, yE, geo, st);
     default: return hipErrorInvalidValue;
   }
 }

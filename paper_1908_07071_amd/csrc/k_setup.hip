@@ -148,17 +148,20 @@ __global__ void k_geom(MeshDims md, const double *__restrict__ verts,
     }
     if (!(det > 0.0)) atomicOr(bad, 1);
     // G = (w / det) * A A^T, with A = det * J^-1 (times the coefficient b
-    // at the node: -div(b grad u), Section 4.2)
+    // at the node: -div(b grad u), Section 4.2); G may be null when the
+    // operator recomputes it
     const double f = coef ? (w / det) * coef[e * nq + q] : w / det;
-    double *Ge = G + e * ncomp * nq;
-    int comp = 0;
-    for (int r = 0; r < DIM; ++r)
-      for (int c2 = r; c2 < DIM; ++c2) {
-        double acc = 0.0;
-        for (int s = 0; s < DIM; ++s) acc += A[r][s] * A[c2][s];
-        Ge[comp * nq + q] = f * acc;
-        ++comp;
-      }
+    if (G) {
+      double *Ge = G + e * ncomp * nq;
+      int comp = 0;
+      for (int r = 0; r < DIM; ++r)
+        for (int c2 = r; c2 < DIM; ++c2) {
+          double acc = 0.0;
+          for (int s = 0; s < DIM; ++s) acc += A[r][s] * A[c2][s];
+          Ge[comp * nq + q] = f * acc;
+          ++comp;
+        }
+    }
     wdet[e * nq + q] = w * det;
   }
 }
@@ -472,7 +475,10 @@ __global__ __launch_bounds__(256) void k_coarse_prolong(MeshDims md, const doubl
 // and each lane keeps eight loads of its row in flight.
 constexpr int kGemvTile = 2048;
 constexpr int kGemvRows = 8;
-__global__ __launch_bounds__(64 * kGemvRows) void k_gemv(int n, const double *__restrict__ A,
+// TA: float64 inverse, or its float32 copy with the mixed-precision
+// preconditioner (products and sums in float64 either way)
+template <typename TA>
+__global__ __launch_bounds__(64 * kGemvRows) void k_gemv(int n, const TA *__restrict__ A,
                                                          const double *__restrict__ x,
                                                          double *__restrict__ y, const double *flag) {
   if (flag && flag[S_DONE] != 0.0) return;  // uniform over the grid
@@ -480,23 +486,23 @@ __global__ __launch_bounds__(64 * kGemvRows) void k_gemv(int n, const double *__
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * kGemvRows + (threadIdx.x >> 6);
   const bool live = row < n;
-  const double *a = A + int64_t(live ? row : 0) * n;
+  const TA *a = A + int64_t(live ? row : 0) * n;
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int j0 = 0; j0 < n; j0 += kGemvTile) {
     const int m = min(kGemvTile, n - j0);
     __syncthreads();
     for (int t = threadIdx.x; t < m; t += 64 * kGemvRows) xs[t] = x[j0 + t];
     __syncthreads();
-    const double *aj = a + j0;
+    const TA *aj = a + j0;
     int j = lane;
     for (; j + 448 < m; j += 512) {
       double av[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) av[q] = aj[j + 64 * q];
+      for (int q = 0; q < 8; ++q) av[q] = double(aj[j + 64 * q]);
 #pragma unroll
       for (int q = 0; q < 8; ++q) acc[q] += av[q] * xs[j + 64 * q];
     }
-    for (; j < m; j += 64) acc[0] += aj[j] * xs[j];
+    for (; j < m; j += 64) acc[0] += double(aj[j]) * xs[j];
   }
   double sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
@@ -664,7 +670,14 @@ hipError_t launch_coarse_prolong(const MeshDims &md, const double *gllx, const d
 hipError_t launch_gemv(int n, const double *A, const double *x, double *y, const double *flag,
                        hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  k_gemv<<<(n + kGemvRows - 1) / kGemvRows, 64 * kGemvRows, 0, st>>>(n, A, x, y, flag);
+  k_gemv<double><<<(n + kGemvRows - 1) / kGemvRows, 64 * kGemvRows, 0, st>>>(n, A, x, y, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemv_f32(int n, const float *A, const double *x, double *y, const double *flag,
+                           hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_gemv<float><<<(n + kGemvRows - 1) / kGemvRows, 64 * kGemvRows, 0, st>>>(n, A, x, y, flag);
   return hipGetLastError();
 }
 

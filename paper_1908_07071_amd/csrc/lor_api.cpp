@@ -200,7 +200,18 @@ int build_coarse(lor_handle &h, const std::vector<double> &st0, hipStream_t st) 
   for (auto &th : pool) th.join();
   HIPCHK(h.alloc(&h.d_A0inv, size_t(h.nc) * h.nc));
   HIPCHK(hipMemcpyAsync(h.d_A0inv, A0.data(), A0.size() * sizeof(double), hipMemcpyHostToDevice, st));
-  return coarse_inverse(h.nc, h.d_A0inv, st);
+  int rc = coarse_inverse(h.nc, h.d_A0inv, st);
+  if (rc != LOR_OK) return rc;
+  if (h.opt.precision == LOR_PREC_MIXED) {
+    // the float32 preconditioner applies the coarse inverse in float32
+    // storage too: half the bytes of the largest array of each application
+    HIPCHK(h.alloc(&h.d_A0inv_f, size_t(h.nc) * h.nc));
+    HIPCHK(launch_to_float(h.d_A0inv, h.d_A0inv_f, int64_t(h.nc) * h.nc, st));
+    HIPCHK(hipStreamSynchronize(st));
+    h.release(h.d_A0inv);
+    h.d_A0inv = nullptr;
+  }
+  return LOR_OK;
 }
 
 int build_patches(lor_handle &h, const std::vector<std::vector<double>> &hst, hipStream_t st) {
@@ -437,7 +448,11 @@ int setup_impl(lor_handle &h, hipStream_t st) {
     HIPCHK(hipStreamSynchronize(st));
   }
   const int ncomp = dim == 3 ? 6 : 3;
-  HIPCHK(h.alloc(&h.d_G, size_t(h.nel) * ncomp * nq));
+  // on request the plane kernel of 3D CG with straight elements and b = 1
+  // recomputes the geometric factors from the vertices instead of storing them
+  h.geo_onfly = !dg && h.coef.empty() && h.nodes.empty() && apply_cg_uses_skeleton(md) &&
+                h.opt.operator_geometry == LOR_GEOM_ONFLY;
+  if (!h.geo_onfly) HIPCHK(h.alloc(&h.d_G, size_t(h.nel) * ncomp * nq));
   HIPCHK(h.alloc(&h.d_wdet, size_t(h.nel) * nq));
   int *bad;
   HIPCHK(h.alloc(&bad, 1));
@@ -571,7 +586,10 @@ int apply_P_cg(lor_handle *h, Work &w, const double *r, double *z, const double 
   if (h->nc > 0) {
     Span sp(h, LOR_T_COARSE, st);
     HIPCHK(launch_coarse_restrict(h->md, h->d_gllx, r, w.rc, st));
-    HIPCHK(launch_gemv(h->nc, h->d_A0inv, w.rc, w.xc, flag, st));
+    if (h->d_A0inv_f)
+      HIPCHK(launch_gemv_f32(h->nc, h->d_A0inv_f, w.rc, w.xc, flag, st));
+    else
+      HIPCHK(launch_gemv(h->nc, h->d_A0inv, w.rc, w.xc, flag, st));
     HIPCHK(launch_coarse_prolong(h->md, h->d_gllx, w.xc, z, flag, st));
   } else {
     HIPCHK(launch_fill(z, h->ncg, 0.0, st));
@@ -642,8 +660,9 @@ int apply_A_impl(lor_handle *h, Work &w, const double *x, double *y, double *par
                  const double *flag, hipStream_t st) {
   Span sp(h, LOR_T_APPLY_A, st);
   if (h->method != LOR_CG) HIPCHK(launch_dg_face(h->md, h->d_D, h->d_fg, x, w.fo, flag, st));
+  GeoArgs geo{h->d_verts, h->d_gllx, h->d_gllw};
   HIPCHK(launch_apply_cg(h->md, h->d_G, h->d_D, x, y, partials, flag, st,
-                         h->method != LOR_CG ? w.fo : nullptr, w.yE));
+                         h->method != LOR_CG ? w.fo : nullptr, w.yE, h->geo_onfly ? &geo : nullptr));
   return LOR_OK;
 }
 
@@ -903,8 +922,9 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const l
     if (opt->sweep_grid_rows < 0) return LOR_EINVAL;
     if (opt->deterministic != 0 && opt->deterministic != 1) return LOR_EINVAL;
     if (opt->launch_order < LOR_LAUNCH_AUTO || opt->launch_order > LOR_LAUNCH_BUCKETS) return LOR_EINVAL;
-    for (int t = 0; t < 2; ++t)
-      if (opt->reserved[t] != 0) return LOR_EINVAL;
+    if (opt->operator_geometry != LOR_GEOM_STORED && opt->operator_geometry != LOR_GEOM_ONFLY)
+      return LOR_EINVAL;
+    if (opt->reserved[0] != 0) return LOR_EINVAL;
   } else {
     lor_default_options(&h->opt);
   }
@@ -1028,7 +1048,7 @@ int lor_bind_workspace(lor_handle_t *h, void *dev_ptr, size_t bytes, void *strea
     };
     set(h->d_verts), set(h->d_gllx), set(h->d_gllw), set(h->d_D), set(h->d_coords);
     set(h->d_G), set(h->d_wdet), set(h->d_fac), set(h->d_fac_off), set(h->d_xfer);
-    set(h->d_A0inv), set(h->d_fg), set(h->d_dinv), set(h->d_coef);
+    set(h->d_A0inv), set(h->d_A0inv_f), set(h->d_fg), set(h->d_dinv), set(h->d_coef);
     for (int k = 0; k < kMaxLevels; ++k) set(h->d_stencil[k]);
     Work &w = h->w;
     set(w.r), set(w.z), set(w.p), set(w.q), set(w.rold), set(w.tmp), set(w.scal), set(w.part);

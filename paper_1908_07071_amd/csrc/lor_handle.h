@@ -71,10 +71,12 @@ struct lor_handle {
   int64_t fac_bytes = 0;
   XferTab *d_xfer = nullptr;
   double *d_A0inv = nullptr;
+  float *d_A0inv_f = nullptr;  // mixed precision: float32 copy (the float64 one is released)
   double *d_fg = nullptr, *d_dinv = nullptr;
   double *d_coef = nullptr;
   int *d_perm = nullptr;       // patches by decreasing work (launch buckets)
   int order_used = 0;          // LOR_LAUNCH_VERTEX or LOR_LAUNCH_BUCKETS
+  bool geo_onfly = false;      // operator recomputes G from the vertices (d_G not stored)
   double tune_ms[2] = {0, 0};  // autotuner: patch launch in vertex order, in buckets
   int npart = 0;
   Work w;                  // workspace of lor_pcg_solve / lor_apply_*
@@ -114,6 +116,17 @@ struct lor_handle {
     bytes += b;
     *ptr = static_cast<T *>(p);
     return hipSuccess;
+  }
+  // releases one allocation of allocs (no-op for pointers it does not hold)
+  void release(void *p) {
+    for (size_t i = 0; i < allocs.size(); ++i)
+      if (allocs[i] == p) {
+        (void)hipFree(p);
+        bytes -= alloc_size[i];
+        allocs.erase(allocs.begin() + i);
+        alloc_size.erase(alloc_size.begin() + i);
+        return;
+      }
   }
   ~lor_handle() {
     for (void *p : allocs) (void)hipFree(p);

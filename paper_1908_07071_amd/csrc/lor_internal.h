@@ -179,9 +179,15 @@ int apply_cg_blocks(const MeshDims &md, bool dg);
 // then written completely, no zeroing needed); otherwise y must be zero on
 // entry (shared nodes are accumulated atomically) and yE is unused.
 bool apply_cg_uses_skeleton(const MeshDims &md);
+// geo: recompute the geometric factors from the vertices instead of reading
+// G (3D CG, 5 <= p + 1 <= 8 only)
+struct GeoArgs {
+  const double *verts = nullptr, *gllx = nullptr, *gllw = nullptr;
+};
 hipError_t launch_apply_cg(const MeshDims &md, const double *G, const double *D,
                            const double *x, double *y, double *partials, const double *flag,
-                           hipStream_t st, const double *fo = nullptr, double *yE = nullptr);
+                           hipStream_t st, const double *fo = nullptr, double *yE = nullptr,
+                           const GeoArgs *geo = nullptr);
 
 // DG (faces, penalties, diagonal, E-vector transfers)
 int64_t dg_face_count(const MeshDims &md);
@@ -207,6 +213,9 @@ hipError_t launch_coarse_prolong(const MeshDims &md, const double *gllx, const d
                                  double *z, const double *flag, hipStream_t st);
 hipError_t launch_gemv(int n, const double *A, const double *x, double *y, const double *flag,
                        hipStream_t st);
+// y = A x with the float32 copy of a float64 matrix (float64 products and sums)
+hipError_t launch_gemv_f32(int n, const float *A, const double *x, double *y, const double *flag,
+                           hipStream_t st);
 hipError_t launch_small_inverse(const double *M, int ldm, double *Minv, int bk, int *bad,
                                 hipStream_t st);
 hipError_t launch_copy_block(const double *src, int64_t lds, double *dst, int64_t ldd, int rows,

@@ -26,6 +26,7 @@ LOR_ORD_MDF, LOR_ORD_NATURAL, LOR_ORD_RCM = 0, 1, 2
 LOR_PROLONG_SUM, LOR_PROLONG_POU = 0, 1
 LOR_PATCH_VERTEX, LOR_PATCH_SINGLE, LOR_PATCH_SLABS, LOR_PATCH_VERTEX_ISO = 0, 1, 2, 3
 LOR_LAUNCH_AUTO, LOR_LAUNCH_VERTEX, LOR_LAUNCH_BUCKETS = 0, 1, 2
+LOR_GEOM_STORED, LOR_GEOM_ONFLY = 0, 1
 LOR_MAP_LDOF, LOR_MAP_ORDER, LOR_MAP_ORDER_OFFSET = 0, 1, 2
 LOR_MAP_SCHEDULE, LOR_MAP_SCHEDULE_OFFSET, LOR_MAP_E2L = 3, 4, 5
 
@@ -60,7 +61,8 @@ class lor_options_t(C.Structure):
     _fields_ = [("precision", C.c_int), ("ordering", C.c_int), ("flexible", C.c_int),
                 ("nthreads", C.c_int), ("prolong_weights", C.c_int), ("patch_mode", C.c_int),
                 ("sweep_grid_rows", C.c_int), ("nslabs", C.c_int),
-                ("deterministic", C.c_int), ("launch_order", C.c_int), ("reserved", C.c_int * 2)]
+                ("deterministic", C.c_int), ("launch_order", C.c_int), ("operator_geometry", C.c_int),
+                ("reserved", C.c_int * 1)]
 
 
 class lor_solve_info_t(C.Structure):

@@ -159,3 +159,37 @@ def test_square_8x8_p3_manufactured(L, torch_dev):
         assert np.abs(xs - inputs.manufactured_u(xy)).max() <= 1e-4
     finally:
         L.lor_free(h)
+
+
+@pytest.mark.parametrize("p", [4, 6])
+def test_operator_geometry_on_the_fly(p, L, torch_dev):
+    """LOR_GEOM_ONFLY: the operator recomputes the geometric factors from the
+    vertices; the same K_p x as the oracle (and as the streamed factors) to
+    the float64 parity tolerance."""
+    torch = torch_dev
+    dim, n = 3, [2, 3, 2]
+    V = inputs.structured_vertices(dim, n, 0.1, seed=17)
+    mesh = M.make_mesh(dim, n, V)
+    K = HO.cg_stiffness(mesh, p)
+    ys = []
+    for geom in (L.LOR_GEOM_ONFLY, L.LOR_GEOM_STORED):
+        o = L.lor_default_options()
+        o.operator_geometry = geom
+        h = L.lor_setup(dim, n, V, p, options=o)
+        try:
+            N = L.lor_ndofs(h)
+            xin = inputs.uniform_vector(N, 19)
+            x = torch.tensor(xin, device="cuda")
+            y = torch.empty_like(x)
+            L.lor_apply_A(h, x, y)
+            torch.cuda.synchronize()
+            ys.append(y.cpu().numpy())
+            ref = K @ xin
+            assert np.abs(ys[-1] - ref).max() <= 1e-12 * np.abs(ref).max()
+            b = torch.tensor(inputs.gaussian_rhs(N, 20), device="cuda")
+            u = torch.zeros_like(b)
+            info = L.lor_pcg_solve(h, b, u, rtol=1e-10, maxit=300)
+            assert info.status == L.LOR_OK
+        finally:
+            L.lor_free(h)
+    assert np.abs(ys[0] - ys[1]).max() <= 1e-13 * np.abs(ys[1]).max()
