@@ -112,8 +112,37 @@ std::vector<char> pack_sweep(const MdfResult &res, int dim, const int *m, bool f
     }
   }
   if (chunks.back().nsteps == 0) chunks.pop_back();
-  // per-lane quads, chunk width and size
   const int hw = sweep_head_words<T>(fwd), pw = sweep_pair_words<T>();
+  // Lanes of a chunk sorted by record length, longest first (lane pairs
+  // first, on even lanes): quad q of the chunk is then loaded by a prefix of
+  // the lanes, so a 128-byte line (8 lanes' quads) is fetched only where
+  // most of it is used.  Rows keep their steps; the lane of a row is free.
+  for (Chunk &c : chunks) {
+    struct Unit {
+      int first, lanes, quads;
+    };
+    std::vector<Unit> units;
+    for (int l = 0; l < kChunkLanes; ++l) {
+      const LaneRec &r = c.lane[l];
+      if (r.row < 0 || r.second) continue;
+      const int q0 = sweep_quads<T>(fwd, (r.c1 - r.c0 + 1) & ~1);
+      if (r.paired) {
+        const LaneRec &r2 = c.lane[l + 1];
+        units.push_back({l, 2, std::max(q0, sweep_quads<T>(fwd, (r2.c1 - r2.c0 + 1) & ~1))});
+      } else {
+        units.push_back({l, 1, q0});
+      }
+    }
+    std::stable_sort(units.begin(), units.end(), [](const Unit &a, const Unit &b) {
+      return a.lanes != b.lanes ? a.lanes > b.lanes : a.quads > b.quads;
+    });
+    std::vector<LaneRec> sorted(kChunkLanes);
+    int l = 0;
+    for (const Unit &u : units)
+      for (int k = 0; k < u.lanes; ++k) sorted[l++] = c.lane[u.first + k];
+    c.lane.swap(sorted);
+  }
+  // per-lane quads, chunk width and size
   std::vector<std::vector<int>> lane_q(chunks.size(), std::vector<int>(64, 1));
   for (size_t ci = 0; ci < chunks.size(); ++ci) {
     Chunk &c = chunks[ci];
