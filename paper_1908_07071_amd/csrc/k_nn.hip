@@ -161,14 +161,16 @@ __global__ void k_output(const float *__restrict__ z, int Np, const float *__res
     y[t] = z[t * Np] * X[2 * t + 1];
 }
 
-// loss partials: sum of ((y - T) mask)^2 and of mask per block; dz of the
-// output layer: column 0 = 2 (y - T) mask / m, other columns 0.
+// loss partials: sum of ((y - T) mask)^2 per block; dz of the output layer:
+// column 0 = 2 (y - T) mask / m (m = *msum, the number of masked points),
+// other columns 0.
 __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ y, const float *__restrict__ T,
                                               const float *__restrict__ X, int64_t rows,
-                                              int64_t npad, int Np, double inv_m,
+                                              int64_t npad, int Np, const double *__restrict__ msum,
                                               float *__restrict__ dz, uint16_t *__restrict__ dz16,
                                               double *__restrict__ part) {
   __shared__ double red[256];
+  const double inv_m = 1.0 / *msum;
   double acc = 0.0;
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < npad;
        t += int64_t(gridDim.x) * blockDim.x) {
@@ -193,10 +195,13 @@ __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ y, const
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// per-block partial sums of a strided float column (mask count, bias grads)
+// per-block partial sums of strided float columns (mask count, bias grads):
+// column col0 + blockIdx.y into part[blockIdx.y * kPartStride + blockIdx.x]
 __global__ __launch_bounds__(256) void k_colsum(const float *__restrict__ a, int64_t rows, int ld,
-                                                int col, double *__restrict__ part) {
+                                                int col0, double *__restrict__ part) {
   __shared__ double red[256];
+  const int col = col0 + int(blockIdx.y);
+  part += size_t(blockIdx.y) * kPartStride;
   double acc = 0.0;
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < rows;
        t += int64_t(gridDim.x) * blockDim.x)
@@ -208,6 +213,18 @@ __global__ __launch_bounds__(256) void k_colsum(const float *__restrict__ a, int
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Totals of per-block partials, summed in block order in double (one thread
+// per column): dsum[c] and, where given, fsum[c] = float(dsum[c]).
+__global__ void k_sum_partials(const double *__restrict__ part, int nblk, int ncols,
+                               double *__restrict__ dsum, float *__restrict__ fsum) {
+  const int c = int(blockIdx.x * blockDim.x + threadIdx.x);
+  if (c >= ncols) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[size_t(c) * kPartStride + b];
+  if (dsum) dsum[c] = s;
+  if (fsum) fsum[c] = float(s);
 }
 
 // Adam: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, w -= lr c1 m / (sqrt(c2 v) + eps)
@@ -375,16 +392,25 @@ hipError_t nn_output(const float *z, int Np, const float *X, int64_t rows, float
   return hipGetLastError();
 }
 
-int nn_red_blocks(int64_t n) { return std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256)); }
+int nn_red_blocks(int64_t n) { return std::min<int64_t>(kPartStride, std::max<int64_t>(1, (n + 255) / 256)); }
 
 hipError_t nn_loss(const float *y, const float *T, const float *X, int64_t rows, int64_t npad,
-                   int Np, double inv_m, float *dz, uint16_t *dz16, double *part, hipStream_t st) {
-  k_loss<<<nn_red_blocks(npad), 256, 0, st>>>(y, T, X, rows, npad, Np, inv_m, dz, dz16, part);
+                   int Np, const double *msum, float *dz, uint16_t *dz16, double *part, hipStream_t st) {
+  k_loss<<<nn_red_blocks(npad), 256, 0, st>>>(y, T, X, rows, npad, Np, msum, dz, dz16, part);
   return hipGetLastError();
 }
 
-hipError_t nn_colsum(const float *a, int64_t rows, int ld, int col, double *part, hipStream_t st) {
-  k_colsum<<<nn_red_blocks(rows), 256, 0, st>>>(a, rows, ld, col, part);
+hipError_t nn_colsum(const float *a, int64_t rows, int ld, int col0, int ncols, double *part,
+                     hipStream_t st) {
+  if (ncols < 1) return hipErrorInvalidValue;
+  k_colsum<<<dim3(nn_red_blocks(rows), ncols), 256, 0, st>>>(a, rows, ld, col0, part);
+  return hipGetLastError();
+}
+
+hipError_t nn_sum_partials(const double *part, int nblk, int ncols, double *dsum, float *fsum,
+                           hipStream_t st) {
+  if (nblk < 1 || nblk > kPartStride || ncols < 1) return hipErrorInvalidValue;
+  k_sum_partials<<<(ncols + 63) / 64, 64, 0, st>>>(part, nblk, ncols, dsum, fsum);
   return hipGetLastError();
 }
 

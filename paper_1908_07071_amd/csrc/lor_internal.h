@@ -308,10 +308,15 @@ hipError_t nn_input(const float *X, int64_t rows, int64_t npad, uint16_t *a0, co
                     hipStream_t st);
 hipError_t nn_output(const float *z, int Np, const float *X, int64_t rows, float *y,
                      const double *flag, hipStream_t st);
+// per-block partial sums: at most kPartStride blocks, column c at part + c * kPartStride
+constexpr int kPartStride = 1024;
 int nn_red_blocks(int64_t n);
 hipError_t nn_loss(const float *y, const float *T, const float *X, int64_t rows, int64_t npad,
-                   int Np, double inv_m, float *dz, uint16_t *dz16, double *part, hipStream_t st);
-hipError_t nn_colsum(const float *a, int64_t rows, int ld, int col, double *part, hipStream_t st);
+                   int Np, const double *msum, float *dz, uint16_t *dz16, double *part, hipStream_t st);
+hipError_t nn_colsum(const float *a, int64_t rows, int ld, int col0, int ncols, double *part,
+                     hipStream_t st);
+hipError_t nn_sum_partials(const double *part, int nblk, int ncols, double *dsum, float *fsum,
+                           hipStream_t st);
 hipError_t nn_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1,
                    float b2, float eps, float c1, float c2, hipStream_t st);
 hipError_t nn_pack(const float *wl, int K27, int cout, int Kp, int Np, uint16_t *Wb, float *bias,

@@ -24,6 +24,7 @@ struct lor_nn {
   uint16_t *cols = nullptr, *dz16 = nullptr;
   float *dcols = nullptr, *dz = nullptr, *dW = nullptr, *y = nullptr, *Xbuf = nullptr;
   double *part = nullptr, *sbuf = nullptr;
+  double *scal = nullptr;   // device scalars of a training step: mask count, loss sum
   float *yall = nullptr;    // warm start: predictions of every patch [J][G^3]
   double *sall = nullptr;   // and their scales [J]
   int step = 0;
@@ -92,42 +93,28 @@ int forward(lor_nn *nn, const float *X, int nb, const double *flag, hipStream_t 
   return LOR_OK;
 }
 
-double host_sum(lor_nn *nn, int count, hipStream_t st, int slot = 0) {
-  std::vector<double> h(count);
-  if (hipMemcpyAsync(h.data(), nn->part + size_t(slot) * 1024, count * sizeof(double),
-                     hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return NAN;
-  double s = 0.0;
-  for (double v : h) s += v;
-  return s;
-}
-
-// Loss of the batch and the flat float32 gradient in nn->g.
+// Loss of the batch and the flat float32 gradient in nn->g.  Every
+// reduction (mask count, loss, bias gradients) is finished on the device, in
+// double over per-block partials in block order; the host waits once, for the
+// mask count and the loss.
 int backward(lor_nn *nn, const float *X, const float *T, int nb, double *loss, hipStream_t st) {
   const int64_t rows = int64_t(nb) * nn->G3, npad = pad16(rows);
   int rc = forward(nn, X, nb, nullptr, st);
   if (rc != LOR_OK) return rc;
-  // number of masked points
-  NCHK(nn_colsum(X, rows, 2, 1, nn->part, st));
-  const double msum = host_sum(nn, nn_red_blocks(rows), st);
-  if (!(msum > 0.0)) return LOR_EINVAL;
-  NCHK(nn_loss(nn->y, T, X, rows, npad, nn->Np[2], 1.0 / msum, nn->dz, nn->dz16, nn->part, st));
-  const double lsum = host_sum(nn, nn_red_blocks(npad), st);
-  if (loss) *loss = lsum / msum;
-  std::vector<float> bgrad;
+  // number of masked points -> scal[0]
+  NCHK(nn_colsum(X, rows, 2, 1, 1, nn->part, st));
+  NCHK(nn_sum_partials(nn->part, nn_red_blocks(rows), 1, nn->scal, nullptr, st));
+  NCHK(nn_loss(nn->y, T, X, rows, npad, nn->Np[2], nn->scal, nn->dz, nn->dz16, nn->part, st));
+  NCHK(nn_sum_partials(nn->part, nn_red_blocks(npad), 1, nn->scal + 1, nullptr, st));
   for (int l = 2; l >= 0; --l) {
     const int Np = nn->Np[l], Kp = nn->Kp[l], cout = nn->cout[l];
     // dW = cols^T dz (sum over all rows), db = column sums of dz
     NCHK(nn_im2col(nn->a[l], rows, nn->G, nn->cin[l], Kp, npad, nn->cols, nullptr, st));
     NCHK(nn_gemm(Kp, Np, int(npad), nn->cols, 1, Kp, nn->dz16, Np, 1, nn->dW, Np, false, st));
     NCHK(nn_grad_gather(nn->dW, nn->K27[l], cout, Np, nn->g + nn->off[l], st));
-    const int nbk = nn_red_blocks(rows);
-    for (int o = 0; o < cout; ++o) NCHK(nn_colsum(nn->dz, rows, Np, o, nn->part + size_t(o) * 1024, st));
-    bgrad.assign(cout, 0.f);
-    for (int o = 0; o < cout; ++o) bgrad[o] = float(host_sum(nn, nbk, st, o));
-    NCHK(hipMemcpyAsync(nn->g + nn->off[l] + int64_t(nn->K27[l]) * cout, bgrad.data(),
-                        cout * sizeof(float), hipMemcpyHostToDevice, st));
+    NCHK(nn_colsum(nn->dz, rows, Np, 0, cout, nn->part, st));
+    NCHK(nn_sum_partials(nn->part, nn_red_blocks(rows), cout, nullptr,
+                         nn->g + nn->off[l] + int64_t(nn->K27[l]) * cout, st));
     if (l > 0) {
       // input gradient: dcols = dz W^T, then col2im and the ReLU of layer l-1
       NCHK(nn_gemm(int(npad), Kp, Np, nn->dz16, Np, 1, nn->Wb[l], 1, Np, nn->dcols, Kp, false, st));
@@ -135,7 +122,12 @@ int backward(lor_nn *nn, const float *X, const float *T, int nb, double *loss, h
                           nn->dz, nn->dz16, st));
     }
   }
+  double hs[2];
+  NCHK(hipMemcpyAsync(hs, nn->scal, sizeof(hs), hipMemcpyDeviceToHost, st));
   NCHK(hipStreamSynchronize(st));
+  // no masked point: the gradient is not defined (and not applied)
+  if (!(hs[0] > 0.0)) return LOR_EINVAL;
+  if (loss) *loss = hs[1] / hs[0];
   return LOR_OK;
 }
 
@@ -231,7 +223,8 @@ int lor_nn_create(lor_handle_t *h, int channels, const double *params, int max_b
   NCHK(nn->alloc(&nn->y, size_t(npad)));
   NCHK(nn->alloc(&nn->Xbuf, size_t(max_batch) * nn->G3 * 2));
   NCHK(nn->alloc(&nn->sbuf, size_t(max_batch)));
-  NCHK(nn->alloc(&nn->part, size_t(Npmax) * 1024));
+  NCHK(nn->alloc(&nn->part, size_t(Npmax) * kPartStride));
+  NCHK(nn->alloc(&nn->scal, 2));
   std::vector<float> w32(o);
   for (int64_t i = 0; i < o; ++i) {
     if (!std::isfinite(params[i])) return LOR_EINVAL;

@@ -152,6 +152,17 @@ def test_gradients_match_oracle(L, torch_dev):
             o += n
             assert np.linalg.norm(gw - dW) <= 5e-2 * np.linalg.norm(dW), (k, n)
             assert np.linalg.norm(gb - db) <= 5e-2 * np.linalg.norm(db) + 1e-7, (k, n)
+        # a batch without a masked point has no loss: refused, and a training
+        # step on it leaves the parameters as they were
+        X0 = X.clone()
+        X0[..., 1] = 0.0
+        with pytest.raises(L.LorError) as ei:
+            L.lor_nn_train_step(nn, X0, T, J, 1e-3)
+        assert ei.value.code == L.LOR_EINVAL
+        w_before = L.lor_nn_get_params(nn, C)
+        with pytest.raises(L.LorError):
+            L.lor_nn_train_step(nn, X0, T, J, 1e-3)
+        assert np.array_equal(L.lor_nn_get_params(nn, C), w_before)
     finally:
         L.lor_nn_free(nn)
         L.lor_free(h)
@@ -218,6 +229,28 @@ def test_training_and_replace_preconditioner(L, torch_dev):
         info0 = L.lor_pcg_solve(h, rt, x, rtol=1e-6, maxit=400)
         assert info0.status == L.LOR_OK
         assert infow.iters <= 1.5 * info0.iters + 3, (infow.iters, info0.iters)
+        # What the trained network gains over the method without it, stated:
+        # nothing here.  In place of the V-cycles it needs more iterations
+        # (or does not converge), and as a warm start it adds the network's
+        # cost to every application of the V-cycles.
+        assert info.status != L.LOR_OK or info.iters > info0.iters, (info.iters, info0.iters)
+        times = {}
+        for mode in (L.LOR_NN_OFF, L.LOR_NN_WARMSTART):
+            L.lor_nn_attach(h, nn if mode else None, mode)
+            L.lor_apply_P(h, rt, z)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(20):
+                L.lor_apply_P(h, rt, z)
+            e1.record()
+            e1.synchronize()
+            times[mode] = e0.elapsed_time(e1) / 20
+        L.lor_nn_attach(h, None, L.LOR_NN_OFF)
+        print("iterations: V-cycle", info0.iters, "network", info.iters, "warm start", infow.iters,
+              "; ms per application: V-cycle", times[L.LOR_NN_OFF], "warm start",
+              times[L.LOR_NN_WARMSTART], flush=True)
+        assert times[L.LOR_NN_WARMSTART] > times[L.LOR_NN_OFF]
     finally:
         L.lor_nn_free(nn)
         L.lor_free(h)
