@@ -13,6 +13,13 @@ from paper_1908_07071_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
+# Float32 preconditioner (stencils, factors and patch vectors in float32,
+# float64 products and sums): every entry |z_i - zref_i| <= FP32_PRECOND_TOL
+# max|zref|, i.e. 32 units of float32 rounding (2^-24) for an entry that sums
+# at most 2^d patch corrections, each through at most four triangular sweeps
+# and two residuals per level.
+FP32_PRECOND_TOL = 2e-6
+
 CASES = [
     # dim, n, p, perturb, seed
     (2, (3, 3), 3, 0.1, 1),
@@ -214,6 +221,10 @@ def test_mixed_precision_preconditioner_and_fcg(case, L, torch_dev):
         zref = B.apply(rin)
         err = np.linalg.norm(z.cpu().numpy() - zref) / np.linalg.norm(zref)
         assert err <= 2e-5, err
+        # element by element, at the float32 parity bound
+        emax = np.abs(z.cpu().numpy() - zref).max() / np.abs(zref).max()
+        print("float32 preconditioner: 2-norm", err, "max", emax, flush=True)
+        assert emax <= FP32_PRECOND_TOL, emax
         x = torch.zeros_like(r)
         info = L.lor_pcg_solve(h, r, x, rtol=1e-10, maxit=500)
         _, it, _ = krylov.pcg(K, rin, B.apply, tol=1e-10, flexible=True)

@@ -2,9 +2,14 @@
 (oracle/nn.py), through the C ABI.
 
 Tolerances: the network's products run in bfloat16 (8-bit significand) with
-float32 accumulation, so outputs and gradients are compared in norm to a few
+float32 accumulation, so outputs and gradients are compared to a few
 percent; the patch data (float32 copies of float64 values) to float32
-rounding.
+rounding.  Element by element: every operand (input, weight, activation
+between layers) is rounded to bfloat16 (relative error <= 2^-9 ~ 2e-3), so
+each of the three layers adds about 3 such roundings relative to the sum of
+magnitudes of its products; |y_i - yref_i| <= BF16_TOL max|yref| allows the
+three layers 1.8e-2 plus cancellation.  Measured: 1.2e-2 on the worst patch
+at 16 channels, 5e-3 at 32.
 """
 import numpy as np
 import pytest
@@ -15,6 +20,12 @@ from paper_1908_07071_amd import inputs
 pytestmark = pytest.mark.gpu
 
 C = 16
+BF16_TOL = 3e-2
+
+
+def _emax(a, ref):
+    """max |a - ref| / max |ref| (element by element)."""
+    return np.abs(np.asarray(a) - ref).max() / np.abs(ref).max()
 
 
 @pytest.fixture(scope="module")
@@ -100,6 +111,7 @@ def test_patch_data_and_forward_match_oracle(L, torch_dev):
         yref, _ = ONN.forward(ONN.unflatten(params, shapes), X.cpu().numpy().astype(np.float64), G)
         err = np.linalg.norm(Y.cpu().numpy() - yref) / np.linalg.norm(yref)
         assert err <= 3e-2, err
+        assert _emax(Y.cpu().numpy(), yref) <= BF16_TOL
     finally:
         L.lor_nn_free(nn)
         L.lor_free(h)
@@ -123,8 +135,9 @@ def test_forward_paths_match_oracle(channels, L, torch_dev):
         shapes = ONN.layer_shapes(channels)
         yref, _ = ONN.forward(ONN.unflatten(params, shapes), X.cpu().numpy().astype(np.float64), G)
         err = np.linalg.norm(Y.cpu().numpy() - yref) / np.linalg.norm(yref)
-        print("channels", channels, "forward error", err, flush=True)
+        print("channels", channels, "forward error", err, "max", _emax(Y.cpu().numpy(), yref), flush=True)
         assert err <= 3e-2, err
+        assert _emax(Y.cpu().numpy(), yref) <= BF16_TOL
     finally:
         L.lor_nn_free(nn)
         L.lor_free(h)
@@ -207,6 +220,7 @@ def test_training_and_replace_preconditioner(L, torch_dev):
         zref = ONN.preconditioner_replace(B, ONN.unflatten(wn, shapes), rin)
         err = np.linalg.norm(z.cpu().numpy() - zref) / np.linalg.norm(zref)
         assert err <= 3e-2, err
+        assert _emax(z.cpu().numpy(), zref) <= BF16_TOL
         x = torch.zeros_like(rt)
         info = L.lor_pcg_solve(h, rt, x, rtol=1e-6, maxit=400, check=False)
         print("FCG with the network:", info.iters, info.status, flush=True)
@@ -218,8 +232,9 @@ def test_training_and_replace_preconditioner(L, torch_dev):
         torch.cuda.synchronize()
         zw = ONN.preconditioner_warmstart(B, ONN.unflatten(wn, shapes), rin)
         errw = np.linalg.norm(z.cpu().numpy() - zw) / np.linalg.norm(zw)
-        print("warm start parity", errw, flush=True)
+        print("warm start parity", errw, "max", _emax(z.cpu().numpy(), zw), flush=True)
         assert errw <= 3e-2, errw
+        assert _emax(z.cpu().numpy(), zw) <= BF16_TOL
         x.zero_()
         infow = L.lor_pcg_solve(h, rt, x, rtol=1e-6, maxit=400, check=False)
         print("FCG with the warm start:", infow.iters, infow.status, flush=True)
@@ -281,10 +296,12 @@ def test_p6_grid_forward_replace_warmstart(channels, L, torch_dev):
         assert err <= 3e-2, err
         # every patch's output, not just the norm over all of them
         Yg = Y.cpu().numpy()
+        assert _emax(Yg, yref) <= BF16_TOL
         for j in range(J):
             nj = np.linalg.norm(yref[j])
             if nj > 0:
                 assert np.linalg.norm(Yg[j] - yref[j]) <= 5e-2 * nj, j
+                assert _emax(Yg[j], yref[j]) <= 5e-2, j
         B = S.SchwarzLOR(mesh, p)
         rin = r.cpu().numpy()
         z = torch.empty_like(r)
@@ -293,15 +310,17 @@ def test_p6_grid_forward_replace_warmstart(channels, L, torch_dev):
         torch.cuda.synchronize()
         zref = ONN.preconditioner_replace(B, P, rin)
         err = np.linalg.norm(z.cpu().numpy() - zref) / np.linalg.norm(zref)
-        print("replace parity", err, flush=True)
+        print("replace parity", err, "max", _emax(z.cpu().numpy(), zref), flush=True)
         assert err <= 3e-2, err
+        assert _emax(z.cpu().numpy(), zref) <= BF16_TOL
         L.lor_nn_attach(h, nn, L.LOR_NN_WARMSTART)
         L.lor_apply_P(h, r, z)
         torch.cuda.synchronize()
         zw = ONN.preconditioner_warmstart(B, P, rin)
         errw = np.linalg.norm(z.cpu().numpy() - zw) / np.linalg.norm(zw)
-        print("warm start parity", errw, flush=True)
+        print("warm start parity", errw, "max", _emax(z.cpu().numpy(), zw), flush=True)
         assert errw <= 3e-2, errw
+        assert _emax(z.cpu().numpy(), zw) <= BF16_TOL
         L.lor_nn_attach(h, None, L.LOR_NN_OFF)
     finally:
         L.lor_nn_free(nn)

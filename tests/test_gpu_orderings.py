@@ -111,7 +111,9 @@ def test_pou_weights(case, precision, L, torch_dev):
         if precision == "fp64":
             assert np.abs(zg - zref).max() <= 1e-12 * np.abs(zref).max()
         else:
+            # float32 parity bound, element by element (as in the CG tests)
             assert np.linalg.norm(zg - zref) <= 2e-5 * np.linalg.norm(zref)
+            assert np.abs(zg - zref).max() <= 2e-6 * np.abs(zref).max()
         K = HO.cg_stiffness(mesh, p)
         x = torch.zeros_like(r)
         info = L.lor_pcg_solve(h, r, x, rtol=1e-10, maxit=500)
