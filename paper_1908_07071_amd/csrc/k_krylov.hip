@@ -40,6 +40,38 @@ __global__ __launch_bounds__(256) void k_dot(const double *__restrict__ a,
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// partials of a.b and a.c in one pass over a (flexible CG: z.r and z.rold);
+// each partial adds its terms in the order k_dot does
+__global__ __launch_bounds__(256) void k_dot2(const double *__restrict__ a,
+                                              const double *__restrict__ b,
+                                              const double *__restrict__ c, int64_t n,
+                                              double *__restrict__ pb, double *__restrict__ pc,
+                                              const double *flag) {
+  if (flag && flag[S_DONE] != 0.0) return;
+  __shared__ double rb[256], rc[256];
+  double ab = 0.0, ac = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const double ai = a[i];
+    ab += ai * b[i];
+    ac += ai * c[i];
+  }
+  rb[threadIdx.x] = ab;
+  rc[threadIdx.x] = ac;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      rb[threadIdx.x] += rb[threadIdx.x + h];
+      rc[threadIdx.x] += rc[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    pb[blockIdx.x] = rb[0];
+    pc[blockIdx.x] = rc[0];
+  }
+}
+
 // x += alpha p ; r -= alpha q ; (optionally rold = r before) ; partial ||r||^2
 __global__ __launch_bounds__(256) void k_cg_update(double *__restrict__ x, double *__restrict__ r,
                                                    double *__restrict__ rold,
@@ -185,6 +217,12 @@ int red_blocks(int64_t n) { return grid_for(n, 256); }
 hipError_t launch_dot_partials(const double *a, const double *b, int64_t n, double *partials,
                                const double *flag, hipStream_t st) {
   k_dot<<<grid_for(n, 256), 256, 0, st>>>(a, b, n, partials, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot2_partials(const double *a, const double *b, const double *c, int64_t n,
+                                double *pb, double *pc, const double *flag, hipStream_t st) {
+  k_dot2<<<grid_for(n, 256), 256, 0, st>>>(a, b, c, n, pb, pc, flag);
   return hipGetLastError();
 }
 

@@ -716,8 +716,10 @@ int pcg_iterations(lor_handle *h, Work &w, double *x, int count, hipStream_t st)
     HIPCHK(launch_finalize(s, w.part, nbv, FIN_RR, nullptr, st));
     rc = apply_P_impl(h, w, w.r, w.z, s, st);
     if (rc != LOR_OK) return rc;
-    HIPCHK(launch_dot_partials(w.r, w.z, N, w.part, s, st));
-    if (fcg) HIPCHK(launch_dot_partials(w.z, w.rold, N, w.part2, s, st));
+    if (fcg)
+      HIPCHK(launch_dot2_partials(w.z, w.r, w.rold, N, w.part, w.part2, s, st));
+    else
+      HIPCHK(launch_dot_partials(w.r, w.z, N, w.part, s, st));
     HIPCHK(launch_finalize(s, w.part, nbv, fcg ? FIN_FCG : FIN_RHO, fcg ? w.part2 : nullptr, st));
     HIPCHK(launch_p_update(w.p, zero_q ? w.q : nullptr, w.z, N, s, st));
   }

@@ -347,6 +347,9 @@ constexpr int kRedBlocks = 1024;  // most blocks of a two-stage reduction
 int red_blocks(int64_t n);
 hipError_t launch_dot_partials(const double *a, const double *b, int64_t n, double *partials,
                                const double *flag, hipStream_t st);
+// a.b and a.c partials in one pass over a
+hipError_t launch_dot2_partials(const double *a, const double *b, const double *c, int64_t n,
+                                double *pb, double *pc, const double *flag, hipStream_t st);
 hipError_t launch_finalize(double *scal, const double *partials, int count, int which,
                            const double *partials2, hipStream_t st);
 hipError_t launch_cg_update(double *x, double *r, double *rold, const double *p, const double *q,
