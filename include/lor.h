@@ -413,6 +413,14 @@ int lor_nn_free(lor_nn_t *nn);
  * (bfloat16 bit patterns, DEVICE); M, N, K multiples of 16. */
 int lor_bf16_gemm(int M, int N, int K, const uint16_t *A, int64_t ai, int64_t ak,
                   const uint16_t *B, int64_t bk, int64_t bj, float *C, int64_t ldc, void *stream);
+/* The float64 matrix-core product of the coarse inverse's set-up (the
+ * rank-b updates of blocked Gauss-Jordan elimination, Section 3.2), exposed
+ * for tests: C = alpha A B + beta C, row major, A(i,k) = A[i lda + k],
+ * B(k,j) = B[k ldb + j], C(i,j) = C[i ldc + j], all DEVICE, any m, n, k >= 0
+ * (lda >= k, ldb >= n, ldc >= n); with beta == 0 C is not read.  Enqueued on
+ * the stream (no synchronization).  LOR_EINVAL for bad sizes or pointers. */
+int lor_f64_gemm(int m, int n, int k, double alpha, const double *A, int64_t lda, const double *B,
+                 int64_t ldb, double beta, double *C, int64_t ldc, void *stream);
 
 /* Integer maps for parity checks, HOST output.  If host_out is NULL only
  * *len is set.  which:

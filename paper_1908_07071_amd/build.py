@@ -30,6 +30,7 @@ SOURCES = [
     ("k_krylov.hip", []),
     ("k_dg.hip", []),
     ("coarse_inverse.cpp", []),
+    ("k_dgemm.hip", []),
     ("k_nn.hip", []),
     ("k_nnconv.hip", []),
     ("nn_api.cpp", []),
@@ -75,10 +76,8 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(*s), SOURCES))
     tmp = LIB + ".tmp"
-    # rocBLAS: only its plain float64 GEMM (trailing updates of the blocked
-    # Gauss-Jordan inverse of the coarse matrix at set-up)
-    cmd = [_hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs, "-lpthread",
-           "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+    # every GPU kernel is built from the sources above; only the HIP runtime is linked
+    cmd = [_hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

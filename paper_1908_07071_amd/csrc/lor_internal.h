@@ -216,6 +216,10 @@ hipError_t launch_gemv(int n, const double *A, const double *x, double *y, const
 // y = A x with the float32 copy of a float64 matrix (float64 products and sums)
 hipError_t launch_gemv_f32(int n, const float *A, const double *x, double *y, const double *flag,
                            hipStream_t st);
+// C = alpha A B + beta C in float64 on the matrix cores (row major, any sizes)
+hipError_t launch_dgemm(int m, int n, int k, double alpha, const double *A, int64_t lda,
+                        const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+                        hipStream_t st);
 hipError_t launch_small_inverse(const double *M, int ldm, double *Minv, int bk, int *bad,
                                 hipStream_t st);
 hipError_t launch_copy_block(const double *src, int64_t lds, double *dst, int64_t ldd, int rows,

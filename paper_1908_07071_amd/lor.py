@@ -38,7 +38,7 @@ EXPORTED = [
     "lor_nn_param_count", "lor_nn_create", "lor_nn_get_params", "lor_nn_shape", "lor_nn_patch_data",
     "lor_nn_forward", "lor_nn_gradients", "lor_nn_train_step", "lor_nn_attach", "lor_nn_free",
     "lor_bf16_gemm", "lor_apply_P_noalloc", "lor_noalloc_scratch_bytes", "lor_workspace_bytes",
-    "lor_bind_workspace", "lor_element_coords", "lor_launch_order",
+    "lor_bind_workspace", "lor_element_coords", "lor_launch_order", "lor_f64_gemm",
 ]
 LOR_NN_OFF, LOR_NN_REPLACE, LOR_NN_WARMSTART = 0, 1, 2
 LOR_T_APPLY_A, LOR_T_PATCH, LOR_T_COARSE = 0, 1, 2
@@ -120,6 +120,8 @@ def _load():
         "lor_nn_free": (C.c_int, [vp]),
         "lor_bf16_gemm": (C.c_int, [C.c_int, C.c_int, C.c_int, vp, C.c_int64, C.c_int64, vp, C.c_int64,
                                     C.c_int64, vp, C.c_int64, vp]),
+        "lor_f64_gemm": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, vp, C.c_int64, vp, C.c_int64,
+                                   C.c_double, vp, C.c_int64, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -440,6 +442,13 @@ def lor_nn_attach(h, nn, mode: int):
 
 def lor_nn_free(nn):
     _check(_lib.lor_nn_free(nn), "lor_nn_free")
+
+
+def lor_f64_gemm(m, n, k, alpha, A, lda, B, ldb, beta, Cmat, ldc, stream=None):
+    """C = alpha A B + beta C on the device (row major, float64 tensors)."""
+    _check(_lib.lor_f64_gemm(int(m), int(n), int(k), float(alpha), _dev(A, "A"), int(lda), _dev(B, "B"),
+                             int(ldb), float(beta), _dev(Cmat, "C"), int(ldc), _stream(stream)),
+           "lor_f64_gemm")
 
 
 def lor_bf16_gemm(M, N, K, A, ai, ak, B, bk, bj, Cmat, ldc, stream=None):
