@@ -166,7 +166,13 @@ typedef struct {
   int launch_order;    /* LOR_LAUNCH_*: the order in which the vertex-patch
                           kernel's workgroups take the patches            */
   int operator_geometry; /* LOR_GEOM_*                                      */
-  int reserved[1];     /* must be zero                                      */
+  int nn_fallback;     /* with a patch network attached (lor_nn_attach):
+                          1 (default) = lor_pcg_solve leaves the network for
+                          the patch V-cycles, restarting flexible CG from
+                          the current iterate's true residual, when the
+                          iteration breaks down or stalls (the recursive
+                          residual falls less than 2x over 16 iterations);
+                          0 = the network to the end                     */
 } lor_options_t;
 
 /* Geometric factors of the operator.  LOR_GEOM_STORED (default): computed
@@ -199,7 +205,9 @@ typedef struct {
   double t_solve;      /* seconds, measured with HIP events                */
   double t_setup;      /* seconds lor_setup took for this handle (host clock) */
   int    replacements; /* residual replacements (restarts from b - A x)    */
-  int    reserved;
+  int    fallback_iter; /* iteration at which a network-preconditioned solve
+                           switched to the patch V-cycles (nn_fallback);
+                           -1 if it did not                                */
 } lor_solve_info_t;
 
 /* Fill *opt with the defaults (FP64, MDF, PCG, all cores). */

@@ -743,6 +743,61 @@ int pcg_finish(lor_handle *h, Work &w, const double *b, const double *x, hipStre
 
 constexpr int kMaxReplace = 4;  // residual replacements per solve
 
+// Enqueues a restart of (flexible) CG from the true residual left in w.tmp
+// by pcg_finish (rt = its squared norm): r = b - A x, z = B r, rho = r.z,
+// p = z; the iteration count is kept.
+int pcg_restart(lor_handle *h, Work &w, double rt, hipStream_t st) {
+  const int64_t N = h->ndofs;
+  double *s = w.scal;
+  HIPCHK(launch_copy(w.r, w.tmp, N, st));
+  HIPCHK(launch_fill(s + S_DONE, 1, 0.0, st));
+  HIPCHK(launch_fill(s + S_FAIL, 1, 0.0, st));
+  HIPCHK(launch_fill(s + S_RR, 1, rt, st));
+  int rc = apply_P_impl(h, w, w.r, w.z, s, st);
+  if (rc != LOR_OK) return rc;
+  HIPCHK(launch_dot_partials(w.r, w.z, N, w.part, s, st));
+  HIPCHK(launch_finalize(s, w.part, red_blocks(N), FIN_RHO, nullptr, st));
+  HIPCHK(launch_copy(w.p, w.z, N, st));
+  if (h->method == LOR_CG && !apply_cg_uses_skeleton(h->md)) HIPCHK(launch_fill(w.q, N, 0.0, st));
+  return LOR_OK;
+}
+
+// Network-preconditioned solves (lor_nn_attach, nn_fallback): leave the
+// network for the patch V-cycles when flexible CG breaks down or stalls.
+// Called at every chunk boundary with the scalars in w.h_scal; rr_hist keeps
+// the recursive residual of the last two boundaries.  On a switch the true
+// residual of the current iterate is computed (x and r restart from b if
+// the iterate is not finite) and CG restarts from it with the V-cycles.
+constexpr double kStall = 0.25;  // ||r||^2 must fall by 4x (||r|| by 2x) per 16 iterations
+int nn_fallback_check(lor_handle *h, Work &w, const double *b, double *x, double rtol, int maxit,
+                      double rr_hist[2], int *fallback_iter, bool *restarted, hipStream_t st) {
+  *restarted = false;
+  if (*fallback_iter >= 0 || !h->nn || h->nn_mode == LOR_NN_OFF || !h->opt.nn_fallback) return LOR_OK;
+  const double *hs = w.h_scal;
+  const double rr = hs[S_RR], tol2 = rtol * rtol * hs[S_BB];
+  const bool fail = hs[S_FAIL] != 0.0;
+  const bool stalled = !(rr <= kStall * rr_hist[0]);
+  rr_hist[0] = rr_hist[1];
+  rr_hist[1] = rr;
+  const int it = int(hs[S_ITERS]);
+  if (!fail && (rr <= tol2 || !stalled)) return LOR_OK;
+  if (it >= maxit) return LOR_OK;  // the iteration budget is spent
+  *fallback_iter = it;
+  h->nn_mode = LOR_NN_OFF;  // restored by lor_pcg_solve on exit
+  int rc = pcg_finish(h, w, b, x, st);
+  if (rc != LOR_OK) return rc;
+  double rt = w.h_scal[S_RRTRUE];
+  if (!std::isfinite(rt)) {
+    HIPCHK(launch_fill(x, h->ndofs, 0.0, st));
+    HIPCHK(launch_copy(w.tmp, b, h->ndofs, st));
+    rt = w.h_scal[S_BB];
+  }
+  rc = pcg_restart(h, w, rt, st);
+  if (rc != LOR_OK) return rc;
+  *restarted = true;
+  return LOR_OK;
+}
+
 // Residual replacement after pcg_finish: decides from w.h_scal whether the
 // recursive residual met rtol while the true one did not, and if so enqueues
 // a restart from the true residual: r = b - A x (left in w.tmp by
@@ -761,24 +816,15 @@ int pcg_replace(lor_handle *h, Work &w, double rtol, int maxit, int &nrep, doubl
     return LOR_OK;
   last_true = rt;
   ++nrep;
-  const int64_t N = h->ndofs;
-  double *s = w.scal;
-  HIPCHK(launch_copy(w.r, w.tmp, N, st));
-  HIPCHK(launch_fill(s + S_DONE, 1, 0.0, st));
-  HIPCHK(launch_fill(s + S_RR, 1, rt, st));
-  int rc = apply_P_impl(h, w, w.r, w.z, s, st);
+  int rc = pcg_restart(h, w, rt, st);
   if (rc != LOR_OK) return rc;
-  HIPCHK(launch_dot_partials(w.r, w.z, N, w.part, s, st));
-  HIPCHK(launch_finalize(s, w.part, red_blocks(N), FIN_RHO, nullptr, st));
-  HIPCHK(launch_copy(w.p, w.z, N, st));
-  if (h->method == LOR_CG && !apply_cg_uses_skeleton(h->md)) HIPCHK(launch_fill(w.q, N, 0.0, st));
   *restarted = true;
   return LOR_OK;
 }
 
 // Status and info from the scalars in w.h_scal.
 int pcg_status(const lor_handle *h, const Work &w, double rtol, double t_solve, int nrep,
-               lor_solve_info_t *info) {
+               lor_solve_info_t *info, int fallback_iter = -1) {
   const double *hs = w.h_scal;
   const double bb = hs[S_BB], rr = hs[S_RR], rt = hs[S_RRTRUE], fail = hs[S_FAIL];
   int status = LOR_OK;
@@ -796,7 +842,7 @@ int pcg_status(const lor_handle *h, const Work &w, double rtol, double t_solve, 
     info->t_solve = t_solve;
     info->t_setup = h->t_setup;
     info->replacements = nrep;
-    info->reserved = 0;
+    info->fallback_iter = fallback_iter;
   }
   return status;
 }
@@ -861,6 +907,7 @@ int lor_default_options(lor_options_t *opt) {
   opt->ordering = LOR_ORD_MDF;
   opt->flexible = 0;
   opt->nthreads = 0;
+  opt->nn_fallback = 1;
   return LOR_OK;
 }
 
@@ -926,7 +973,7 @@ int lor_setup(const lor_mesh_t *mesh, int p, int method, double penalty, const l
     if (opt->launch_order < LOR_LAUNCH_AUTO || opt->launch_order > LOR_LAUNCH_BUCKETS) return LOR_EINVAL;
     if (opt->operator_geometry != LOR_GEOM_STORED && opt->operator_geometry != LOR_GEOM_ONFLY)
       return LOR_EINVAL;
-    if (opt->reserved[0] != 0) return LOR_EINVAL;
+    if (opt->nn_fallback != 0 && opt->nn_fallback != 1) return LOR_EINVAL;
   } else {
     lor_default_options(&h->opt);
   }
@@ -1159,10 +1206,17 @@ int lor_pcg_solve(lor_handle_t *h, const double *b, double *x, double rtol, int 
   hipStream_t st = static_cast<hipStream_t>(stream);
   Work &w = h->w;
   HIPCHK(hipEventRecord(h->ev0, st));
+  // the network mode is switched off by a fallback for the rest of this
+  // solve only
+  struct ModeGuard {
+    lor_handle *h;
+    int mode;
+    ~ModeGuard() { h->nn_mode = mode; }
+  } guard{h, h->nn_mode};
   int rc = pcg_init(h, w, b, x, rtol, maxit, st);
   if (rc != LOR_OK) return rc;
-  int nrep = 0;
-  double last_true = HUGE_VAL;
+  int nrep = 0, fallback_iter = -1;
+  double last_true = HUGE_VAL, rr_hist[2] = {HUGE_VAL, HUGE_VAL};
   for (;;) {
     bool done = maxit == 0;
     while (!done) {
@@ -1171,6 +1225,10 @@ int lor_pcg_solve(lor_handle_t *h, const double *b, double *x, double rtol, int 
       HIPCHK(hipMemcpyAsync(w.h_scal, w.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       done = w.h_scal[S_DONE] != 0.0;  // also set on the device at maxit
+      bool switched = false;
+      rc = nn_fallback_check(h, w, b, x, rtol, maxit, rr_hist, &fallback_iter, &switched, st);
+      if (rc != LOR_OK) return rc;
+      if (switched) done = false;
     }
     HIPCHK(hipEventRecord(h->ev1, st));
     rc = pcg_finish(h, w, b, x, st);
@@ -1182,7 +1240,7 @@ int lor_pcg_solve(lor_handle_t *h, const double *b, double *x, double rtol, int 
   }
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-  return pcg_status(h, w, rtol, ms * 1e-3, nrep, info);
+  return pcg_status(h, w, rtol, ms * 1e-3, nrep, info, fallback_iter);
 }
 
 int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const double *const *b,

@@ -62,13 +62,13 @@ class lor_options_t(C.Structure):
                 ("nthreads", C.c_int), ("prolong_weights", C.c_int), ("patch_mode", C.c_int),
                 ("sweep_grid_rows", C.c_int), ("nslabs", C.c_int),
                 ("deterministic", C.c_int), ("launch_order", C.c_int), ("operator_geometry", C.c_int),
-                ("reserved", C.c_int * 1)]
+                ("nn_fallback", C.c_int)]
 
 
 class lor_solve_info_t(C.Structure):
     _fields_ = [("iters", C.c_int), ("status", C.c_int), ("rel_res", C.c_double),
                 ("rel_res_true", C.c_double), ("t_solve", C.c_double), ("t_setup", C.c_double),
-                ("replacements", C.c_int), ("reserved", C.c_int)]
+                ("replacements", C.c_int), ("fallback_iter", C.c_int)]
 
 
 def _load():

@@ -72,10 +72,12 @@ def test_bf16_gemm_layouts(L, torch_dev):
     assert np.abs(Cg.cpu().numpy() - ref).max() <= 1e-5 * np.abs(ref).max()
 
 
-def _problem(L, n=2, p=3, seed=9):
+def _problem(L, n=2, p=3, seed=9, fallback=1):
     V = inputs.structured_vertices(3, n, 0.1, seed=seed)
     mesh = M.make_mesh(3, [n] * 3, V)
-    h = L.lor_setup(3, n, V, p)
+    opt = L.lor_default_options()
+    opt.nn_fallback = fallback
+    h = L.lor_setup(3, n, V, p, options=opt)
     return h, mesh, p
 
 
@@ -188,7 +190,8 @@ def test_training_and_replace_preconditioner(L, torch_dev):
     as a warm start of the patch V-cycles it matches the float64 reference
     warm start and flexible CG converges in about the V-cycle's iterations."""
     torch = torch_dev
-    h, mesh, p = _problem(L)
+    # the network alone, to the end of each solve (no V-cycle fallback)
+    h, mesh, p = _problem(L, fallback=0)
     params = inputs.nn_initial_params(C, seed=5)
     nn = L.lor_nn_create(h, C, params, max_batch=64)
     try:
@@ -325,3 +328,39 @@ def test_p6_grid_forward_replace_warmstart(channels, L, torch_dev):
     finally:
         L.lor_nn_free(nn)
         L.lor_free(h)
+
+
+def test_vcycle_fallback(L, torch_dev):
+    """An untrained network in place of the patch V-cycles: with the
+    fallback (the default) flexible CG leaves it for the V-cycles once it
+    breaks down or stalls and still reaches the tolerance, the true residual
+    included; without it the network runs to the end of the solve."""
+    torch = torch_dev
+    for fallback in (1, 0):
+        h, mesh, p = _problem(L, fallback=fallback)
+        nn = L.lor_nn_create(h, C, inputs.nn_initial_params(C, seed=11), max_batch=32)
+        try:
+            N = L.lor_ndofs(h)
+            r = torch.tensor(inputs.gaussian_rhs(N, 12), device="cuda")
+            x0 = torch.zeros_like(r)
+            info0 = L.lor_pcg_solve(h, r, x0, rtol=1e-8, maxit=400)
+            assert info0.fallback_iter == -1
+            L.lor_nn_attach(h, nn, L.LOR_NN_REPLACE)
+            x = torch.zeros_like(r)
+            info = L.lor_pcg_solve(h, r, x, rtol=1e-8, maxit=400, check=False)
+            print("fallback", fallback, "status", info.status, "iterations", info.iters, "switched at",
+                  info.fallback_iter, "V-cycle alone", info0.iters, flush=True)
+            if fallback:
+                assert info.status == L.LOR_OK and info.rel_res_true <= 1e-8, (info.status, info.rel_res_true)
+                assert 0 <= info.fallback_iter < info.iters
+                # the network stays attached for the next solve
+                x.zero_()
+                info2 = L.lor_pcg_solve(h, r, x, rtol=1e-8, maxit=400, check=False)
+                assert info2.fallback_iter >= 0
+            else:
+                assert info.fallback_iter == -1
+        finally:
+            L.lor_nn_attach(h, None, L.LOR_NN_OFF)
+            L.lor_nn_free(nn)
+            L.lor_free(h)
+
