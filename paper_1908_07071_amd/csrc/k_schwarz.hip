@@ -470,15 +470,28 @@ __device__ __forceinline__ void residual(T *R, const T *B, const T *X, const Box
 // values wy[block][G^d] times dscale[block], patches jfirst + block) and
 // scatter y_j + V_j(r_j - A_j y_j).
 template <int DIM, typename T, typename ST, int W, bool WARM>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_patch_vcycle(PatchArgs pa, const double *__restrict__ r,
-                                                     double *__restrict__ z, const double *flag,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_patch_vcycle(PatchArgs pa, const double *__restrict__ r_in,
+                                                     double *__restrict__ z_in, const double *flag_in,
                                                      float *__restrict__ dense,
                                                      const double *__restrict__ dscale,
                                                      const float *__restrict__ wy, int jfirst) {
+  const double *__restrict__ r = r_in;
+  double *__restrict__ z = z_in;
+  const double *flag = flag_in;
+  int slot = int(blockIdx.x);  // the block's place in the launch order
+  if (!WARM && pa.nrhs > 0) {
+    // several right-hand sides: the blocks of one patch sit 8 apart (same XCD)
+    const int b = int(blockIdx.x), t = b >> 3, k = t % pa.nrhs;
+    slot = (t / pa.nrhs) * 8 + (b & 7);
+    if (slot >= pa.nv[0] * pa.nv[1] * (DIM == 3 ? pa.nv[2] : 1)) return;
+    r = pa.rs[k];
+    z = pa.zs[k];
+    flag = pa.flags[k];
+  }
   if (flag && flag[S_DONE] != 0.0) return;
   extern __shared__ __align__(16) char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
-  int j = jfirst + int(blockIdx.x);
+  int j = jfirst + slot;
   if (!WARM && pa.perm) j = pa.perm[j];
   if (pa.color >= 0) {
     // the patches of one vertex-parity class: their level-0 boxes are
@@ -778,6 +791,7 @@ hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r,
       pc.plain = 0;
       pc.color = color;
       pc.perm = nullptr;
+      pc.nrhs = 0;
       int cnt = 1;
       for (int d = 0; d < pa.md.dim; ++d) cnt *= (pa.nv[d] - ((color >> d) & 1) + 1) / 2;
       pc.plain = 1;
@@ -802,12 +816,41 @@ hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r,
   return launch_t<2, double, double, false>(pa, npatch, r, z, flag, dense, dscale, nullptr, 0, st);
 }
 
+hipError_t launch_patch_vcycle_multi(const PatchArgs &pa, int npatch, int nrhs,
+                                     const double *const *r, double *const *z,
+                                     const double *const *flags, hipStream_t st) {
+  if (nrhs < 1 || nrhs > kMaxRhs || pa.plain || !r || !z) return hipErrorInvalidValue;
+  int J = 1;
+  for (int d = 0; d < pa.md.dim; ++d) J *= pa.nv[d];
+  if (npatch != J) return hipErrorInvalidValue;
+  if (npatch <= 0) return hipSuccess;
+  PatchArgs pm = pa;
+  pm.nrhs = nrhs;
+  for (int k = 0; k < kMaxRhs; ++k) {
+    pm.rs[k] = k < nrhs ? r[k] : nullptr;
+    pm.zs[k] = k < nrhs ? z[k] : nullptr;
+    pm.flags[k] = k < nrhs && flags ? flags[k] : nullptr;
+    if (k < nrhs && (!pm.rs[k] || !pm.zs[k])) return hipErrorInvalidValue;
+  }
+  const int64_t blocks = int64_t((npatch + 7) / 8) * 8 * nrhs;
+  if (blocks > int64_t(INT32_MAX)) return hipErrorInvalidValue;
+  if (pa.fp32) {
+    if (pa.md.dim == 3)
+      return launch_t<3, float, float, false>(pm, int(blocks), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, st);
+    return launch_t<2, float, float, false>(pm, int(blocks), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, st);
+  }
+  if (pa.md.dim == 3)
+    return launch_t<3, double, double, false>(pm, int(blocks), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, st);
+  return launch_t<2, double, double, false>(pm, int(blocks), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, st);
+}
+
 hipError_t launch_patch_vcycle_warm(const PatchArgs &pa, int first, int count, const double *r,
                                     double *z, const float *y, const double *scale,
                                     const double *flag, hipStream_t st) {
   if (pa.md.dim != 3 || !y || !scale || first < 0 || count < 0 || pa.plain) return hipErrorInvalidValue;
   PatchArgs pw = pa;
   pw.perm = nullptr;  // predictions and scales are indexed by block
+  pw.nrhs = 0;
   if (pa.fp32)
     return launch_t<3, float, float, true>(pw, count, r, z, flag, nullptr, scale, y, first, st);
   return launch_t<3, double, double, true>(pw, count, r, z, flag, nullptr, scale, y, first, st);

@@ -576,29 +576,62 @@ struct Span {
   }
 };
 
-// Conforming Schwarz preconditioner on L-vectors (eq. as).
-int apply_P_cg(lor_handle *h, Work &w, const double *r, double *z, const double *flag,
-               hipStream_t st) {
-  if (h->opt.patch_mode == LOR_PATCH_SINGLE) {
-    Span sp(h, LOR_T_PATCH, st);
-    return apply_boxes(h, r, z, flag, st);
+// The preconditioner in three parts, so that a batch can put the patch
+// corrections of several right-hand sides of one matrix into one launch:
+//   pre:     (DG) r_L = E^T r ; the coarse correction z_L = P_0 A_0^-1 P_0^T r_L
+//            (it initialises z_L);
+//   patches: z_L += sum_j P_j^T V_j(P_j r_L) (or the box patches, the network);
+//   post:    (DG) z = D_B^-1 r on element-boundary nodes + E z_L.
+// (r_L, z_L) are (r, z) for CG and the handle's L-vectors for DG (eq. dg-as).
+void patch_io(const lor_handle *h, const Work &w, const double *r, double *z, const double **pr,
+              double **pz) {
+  if (h->method == LOR_CG) {
+    *pr = r;
+    *pz = z;
+  } else {
+    *pr = w.rL;
+    *pz = w.zL;
   }
+}
+
+int apply_P_pre(lor_handle *h, Work &w, const double *r, double *z, const double *flag,
+                hipStream_t st) {
+  const double *pr;
+  double *pz;
+  patch_io(h, w, r, z, &pr, &pz);
+  if (h->method != LOR_CG) HIPCHK(launch_dg_restrict(h->md, r, w.rL, flag, st));
+  if (h->opt.patch_mode == LOR_PATCH_SINGLE) return LOR_OK;  // the box V-cycle writes z_L
   if (h->nc > 0) {
     Span sp(h, LOR_T_COARSE, st);
-    HIPCHK(launch_coarse_restrict(h->md, h->d_gllx, r, w.rc, st));
+    HIPCHK(launch_coarse_restrict(h->md, h->d_gllx, pr, w.rc, st));
     if (h->d_A0inv_f)
       HIPCHK(launch_gemv_f32(h->nc, h->d_A0inv_f, w.rc, w.xc, flag, st));
     else
       HIPCHK(launch_gemv(h->nc, h->d_A0inv, w.rc, w.xc, flag, st));
-    HIPCHK(launch_coarse_prolong(h->md, h->d_gllx, w.xc, z, flag, st));
+    HIPCHK(launch_coarse_prolong(h->md, h->d_gllx, w.xc, pz, flag, st));
   } else {
-    HIPCHK(launch_fill(z, h->ncg, 0.0, st));
+    HIPCHK(launch_fill(pz, h->ncg, 0.0, st));
   }
+  return LOR_OK;
+}
+
+int apply_P_patches(lor_handle *h, Work &w, const double *r, double *z, const double *flag,
+                    hipStream_t st) {
+  const double *pr;
+  double *pz;
+  patch_io(h, w, r, z, &pr, &pz);
   Span sp(h, LOR_T_PATCH, st);
-  if (box_mode(h->opt.patch_mode)) return apply_boxes(h, r, z, flag, st);
-  if (h->nn && h->nn_mode == LOR_NN_REPLACE) return nn_apply_patches(h->nn, r, z, flag, st);
-  if (h->nn && h->nn_mode == LOR_NN_WARMSTART) return nn_apply_patches_warm(h->nn, r, z, flag, st);
-  HIPCHK(launch_patch_vcycle(h->pa, h->J, r, z, flag, st));
+  if (h->opt.patch_mode == LOR_PATCH_SINGLE || box_mode(h->opt.patch_mode))
+    return apply_boxes(h, pr, pz, flag, st);
+  if (h->nn && h->nn_mode == LOR_NN_REPLACE) return nn_apply_patches(h->nn, pr, pz, flag, st);
+  if (h->nn && h->nn_mode == LOR_NN_WARMSTART) return nn_apply_patches_warm(h->nn, pr, pz, flag, st);
+  HIPCHK(launch_patch_vcycle(h->pa, h->J, pr, pz, flag, st));
+  return LOR_OK;
+}
+
+int apply_P_post(lor_handle *h, Work &w, const double *r, double *z, const double *flag,
+                 hipStream_t st) {
+  if (h->method != LOR_CG) HIPCHK(launch_dg_prolong_jacobi(h->md, r, h->d_dinv, w.zL, z, flag, st));
   return LOR_OK;
 }
 
@@ -606,12 +639,17 @@ int apply_P_cg(lor_handle *h, Work &w, const double *r, double *z, const double 
 // E B E^T r.
 int apply_P_impl(lor_handle *h, Work &w, const double *r, double *z, const double *flag,
                  hipStream_t st) {
-  if (h->method == LOR_CG) return apply_P_cg(h, w, r, z, flag, st);
-  HIPCHK(launch_dg_restrict(h->md, r, w.rL, flag, st));
-  int rc = apply_P_cg(h, w, w.rL, w.zL, flag, st);
-  if (rc != LOR_OK) return rc;
-  HIPCHK(launch_dg_prolong_jacobi(h->md, r, h->d_dinv, w.zL, z, flag, st));
-  return LOR_OK;
+  int rc = apply_P_pre(h, w, r, z, flag, st);
+  if (rc == LOR_OK) rc = apply_P_patches(h, w, r, z, flag, st);
+  if (rc == LOR_OK) rc = apply_P_post(h, w, r, z, flag, st);
+  return rc;
+}
+
+// Whether the batch can put the patch corrections of several right-hand
+// sides of this handle into one launch (vertex patches, atomics, V-cycles).
+bool multi_rhs_patches(const lor_handle *h) {
+  return h->J > 0 && h->opt.patch_mode == LOR_PATCH_VERTEX && !h->pa.plain &&
+         !(h->nn && h->nn_mode != LOR_NN_OFF);
 }
 
 }  // namespace
@@ -692,36 +730,87 @@ int pcg_init(lor_handle *h, Work &w, const double *b, double *x, double rtol, in
   return LOR_OK;
 }
 
-// Enqueues `count` (flexible) CG iterations; every kernel returns at once
+// One (flexible) CG iteration in three parts around the preconditioner's
+// patch corrections (see apply_P_pre): pre = q = A p, alpha, x and r, the
+// recursive residual, and the preconditioner's first part; post = its last
+// part, rho (and for FCG z.r_old), beta and p.  Every kernel returns at once
 // after the device-side convergence flag is set, so the sequence can be
 // replayed as a graph until the flag is seen on the host.
-int pcg_iterations(lor_handle *h, Work &w, double *x, int count, hipStream_t st) {
-  const int64_t N = h->ndofs;
-  double *s = w.scal;
+bool uses_fcg(const lor_handle *h) {
   // flexible CG whenever the preconditioner is not a fixed SPD operator
   // (float32 patch solves, or the nonlinear patch network)
-  const bool fcg = h->opt.flexible != 0 || h->opt.precision == LOR_PREC_MIXED ||
-                   h->opt.prolong_weights == LOR_PROLONG_POU ||
-                   (h->nn && h->nn_mode != LOR_NN_OFF);
+  return h->opt.flexible != 0 || h->opt.precision == LOR_PREC_MIXED ||
+         h->opt.prolong_weights == LOR_PROLONG_POU || (h->nn && h->nn_mode != LOR_NN_OFF);
+}
+
+int pcg_iter_pre(lor_handle *h, Work &w, double *x, hipStream_t st) {
+  const int64_t N = h->ndofs;
+  double *s = w.scal;
+  const int nba = apply_cg_blocks(h->md, h->method != LOR_CG);
+  const int nbv = red_blocks(N);
+  int rc = apply_A_impl(h, w, w.p, w.q, w.part, s, st);
+  if (rc != LOR_OK) return rc;
+  HIPCHK(launch_finalize(s, w.part, nba, FIN_PQ, nullptr, st));
+  HIPCHK(launch_cg_update(x, w.r, uses_fcg(h) ? w.rold : nullptr, w.p, w.q, N, s, w.part, st));
+  HIPCHK(launch_finalize(s, w.part, nbv, FIN_RR, nullptr, st));
+  return apply_P_pre(h, w, w.r, w.z, s, st);
+}
+
+int pcg_iter_post(lor_handle *h, Work &w, hipStream_t st) {
+  const int64_t N = h->ndofs;
+  double *s = w.scal;
+  const bool fcg = uses_fcg(h);
   // the operator writes q completely (DG, or CG through the skeleton gather);
   // otherwise q is accumulated atomically and must be cleared each iteration
   const bool zero_q = h->method == LOR_CG && !apply_cg_uses_skeleton(h->md);
-  const int nba = apply_cg_blocks(h->md, h->method != LOR_CG);
   const int nbv = red_blocks(N);
+  int rc = apply_P_post(h, w, w.r, w.z, s, st);
+  if (rc != LOR_OK) return rc;
+  if (fcg)
+    HIPCHK(launch_dot2_partials(w.z, w.r, w.rold, N, w.part, w.part2, s, st));
+  else
+    HIPCHK(launch_dot_partials(w.r, w.z, N, w.part, s, st));
+  HIPCHK(launch_finalize(s, w.part, nbv, fcg ? FIN_FCG : FIN_RHO, fcg ? w.part2 : nullptr, st));
+  HIPCHK(launch_p_update(w.p, zero_q ? w.q : nullptr, w.z, N, s, st));
+  return LOR_OK;
+}
+
+// Enqueues `count` iterations of one solve.
+int pcg_iterations(lor_handle *h, Work &w, double *x, int count, hipStream_t st) {
   for (int i = 0; i < count; ++i) {
-    int rc = apply_A_impl(h, w, w.p, w.q, w.part, s, st);
+    int rc = pcg_iter_pre(h, w, x, st);
+    if (rc == LOR_OK) rc = apply_P_patches(h, w, w.r, w.z, w.scal, st);
+    if (rc == LOR_OK) rc = pcg_iter_post(h, w, st);
     if (rc != LOR_OK) return rc;
-    HIPCHK(launch_finalize(s, w.part, nba, FIN_PQ, nullptr, st));
-    HIPCHK(launch_cg_update(x, w.r, fcg ? w.rold : nullptr, w.p, w.q, N, s, w.part, st));
-    HIPCHK(launch_finalize(s, w.part, nbv, FIN_RR, nullptr, st));
-    rc = apply_P_impl(h, w, w.r, w.z, s, st);
-    if (rc != LOR_OK) return rc;
-    if (fcg)
-      HIPCHK(launch_dot2_partials(w.z, w.r, w.rold, N, w.part, w.part2, s, st));
-    else
-      HIPCHK(launch_dot_partials(w.r, w.z, N, w.part, s, st));
-    HIPCHK(launch_finalize(s, w.part, nbv, fcg ? FIN_FCG : FIN_RHO, fcg ? w.part2 : nullptr, st));
-    HIPCHK(launch_p_update(w.p, zero_q ? w.q : nullptr, w.z, N, s, st));
+  }
+  return LOR_OK;
+}
+
+// Enqueues `count` iterations of up to kMaxRhs solves with the same handle in
+// lockstep: the patch corrections of all of them in one launch.
+int pcg_iterations_multi(lor_handle *h, Work *const *w, double *const *x, int n, int count,
+                         hipStream_t st) {
+  if (n < 1 || n > kMaxRhs) return LOR_EINVAL;
+  const double *pr[kMaxRhs];
+  double *pz[kMaxRhs];
+  const double *fl[kMaxRhs];
+  for (int k = 0; k < n; ++k) {
+    patch_io(h, *w[k], w[k]->r, w[k]->z, &pr[k], &pz[k]);
+    fl[k] = w[k]->scal;
+  }
+  for (int i = 0; i < count; ++i) {
+    for (int k = 0; k < n; ++k) {
+      int rc = pcg_iter_pre(h, *w[k], x[k], st);
+      if (rc != LOR_OK) return rc;
+    }
+    {
+      Span sp(h, LOR_T_PATCH, st);
+      HIPCHK(launch_patch_vcycle_multi(h->pa, h->J, n, pr, pz, fl, st));
+    }
+    for (int k = 0; k < n; ++k) {
+      int rc = pcg_iter_post(h, *w[k], st);
+      if (rc != LOR_OK) return rc;
+    }
   }
   return LOR_OK;
 }
@@ -1260,13 +1349,21 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
     lor_handle *h = nullptr;
     Work w;
     hipStream_t st = nullptr;
-    hipGraphExec_t chunk = nullptr;
     int64_t it = 0;
     bool done = false, final = false;
     int nrep = 0;
     double last_true = HUGE_VAL;
   };
+  // The right-hand sides of one problem run in lockstep in groups of up to
+  // kMaxRhs pairs (one captured chunk, the patch corrections of the group in
+  // one launch) where the handle's preconditioner allows it, else alone.
+  struct Group {
+    int first = 0, n = 1;
+    hipStream_t st = nullptr;
+    hipGraphExec_t chunk = nullptr;
+  };
   std::vector<Pair> pairs(npair);
+  std::vector<Group> groups;
   std::vector<hipStream_t> streams;
   hipEvent_t ready = nullptr, start = nullptr, stop = nullptr;
   int rc = LOR_OK;
@@ -1274,8 +1371,8 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
   // workspaces are cached on their handles (allocated the first time a
   // handle needs that many, freed by lor_free)
   auto cleanup = [&]() {
-    for (Pair &q : pairs)
-      if (q.chunk) (void)hipGraphExecDestroy(q.chunk);
+    for (Group &g : groups)
+      if (g.chunk) (void)hipGraphExecDestroy(g.chunk);
     for (hipStream_t t : streams) (void)hipStreamDestroy(t);
     if (ready) (void)hipEventDestroy(ready);
     if (start) (void)hipEventDestroy(start);
@@ -1291,7 +1388,16 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
     hipError_t e_ = (x);                                     \
     if (e_ != hipSuccess) return fail(hip_fail(e_, #x, __LINE__)); \
   } while (0)
-  const int ns = std::min(kBatchStreams, npair);
+  for (int i = 0; i < nprob; ++i) {
+    const int step = multi_rhs_patches(hs[i]) ? kMaxRhs : 1;
+    for (int j = 0; j < nrhs; j += step) {
+      Group g;
+      g.first = i * nrhs + j;
+      g.n = std::min(step, nrhs - j);
+      groups.push_back(g);
+    }
+  }
+  const int ns = std::min(kBatchStreams, int(groups.size()));
   for (int i = 0; i < ns; ++i) {
     hipStream_t t = nullptr;
     BCHK(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));  // default priority
@@ -1307,10 +1413,13 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
     // a handle may serve several problems: its pairs take consecutive
     // cached workspaces
     std::vector<std::pair<lor_handle *, int>> used;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      groups[gi].st = streams[gi % ns];
+      for (int k = groups[gi].first; k < groups[gi].first + groups[gi].n; ++k) pairs[k].st = groups[gi].st;
+    }
     for (int k = 0; k < npair; ++k) {
       Pair &q = pairs[k];
       q.h = hs[k / nrhs];
-      q.st = streams[k % ns];
       int slot = 0;
       bool found = false;
       for (auto &u : used)
@@ -1328,22 +1437,33 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
       q.w = q.h->bwork[slot];
     }
   }
-  // one captured chunk of iterations per pair (kernels become no-ops once the
-  // pair has converged, so the chunk is replayed until its flag is set)
-  for (int k = 0; k < npair; ++k) {
-    Pair &q = pairs[k];
+  // one captured chunk of iterations per group (kernels become no-ops once a
+  // pair has converged, so the chunk is replayed until every pair's flag is
+  // set)
+  for (Group &gr : groups) {
+    lor_handle *h = pairs[gr.first].h;
     hipGraph_t g = nullptr;
-    q.h->capturing = true;
-    BCHK(hipStreamBeginCapture(q.st, hipStreamCaptureModeThreadLocal));
-    rc = pcg_iterations(q.h, q.w, x[k], kChunk, q.st);
-    hipError_t e = hipStreamEndCapture(q.st, &g);
-    q.h->capturing = false;
+    h->capturing = true;
+    BCHK(hipStreamBeginCapture(gr.st, hipStreamCaptureModeThreadLocal));
+    if (gr.n > 1) {
+      Work *ws[kMaxRhs];
+      double *xs[kMaxRhs];
+      for (int k = 0; k < gr.n; ++k) {
+        ws[k] = &pairs[gr.first + k].w;
+        xs[k] = x[gr.first + k];
+      }
+      rc = pcg_iterations_multi(h, ws, xs, gr.n, kChunk, gr.st);
+    } else {
+      rc = pcg_iterations(h, pairs[gr.first].w, x[gr.first], kChunk, gr.st);
+    }
+    hipError_t e = hipStreamEndCapture(gr.st, &g);
+    h->capturing = false;
     if (rc != LOR_OK) {
       if (g) (void)hipGraphDestroy(g);
       return fail(rc);
     }
     BCHK(e);
-    e = hipGraphInstantiate(&q.chunk, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&gr.chunk, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     BCHK(e);
   }
@@ -1364,13 +1484,18 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
   for (;;) {
     for (;;) {
       bool any = false;
-      for (Pair &q : pairs) {
-        if (q.done) continue;
+      for (Group &gr : groups) {
+        bool live = false;
+        for (int k = gr.first; k < gr.first + gr.n; ++k) live = live || !pairs[k].done;
+        if (!live) continue;
         any = true;
-        BCHK(hipGraphLaunch(q.chunk, q.st));
-        BCHK(hipMemcpyAsync(q.w.h_scal, q.w.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
-                            q.st));
-        q.it += kChunk;
+        BCHK(hipGraphLaunch(gr.chunk, gr.st));
+        for (int k = gr.first; k < gr.first + gr.n; ++k) {
+          Pair &q = pairs[k];
+          BCHK(hipMemcpyAsync(q.w.h_scal, q.w.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                              q.st));
+          q.it += kChunk;
+        }
       }
       if (!any) break;
       for (hipStream_t t : streams) BCHK(hipStreamSynchronize(t));

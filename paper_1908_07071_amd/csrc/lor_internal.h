@@ -12,6 +12,7 @@
 namespace lor {
 
 constexpr int kMaxP = 14;          // largest supported polynomial degree
+constexpr int kMaxRhs = 4;         // right-hand sides per multi-RHS patch launch
 constexpr int kMaxLevels = 6;      // 1 + ceil(log2(16)) = 5, one spare
 constexpr int kMaxQ = kMaxP + 1;   // GLL points per direction
 
@@ -60,6 +61,13 @@ struct PatchArgs {
   int color;                         // parity class of this launch, -1: every patch
   const int *perm;                   // launch order: block b runs patch perm[b] (nullptr:
                                      //    vertex order)
+  // Several right-hand sides of one matrix in one launch (nrhs > 0, see
+  // launch_patch_vcycle_multi): right-hand side k reads rs[k], adds into
+  // zs[k] and stops at flags[k]; otherwise nrhs == 0.
+  int nrhs;
+  const double *rs[kMaxRhs];
+  double *zs[kMaxRhs];
+  const double *flags[kMaxRhs];
 };
 
 // Sweep block: the data of one ILU(0) triangular sweep (forward or backward)
@@ -237,6 +245,15 @@ hipError_t prepare_patch_vcycle(const PatchArgs &pa);
 hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r, double *z,
                                const double *flag, hipStream_t st, float *dense = nullptr,
                                const double *dscale = nullptr);
+// z_k += sum_j R_j^T V_j(R_j r_k) for nrhs <= kMaxRhs right-hand sides of one
+// matrix in one launch (flags[k]: the done flag of right-hand side k, or
+// nullptr).  Block b takes right-hand side (b / 8) % nrhs of patch slot
+// (b / (8 nrhs)) 8 + b % 8: the nrhs blocks of one patch land on the same
+// XCD within a few dispatches of each other and share its L2 for the
+// patch's factor and stencil records.  Not with the colored (plain) scatter.
+hipError_t launch_patch_vcycle_multi(const PatchArgs &pa, int npatch, int nrhs,
+                                     const double *const *r, double *const *z,
+                                     const double *const *flags, hipStream_t st);
 // Warm start of the patch V-cycles for patches first .. first + count - 1
 // (3D): y [count][(2p-1)^3] predictions on the patch grid, scale [count];
 // z += y_j + V_j(r_j - A_j y_j) (scaled) for each.
