@@ -51,10 +51,13 @@ def _setup(L, prob):
     return L.lor_setup(dim, list(n), V, p, method=code, penalty=eta, options=opt)
 
 
-def test_batch_matches_single_solves(L, torch_dev):
+@pytest.mark.parametrize("nrhs,probs", [(3, PROBLEMS), (5, PROBLEMS[1:3])], ids=["rhs3", "rhs5"])
+def test_batch_matches_single_solves(nrhs, probs, L, torch_dev):
+    """The right-hand sides of a problem run in lockstep groups of up to four
+    (one patch launch per group and iteration): three per problem, and five
+    (a group of four and one of one) on two problems."""
     torch = torch_dev
-    nrhs = 3
-    hs = [_setup(L, pr) for pr in PROBLEMS]
+    hs = [_setup(L, pr) for pr in probs]
     try:
         bs, xs = [], []
         for i, h in enumerate(hs):

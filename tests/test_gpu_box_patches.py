@@ -94,3 +94,31 @@ def test_box_patch_parity(case, L, torch_dev):
     finally:
         L.lor_free(h)
         del ws
+
+
+@pytest.mark.parametrize("dim,p", [(2, 3), (2, 7), (3, 3)])
+def test_float32_patches_on_strip_meshes(dim, p, L, torch_dev):
+    """Strip meshes with element aspect ratio 1500 (Section 4.5): the float32
+    patch V-cycles, which treat every patch alike, cost flexible CG at most
+    10% more iterations than float64 ones (measured: at most 5%) and the
+    solve still reaches its tolerance, true residual included."""
+    torch = torch_dev
+    n = 8 if dim == 2 else 6
+    V = inputs.strip_vertices(n, 1500.0, dim=dim)
+    its = {}
+    for prec in ("fp64", "mixed"):
+        opt = L.lor_default_options()
+        opt.precision = L.LOR_PREC_MIXED if prec == "mixed" else L.LOR_PREC_FP64
+        opt.flexible = 1
+        h = L.lor_setup(dim, n, V, p, options=opt)
+        try:
+            N = L.lor_ndofs(h)
+            b = torch.tensor(inputs.gaussian_rhs(N, 3), device="cuda")
+            x = torch.zeros_like(b)
+            info = L.lor_pcg_solve(h, b, x, rtol=1e-8, maxit=3000)
+            assert info.rel_res_true <= 1e-8
+            its[prec] = info.iters
+        finally:
+            L.lor_free(h)
+    print("strip", dim, p, its, flush=True)
+    assert its["mixed"] <= 1.1 * its["fp64"] + 2, its
