@@ -13,8 +13,10 @@
 //    takes a lane pair that adds its two partial sums), interleaved by lane
 //    so that a chunk arrives in a few coalesced loads; chunk c+1 is loaded
 //    into a second register buffer while the levels of chunk c run;
-//  * residuals and prolongations take two rows per lane, so that two
-//    stencil records or table lookups per lane are in flight.
+//  * in float64, residuals and prolongations take two rows per lane, so
+//    that two stencil records or table lookups per lane are in flight; in
+//    float32 one, which keeps the kernel at 111 registers and 14 patches
+//    per CU (the LDS limit).
 // Corrections of overlapping patches are added with FP64 atomics.
 #include <hip/hip_runtime.h>
 
@@ -76,6 +78,7 @@ struct Walk {
   int x, y, z;     // current row
   int dx, dy, dz;  // the stride in coordinates (dx < m0, dy < m1)
   int m0, m1;
+  Walk() = default;
   __device__ __forceinline__ Walk(const Box<DIM> &bx, int i, int stride) {
     m0 = max(bx.m[0], 1);
     m1 = max(bx.m[1], 1);
@@ -357,9 +360,15 @@ __device__ __forceinline__ void residual_full(T *R, const T *B, const T *X, cons
                                               const ST *__restrict__ st, const int *lng,
                                               const double *__restrict__ rglob, const MeshDims &md) {
   constexpr int NS = DIM == 3 ? 27 : 9, W = rec_width<DIM, ST>();
-  constexpr int RB = 2;  // two record loads in flight per lane (a fourth wave per SIMD lost, worth it)
+  // rows per lane and pass: two stencil records in flight per lane in float64
+  // (its patches are few per CU, LDS-bound); one in float32, whose 111
+  // registers let a fourth wavefront per SIMD in (14 patches per CU, 12 with
+  // two rows: the added occupancy wins since the sweep records were sorted)
+  constexpr int RB = sizeof(T) == 4 ? 1 : 2;
   const int mx = bx.m[0], my = bx.m[1], mz = bx.m[2];
-  Walk<DIM> w[RB] = {Walk<DIM>(bx, threadIdx.x, 64 * RB), Walk<DIM>(bx, threadIdx.x + 64, 64 * RB)};
+  Walk<DIM> w[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) w[r] = Walk<DIM>(bx, threadIdx.x + 64 * r, 64 * RB);
   for (int i0 = threadIdx.x; i0 < bx.n; i0 += 64 * RB) {
     ST a[RB][NS];
     T acc[RB];
@@ -405,11 +414,13 @@ __device__ __forceinline__ void residual_scatter(T *R, const T *B, const T *X, c
   //                                to a(i,s) by symmetry)
   // the second kind by LDS atomics into R, cleared first.
   constexpr int NS = DIM == 3 ? 27 : 9, C = NS / 2, W = rec_width<DIM, ST>();
-  constexpr int RB = 2;
+  constexpr int RB = sizeof(T) == 4 ? 1 : 2;
   const int mx = bx.m[0], my = bx.m[1], mz = bx.m[2];
   for (int i = threadIdx.x; i < bx.n; i += 64) R[i] = T(0);
   wave_sync();
-  Walk<DIM> w[RB] = {Walk<DIM>(bx, threadIdx.x, 64 * RB), Walk<DIM>(bx, threadIdx.x + 64, 64 * RB)};
+  Walk<DIM> w[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) w[r] = Walk<DIM>(bx, threadIdx.x + 64 * r, 64 * RB);
   for (int i0 = threadIdx.x; i0 < bx.n; i0 += 64 * RB) {
     ST a[RB][NS];
     T acc[RB];
@@ -648,11 +659,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       const XferTab *tb0 = &pa.xfer[k * 3 + typ[0]];
       const XferTab *tb1 = &pa.xfer[k * 3 + typ[1]];
       const XferTab *tb2 = &pa.xfer[k * 3 + typ[DIM - 1]];
-      // two rows per lane and iteration (two rounds of table loads in
-      // flight); a row past the end uses row i0's coordinates, its store is
-      // skipped
-      constexpr int PB = 2;
-      Walk<DIM> wf[PB] = {Walk<DIM>(fb, threadIdx.x, 64 * PB), Walk<DIM>(fb, threadIdx.x + 64, 64 * PB)};
+      // PB rows per lane and iteration (as the residual's RB); a row past
+      // the end uses row i0's coordinates, its store is skipped
+      constexpr int PB = sizeof(T) == 4 ? 1 : 2;
+      Walk<DIM> wf[PB];
+#pragma unroll
+      for (int r = 0; r < PB; ++r) wf[r] = Walk<DIM>(fb, threadIdx.x + 64 * r, 64 * PB);
       for (int i0 = threadIdx.x; i0 < fb.n; i0 += 64 * PB) {
         // fixed 2 x 2 (x 2) gather; sources on the patch boundary get weight 0
         int cx[PB][2], cy[PB][2], cz[PB][2];
