@@ -202,14 +202,29 @@ __device__ __forceinline__ void load_chunk(uint4 (&R)[QM], const uint4 *src, int
 }
 
 // The steps of one chunk with NPP coupling pairs per lane record: the
-// chunk's widest record (records with fewer couplings have zero padding pairs
-// that read the row itself), so a chunk of narrow rows costs fewer LDS reads
-// and FMAs.  SPLIT: the chunk holds rows split over a lane pair; the second
-// lane of a pair starts from zero, and the first adds the pair's partial sum.
+// chunk's widest record (records with fewer couplings have zero padding
+// couplings that read the row itself), so a chunk of narrow rows costs fewer
+// LDS reads and FMAs.  SPLIT: the chunk holds rows split over a lane pair; the
+// second lane of a pair starts from zero, and the first adds the pair's
+// partial sum.  The neighbours' LDS indices come from the record's slot mask
+// and the level box's slot table, once per chunk.
 template <typename T, bool FWD, int QM, int NPP, bool SPLIT>
-__device__ __forceinline__ void run_steps(const uint4 (&R)[QM], T *Y, int nsteps, int mystep,
-                                          int row, bool second, bool paired) {
-  constexpr int H = sweep_head_words<T>(FWD), PW = sweep_pair_words<T>(), SZ = int(sizeof(T)) / 4;
+__device__ __forceinline__ void run_steps(const uint4 (&R)[QM], T *Y, const short *tab, int nsteps,
+                                          int mystep, int row, bool second, bool paired) {
+  constexpr int H = sweep_head_words<T>(FWD), SZ = int(sizeof(T)) / 4;
+  int nb[2 * NPP + 1];
+  {
+    uint32_t m = wget(R, H);
+    // table reads for every coupling slot first, one LDS wait for all of them
+#pragma unroll
+    for (int k = 0; k < 2 * NPP; ++k) {
+      const uint32_t sl = m ? uint32_t(__builtin_ctz(m)) : 27u;  // 27: padding, offset 0
+      m &= m - 1;
+      nb[k] = tab[sl];
+    }
+#pragma unroll
+    for (int k = 0; k < 2 * NPP; ++k) nb[k] += row;
+  }
   for (int s = 0; s < nsteps; ++s) {
     T part = T(0);
     if (mystep == s) {
@@ -217,15 +232,11 @@ __device__ __forceinline__ void run_steps(const uint4 (&R)[QM], T *Y, int nsteps
       if (SPLIT) acc0 = second ? T(0) : acc0;
       T acc1 = T(0);
       // all LDS reads are issued before the FMAs, with no branch between them
-      // (padding pairs have zero values and offsets: they read the row
-      // itself), so a step costs one LDS round trip
+      // (padding couplings have zero values and read the row itself), so a
+      // step costs one LDS round trip
       T y[2 * NPP + 2];
 #pragma unroll
-      for (int p = 0; p < NPP; ++p) {
-        const uint32_t o = wget(R, H + p * PW + PW - 1);
-        y[2 * p] = Y[row + int(short(o & 0xFFFF))];
-        y[2 * p + 1] = Y[row + int(short(o >> 16))];
-      }
+      for (int k = 0; k < 2 * NPP; ++k) y[k] = Y[nb[k]];
       // one wait for all of them (fewer instructions per step than a wait
       // before every FMA); the scheduling barriers keep it in place
       __builtin_amdgcn_sched_barrier(0);
@@ -233,8 +244,8 @@ __device__ __forceinline__ void run_steps(const uint4 (&R)[QM], T *Y, int nsteps
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int p = 0; p < NPP; ++p) {
-        acc0 -= word_get<T, QM>(R, H + p * PW) * y[2 * p];
-        acc1 -= word_get<T, QM>(R, H + p * PW + SZ) * y[2 * p + 1];
+        acc0 -= word_get<T, QM>(R, H + 1 + (2 * p) * SZ) * y[2 * p];
+        acc1 -= word_get<T, QM>(R, H + 1 + (2 * p + 1) * SZ) * y[2 * p + 1];
       }
       if (SPLIT)
         part = acc0 + acc1;
@@ -250,38 +261,52 @@ __device__ __forceinline__ void run_steps(const uint4 (&R)[QM], T *Y, int nsteps
 }
 
 template <typename T, bool FWD, int QM, bool SPLIT>
-__device__ __forceinline__ void run_chunk_w(const uint4 (&R)[QM], T *Y, int npairs, int nsteps, int mystep,
-                                            int row, bool second, bool paired) {
+__device__ __forceinline__ void run_chunk_w(const uint4 (&R)[QM], T *Y, const short *tab, int npairs,
+                                            int nsteps, int mystep, int row, bool second, bool paired) {
   switch (npairs) {
-    case 0: run_steps<T, FWD, QM, 0, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
-    case 1: run_steps<T, FWD, QM, 1, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
-    case 2: run_steps<T, FWD, QM, 2, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
-    case 3: run_steps<T, FWD, QM, 3, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
-    case 4: run_steps<T, FWD, QM, 4, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
-    case 5: run_steps<T, FWD, QM, 5, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
-    case 6: run_steps<T, FWD, QM, 6, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
-    default: run_steps<T, FWD, QM, kLaneCouplings / 2, SPLIT>(R, Y, nsteps, mystep, row, second, paired); break;
+    case 0: run_steps<T, FWD, QM, 0, SPLIT>(R, Y, tab, nsteps, mystep, row, second, paired); break;
+    case 1: run_steps<T, FWD, QM, 1, SPLIT>(R, Y, tab, nsteps, mystep, row, second, paired); break;
+    case 2: run_steps<T, FWD, QM, 2, SPLIT>(R, Y, tab, nsteps, mystep, row, second, paired); break;
+    case 3: run_steps<T, FWD, QM, 3, SPLIT>(R, Y, tab, nsteps, mystep, row, second, paired); break;
+    case 4: run_steps<T, FWD, QM, 4, SPLIT>(R, Y, tab, nsteps, mystep, row, second, paired); break;
+    case 5: run_steps<T, FWD, QM, 5, SPLIT>(R, Y, tab, nsteps, mystep, row, second, paired); break;
+    case 6: run_steps<T, FWD, QM, 6, SPLIT>(R, Y, tab, nsteps, mystep, row, second, paired); break;
+    default: run_steps<T, FWD, QM, kLaneCouplings / 2, SPLIT>(R, Y, tab, nsteps, mystep, row, second, paired); break;
   }
 }
 
 template <typename T, bool FWD, int QM>
-__device__ __forceinline__ void run_chunk(const uint4 (&R)[QM], T *Y, uint32_t hdr) {
+__device__ __forceinline__ void run_chunk(const uint4 (&R)[QM], T *Y, const short *tab, uint32_t hdr) {
   const int nsteps = (hdr >> 8) & 0xFF;
   const int npairs = int((hdr >> 16) & 0xFF) / 2;  // the chunk's widest record, in pairs
   const uint32_t d0 = R[0].x;
   const int mystep = (d0 & kSweepValid) ? int((d0 >> 16) & 0x3F) : -1;
   const int row = int(d0 & 0xFFFF);
   if (hdr & kChunkSplit)
-    run_chunk_w<T, FWD, QM, true>(R, Y, npairs, nsteps, mystep, row, (d0 & kSweepSecond) != 0,
+    run_chunk_w<T, FWD, QM, true>(R, Y, tab, npairs, nsteps, mystep, row, (d0 & kSweepSecond) != 0,
                                   (d0 & kSweepPaired) != 0);
   else
-    run_chunk_w<T, FWD, QM, false>(R, Y, npairs, nsteps, mystep, row, false, false);
+    run_chunk_w<T, FWD, QM, false>(R, Y, tab, npairs, nsteps, mystep, row, false, false);
+}
+
+// Slot table of a level box with extents m0 x m1 (x ...): entry s the LDS
+// offset of stencil slot s (x fastest: (s%3-1) + m0 ((s/3)%3-1) + m0 m1
+// (s/9-1)), entry 27 zero (padding couplings).
+template <int DIM>
+__device__ __forceinline__ void slot_table(short *tab, int m0, int m1) {
+  const int s = int(threadIdx.x);
+  if (s < 28) {
+    int o = 0;
+    if (s < (DIM == 3 ? 27 : 9)) o = (s % 3 - 1) + m0 * ((s / 3) % 3 - 1) + (DIM == 3 ? m0 * m1 * (s / 9 - 1) : 0);
+    tab[s] = short(o);
+  }
+  wave_sync();
 }
 
 // forward:  w_i = y_i - sum_{earlier m} l_im w_m
 // backward: y_i = w_i / D_i - sum_{later m} l_mi y_m       (both in place on Y)
 template <typename T, bool FWD>
-__device__ __forceinline__ void sweep(T *Y, const char *blk) {
+__device__ __forceinline__ void sweep(T *Y, const char *blk, const short *tab) {
   constexpr int QM = sweep_quads<T>(FWD, kLaneCouplings);
   const int nch = *reinterpret_cast<const int *>(blk);
   uint32_t hdr = reinterpret_cast<const uint32_t *>(blk)[1];
@@ -299,7 +324,7 @@ __device__ __forceinline__ void sweep(T *Y, const char *blk) {
       load_chunk<T, FWD, QM>(B, src, nextq(A[0].x), zero);
       src += int(h1 & 0xFF) * 64;
     }
-    run_chunk<T, FWD, QM>(A, Y, hdr);
+    run_chunk<T, FWD, QM>(A, Y, tab, hdr);
     if (c + 1 >= nch) break;
     wait_vm();
     const uint32_t h2 = __builtin_amdgcn_readlane(B[0].x, 63);
@@ -307,7 +332,7 @@ __device__ __forceinline__ void sweep(T *Y, const char *blk) {
       load_chunk<T, FWD, QM>(A, src, nextq(B[0].x), zero);
       src += int(h2 & 0xFF) * 64;
     }
-    run_chunk<T, FWD, QM>(B, Y, h1);
+    run_chunk<T, FWD, QM>(B, Y, tab, h1);
     hdr = h2;
   }
 }
@@ -475,6 +500,18 @@ __device__ __forceinline__ void residual(T *R, const T *B, const T *X, const Box
     residual_full<DIM, T, ST, GB>(R, B, X, bx, st, lng, rglob, md);
 }
 
+// LDS values per patch: the largest patch's, plus its level-0 right side
+// with a warm start
+template <int DIM, bool WARM>
+__host__ __device__ inline size_t lds_values(const PatchArgs &pa) {
+  size_t n0 = 1;
+  for (int d = 0; d < DIM; ++d) n0 *= size_t(2 * pa.s[0] - 1);
+  return size_t(pa.lds_total) + (WARM ? n0 : 0);
+}
+
+// bytes of the slot table after the patch vectors (28 int16 entries)
+constexpr int kSlotTableBytes = 64;
+
 // One wavefront per patch.  Modes: scatter-add the correction into z (the
 // preconditioner); write it into the patch grid (dense, training data); or,
 // with WARM, start from a prediction y_j of the patch solve (patch-grid
@@ -502,6 +539,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   if (flag && flag[S_DONE] != 0.0) return;
   extern __shared__ __align__(16) char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
+  short *tab = reinterpret_cast<short *>(lds_raw + lds_values<DIM, WARM>(pa) * sizeof(T));
   int j = jfirst + slot;
   if (!WARM && pa.perm) j = pa.perm[j];
   if (pa.color >= 0) {
@@ -590,8 +628,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       for (int i = threadIdx.x; i < fb.n; i += 64) Xk[i] = Bk[i];
       wave_sync();
     }
-    sweep<T, true>(Xk, bf);
-    sweep<T, false>(Xk, bb);
+    slot_table<DIM>(tab, fb.m[0], fb.m[1]);
+    sweep<T, true>(Xk, bf, tab);
+    sweep<T, false>(Xk, bb, tab);
     if (k == 0 && !WARM)
       residual<DIM, T, ST, true>(Rk, Bk, Xk, fb, stn[k], pa.lng[k], r, md);
     else
@@ -712,8 +751,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       residual<DIM, T, ST, true>(Rk, Bk, Xk, fb, stn[k], pa.lng[k], r, md);
     else
       residual<DIM, T, ST, false>(Rk, Bk, Xk, fb, stn[k], pa.lng[k], r, md);
-    sweep<T, true>(Rk, bf);
-    sweep<T, false>(Rk, bb);
+    slot_table<DIM>(tab, fb.m[0], fb.m[1]);
+    sweep<T, true>(Rk, bf, tab);
+    sweep<T, false>(Rk, bb, tab);
     for (int i = threadIdx.x; i < fb.n; i += 64) Xk[i] += Rk[i];
     wave_sync();
   }
@@ -761,20 +801,11 @@ hipError_t prepare_t() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
 }
 
-// LDS values per patch: the largest patch's, plus its level-0 right side
-// with a warm start
-template <int DIM, bool WARM>
-size_t lds_values(const PatchArgs &pa) {
-  size_t n0 = 1;
-  for (int d = 0; d < DIM; ++d) n0 *= size_t(2 * pa.s[0] - 1);
-  return size_t(pa.lds_total) + (WARM ? n0 : 0);
-}
-
 template <int DIM, typename T, typename ST, bool WARM>
 hipError_t launch_t(const PatchArgs &pa, int npatch, const double *r, double *z, const double *flag,
                     float *dense, const double *dscale, const float *wy, int jfirst, hipStream_t st) {
   constexpr int W = DIM == 3 ? 26 : 8;
-  const size_t lds = lds_values<DIM, WARM>(pa) * sizeof(T);
+  const size_t lds = lds_values<DIM, WARM>(pa) * sizeof(T) + kSlotTableBytes;
   if (lds > size_t(kMaxDynLds)) return hipErrorInvalidValue;
   if (npatch <= 0) return hipSuccess;
   k_patch_vcycle<DIM, T, ST, W, WARM><<<npatch, 64, lds, st>>>(pa, r, z, flag, dense, dscale, wy, jfirst);

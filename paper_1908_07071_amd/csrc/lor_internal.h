@@ -86,11 +86,15 @@ struct PatchArgs {
 //   quads of this lane's record in the next chunk (22-26) | kSweepPaired |
 //   kSweepSecond | kSweepValid (lanes without a row only carry the next
 //   size); for the backward sweep then 1 / D as T (zero in the second lane
-//   of a pair); then the couplings in pairs: T v0, T v1, uint32 (int16 off0 |
-//   int16 off1 << 16), where off is the LDS offset of the neighbour from the
-//   row (padding pairs are zero).  Lane 63 carries the header of the next
-//   chunk instead: Q (bits 0-7) | nsteps (8-15) | W (16-23) | kChunkSplit,
-//   W = couplings per lane record (even).
+//   of a pair); then one uint32 slot mask: bit s set for every stencil slot
+//   s (the neighbour at offset (s%3-1, (s/3)%3-1, s/9-1), s != centre) that
+//   this lane couples, and the coupling values as T in increasing slot order
+//   (the record is zero beyond them).  The kernel turns a slot into the
+//   neighbour's LDS offset from a 28-entry table of the level box (entry 27:
+//   0, for padding couplings, which read the row itself with weight 0).  Lane
+//   63 carries the header of the next chunk instead: Q (bits 0-7) | nsteps
+//   (8-15) | W (16-23) | kChunkSplit,
+//   W = the chunk's most couplings in a lane record, rounded up to even.
 // Level stencils as the patch kernel reads them: point-major records, one
 // per grid point g at g * rec_width.
 //   float:  the full stencil, slots 0 .. 3^d - 1 in slot order, zero-padded
@@ -123,13 +127,10 @@ template <typename T>
 __host__ __device__ constexpr int sweep_head_words(bool fwd) {
   return fwd ? 1 : 1 + int(sizeof(T)) / 4;
 }
+// quads of a lane record with c couplings (head, slot mask, c values)
 template <typename T>
-__host__ __device__ constexpr int sweep_pair_words() {
-  return 2 * int(sizeof(T)) / 4 + 1;
-}
-template <typename T>
-__host__ __device__ constexpr int sweep_quads(bool fwd, int w) {
-  return (sweep_head_words<T>(fwd) + ((w + 1) / 2) * sweep_pair_words<T>() + 3) / 4;
+__host__ __device__ constexpr int sweep_quads(bool fwd, int c) {
+  return (sweep_head_words<T>(fwd) + 1 + c * int(sizeof(T)) / 4 + 3) / 4;
 }
 __host__ __device__ inline int64_t align16(int64_t b) { return (b + 15) & ~int64_t(15); }
 

@@ -70,11 +70,6 @@ std::vector<char> pack_sweep(const MdfResult &res, int dim, const int *m, bool f
   const int NS = dim == 3 ? 27 : 9, C = NS / 2;
   const int depth = int(res.level_ptr.size()) - 1;
   const int mx = m[0], my = m[1], mz = dim == 3 ? m[2] : 1;
-  int dl[27];
-  for (int s = 0; s < NS; ++s) {
-    const int ox = s % 3 - 1, oy = (s / 3) % 3 - 1, oz = dim == 3 ? s / 9 - 1 : 0;
-    dl[s] = ox + mx * (oy + my * oz);
-  }
   auto couplings = [&](int i, std::vector<int> &slots) {
     slots.clear();
     const int ix = i % mx, iy = (i / mx) % my, iz = i / (mx * my);
@@ -112,7 +107,7 @@ std::vector<char> pack_sweep(const MdfResult &res, int dim, const int *m, bool f
     }
   }
   if (chunks.back().nsteps == 0) chunks.pop_back();
-  const int hw = sweep_head_words<T>(fwd), pw = sweep_pair_words<T>();
+  const int hw = sweep_head_words<T>(fwd), sz = int(sizeof(T)) / 4;
   // Lanes of a chunk sorted by record length, longest first (lane pairs
   // first, on even lanes): quad q of the chunk is then loaded by a prefix of
   // the lanes, so a 128-byte line (8 lanes' quads) is fetched only where
@@ -125,10 +120,10 @@ std::vector<char> pack_sweep(const MdfResult &res, int dim, const int *m, bool f
     for (int l = 0; l < kChunkLanes; ++l) {
       const LaneRec &r = c.lane[l];
       if (r.row < 0 || r.second) continue;
-      const int q0 = sweep_quads<T>(fwd, (r.c1 - r.c0 + 1) & ~1);
+      const int q0 = sweep_quads<T>(fwd, r.c1 - r.c0);
       if (r.paired) {
         const LaneRec &r2 = c.lane[l + 1];
-        units.push_back({l, 2, std::max(q0, sweep_quads<T>(fwd, (r2.c1 - r2.c0 + 1) & ~1))});
+        units.push_back({l, 2, std::max(q0, sweep_quads<T>(fwd, r2.c1 - r2.c0))});
       } else {
         units.push_back({l, 1, q0});
       }
@@ -149,11 +144,10 @@ std::vector<char> pack_sweep(const MdfResult &res, int dim, const int *m, bool f
     for (int l = 0; l < kChunkLanes; ++l) {
       const LaneRec &r = c.lane[l];
       if (r.row < 0) continue;
-      const int w = (r.c1 - r.c0 + 1) & ~1;
-      c.w = std::max(c.w, w);
-      lane_q[ci][l] = sweep_quads<T>(fwd, w);
+      c.w = std::max(c.w, (r.c1 - r.c0 + 1) & ~1);
+      lane_q[ci][l] = sweep_quads<T>(fwd, r.c1 - r.c0);
+      c.q = std::max(c.q, lane_q[ci][l]);
     }
-    c.q = sweep_quads<T>(fwd, c.w);
   }
   auto header = [](const Chunk &c) {
     return uint32_t(c.q) | (uint32_t(c.nsteps) << 8) | (uint32_t(c.w) << 16) | (c.split ? kChunkSplit : 0u);
@@ -184,13 +178,12 @@ std::vector<char> pack_sweep(const MdfResult &res, int dim, const int *m, bool f
                (r.paired ? kSweepPaired : 0u) | (r.second ? kSweepSecond : 0u);
       if (!fwd && !r.second) put<T>(rec, 1, T(1.0 / res.D[r.row]));
       couplings(r.row, slots);
+      uint32_t mask = 0;
       for (int q = r.c0; q < r.c1; ++q) {
-        const int pr = (q - r.c0) / 2, hi = (q - r.c0) % 2;
-        const int w0 = hw + pr * pw;
-        put<T>(rec, w0 + hi * int(sizeof(T)) / 4, T(res.L[size_t(r.row) * NS + slots[q]]));
-        const uint32_t o = uint32_t(uint16_t(int16_t(dl[slots[q]])));
-        rec[w0 + pw - 1] |= hi ? (o << 16) : o;
+        mask |= 1u << slots[q];
+        put<T>(rec, hw + 1 + (q - r.c0) * sz, T(res.L[size_t(r.row) * NS + slots[q]]));
       }
+      rec[hw] = mask;
       for (int qd = 0; qd < c.q; ++qd)
         std::memcpy(out.data() + base + 16 * (int64_t(qd) * 64 + l), &rec[4 * qd], 16);
     }

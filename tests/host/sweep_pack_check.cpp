@@ -40,12 +40,17 @@ static T word_as(const uint32_t *w, int b) {
   return v;
 }
 
-// Replays one packed block on Y (one wavefront of 64 lanes).
+// Replays one packed block on Y (one wavefront of 64 lanes) of a dim-D box
+// with extents m (the slot table of the kernel: offset of stencil slot s).
 template <typename T, bool FWD>
-static bool replay(const std::vector<char> &blk, std::vector<T> &Y) {
+static bool replay(const std::vector<char> &blk, std::vector<T> &Y, int dim, const int *m) {
   constexpr int QM = sweep_quads<T>(FWD, kLaneCouplings);
-  constexpr int H = sweep_head_words<T>(FWD), PW = sweep_pair_words<T>(), SZ = sizeof(T) / 4;
+  constexpr int H = sweep_head_words<T>(FWD), SZ = sizeof(T) / 4;
   const int n = int(Y.size());
+  const int NS = dim == 3 ? 27 : 9, C = NS / 2;
+  int tab[28];
+  for (int s = 0; s < 28; ++s)
+    tab[s] = s < NS ? (s % 3 - 1) + m[0] * ((s / 3) % 3 - 1) + (dim == 3 ? m[0] * m[1] * (s / 9 - 1) : 0) : 0;
   int nch;
   uint32_t hdr;
   std::memcpy(&nch, blk.data(), 4);
@@ -88,14 +93,18 @@ static bool replay(const std::vector<char> &blk, std::vector<T> &Y) {
         T acc0 = FWD ? Y[row] : Y[row] * word_as<T>(rec(l), 1);
         if (split) acc0 = second ? T(0) : acc0;
         T acc1 = T(0);
-        for (int p = 0; p < npairs; ++p) {
-          const uint32_t o = rec(l)[H + p * PW + PW - 1];
-          const int j0 = row + int(short(o & 0xFFFF)), j1 = row + int(short(o >> 16));
-          CHECK(j0 >= 0 && j0 < n && j1 >= 0 && j1 < n, "neighbour outside the box");
-          if (j0 != row) reads.push_back(j0);
-          if (j1 != row) reads.push_back(j1);
-          acc0 -= word_as<T>(rec(l), H + p * PW) * Y[j0];
-          acc1 -= word_as<T>(rec(l), H + p * PW + SZ) * Y[j1];
+        uint32_t mask = rec(l)[H];
+        CHECK(!((mask >> C) & 1) && (mask >> NS) == 0, "slot mask %x of row %d", mask, row);
+        CHECK(__builtin_popcount(mask) <= 2 * npairs, "row %d has more couplings than the chunk's width", row);
+        for (int k = 0; k < 2 * npairs; ++k) {
+          const int sl = mask ? __builtin_ctz(mask) : 27;
+          mask &= mask - 1;
+          const int j = row + tab[sl];
+          CHECK(j >= 0 && j < n, "neighbour outside the box");
+          const T v = word_as<T>(rec(l), H + 1 + k * SZ);
+          CHECK(sl != 27 || v == T(0), "padding coupling with a nonzero value");
+          if (j != row) reads.push_back(j);
+          (k % 2 ? acc1 : acc0) -= v * Y[j];
         }
         part[l] = acc0 + acc1;
         if (!second) {
@@ -215,9 +224,9 @@ static void run_case(int dim, const int *m, std::vector<double> rows, unsigned s
   std::vector<T> Y(n);
   for (int i = 0; i < n; ++i) Y[i] = T(y0[i]);
   const int f0 = failures;
-  const bool okf = replay<T, true>(pack_sweep<T>(res, dim, m, true), Y);
+  const bool okf = replay<T, true>(pack_sweep<T>(res, dim, m, true), Y, dim, m);
   const double ef = relerr(Y, w);
-  const bool okb = okf && replay<T, false>(pack_sweep<T>(res, dim, m, false), Y);
+  const bool okb = okf && replay<T, false>(pack_sweep<T>(res, dim, m, false), Y, dim, m);
   const double eb = relerr(Y, y);
   const double tol = sizeof(T) == 4 ? 2e-6 : 1e-13;
   const bool ok = okf && okb && failures == f0 && ef < tol && eb < tol;

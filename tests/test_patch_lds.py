@@ -6,8 +6,9 @@ the prolongation.  That is valid when, for every patch shape (each
 direction interior, 2 s_k - 1 points, or on the boundary, s_k - 1),
 2 n_1 + 3 sum_{k>=2} n_k <= n_0.  With the kept-point rule of Section 3.3
 it holds for every supported degree; the LDS need 2 n_0 + n_1 of the
-largest patch then fits the 160 KiB of a CU up to the degrees that
-include/lor.h states (3D: p <= 11 in float64, p <= 13 in float32)."""
+largest patch (plus a 64-byte slot table) then fits the 160 KiB of a CU up
+to the degrees that include/lor.h states (3D: p <= 11 in float64, p <= 13
+in float32)."""
 import itertools
 
 import pytest
@@ -38,11 +39,14 @@ def test_lds_need_and_documented_degree_limits():
     def need(p, dim, bytes_per_value):
         s = OL.level_sizes(p)
         n = [_level_points(sk, (True,) * dim) for sk in s]
-        return (2 * n[0] + (n[1] if len(n) > 1 else 0)) * bytes_per_value
+        # plus the 64-byte slot table of the sweep records
+        return (2 * n[0] + (n[1] if len(n) > 1 else 0)) * bytes_per_value + 64
 
     fits = {(dim, b): [p for p in range(1, 15) if need(p, dim, b) <= LDS_BYTES] for dim in (2, 3) for b in (4, 8)}
     assert fits[(2, 4)] == list(range(1, 15)) and fits[(2, 8)] == list(range(1, 15))
     assert fits[(3, 8)] == list(range(1, 12))   # float64: p <= 11
     assert fits[(3, 4)] == list(range(1, 14))   # float32: p <= 13
-    # the benchmark's p = 6 patch: 11.1 KB in float, 22.3 KB in float64
-    assert need(6, 3, 4) == 11148 and need(6, 3, 8) == 22296
+    # the benchmark's p = 6 patch: 11.2 KB in float (14 per CU in 160 KiB,
+    # 512-byte granules included), 22.4 KB in float64 (7 per CU)
+    assert need(6, 3, 4) == 11212 and need(6, 3, 8) == 22360
+    assert 14 * ((11212 + 511) // 512 * 512) <= LDS_BYTES
