@@ -374,6 +374,41 @@ int build_boxes(lor_handle &h, const std::vector<std::vector<double>> &hst, hipS
       bp.lv[k].b = h.box_b[k];
       bp.lv[k].r = h.box_r[k];
     }
+  // colours (greedy, in box order): boxes of one colour have disjoint
+  // level-0 point ranges, so their corrections can be added side by side
+  h.box_color.assign(h.boxes.size(), 0);
+  h.box_ncolor = h.boxes.empty() ? 0 : 1;
+  if (!single && h.boxes.size() > 1) {
+    auto overlap = [&](const SingleLevelDev &a, const SingleLevelDev &b) {
+      if (a.n <= 0 || b.n <= 0) return false;
+      for (int d = 0; d < dim; ++d)
+        if (a.lo[d] + a.m[d] <= b.lo[d] || b.lo[d] + b.m[d] <= a.lo[d]) return false;
+      return true;
+    };
+    for (size_t j = 0; j < h.boxes.size(); ++j) {
+      std::vector<char> used(h.boxes.size() + 1, 0);
+      for (size_t i = 0; i < j; ++i)
+        if (overlap(h.boxes[i].lv[0], h.boxes[j].lv[0])) used[h.box_color[i]] = 1;
+      int c = 0;
+      while (used[c]) ++c;
+      h.box_color[j] = c;
+      h.box_ncolor = std::max(h.box_ncolor, c + 1);
+    }
+    // the other streams' level vectors, the streams and their events
+    for (int t = 0; t < lor_handle::kBoxStreams - 1; ++t) {
+      h.box_sx[t].assign(L, nullptr);
+      h.box_sb[t].assign(L, nullptr);
+      h.box_sr[t].assign(L, nullptr);
+      for (int k = 0; k < L; ++k) {
+        if (maxn[k] <= 0) continue;
+        SCHK(h.alloc(&h.box_sx[t][k], size_t(maxn[k])));
+        SCHK(h.alloc(&h.box_sb[t][k], size_t(maxn[k])));
+        SCHK(h.alloc(&h.box_sr[t][k], size_t(maxn[k])));
+      }
+    }
+    for (hipStream_t &t : h.box_st) SCHK(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
+    for (hipEvent_t &e : h.box_ev) SCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   if (h.opt.prolong_weights == LOR_PROLONG_POU && h.opt.patch_mode != LOR_PATCH_SINGLE) {
     std::vector<double> w(count.size());
     for (size_t i = 0; i < count.size(); ++i) w[i] = count[i] > 0.0 ? 1.0 / count[i] : 0.0;
@@ -385,9 +420,20 @@ int build_boxes(lor_handle &h, const std::vector<std::vector<double>> &hst, hipS
 
 namespace {
 
+// The level vectors a box patch's V-cycle works in (one set per stream).
+struct BoxBufs {
+  double *const *x, *const *b, *const *r;  // per level
+};
+
+BoxBufs box_bufs(const lor_handle *h, int set) {
+  if (set == 0) return {h->box_x.data(), h->box_b.data(), h->box_r.data()};
+  return {h->box_sx[set - 1].data(), h->box_sb[set - 1].data(), h->box_sr[set - 1].data()};
+}
+
 int vcycle(lor_handle *h, BoxPatchDev &bp, int k, const double *b, double *x, const double *flag,
-           hipStream_t st) {
+           hipStream_t st, const BoxBufs &buf) {
   SingleLevelDev &lv = bp.lv[k];
+  double *rk = buf.r[k];
   if (lv.n <= 0) return LOR_OK;
   if (k == h->L - 1) {
     SCHK(launch_gemv(int(lv.n), lv.ainv, b, x, flag, st));
@@ -399,19 +445,20 @@ int vcycle(lor_handle *h, BoxPatchDev &bp, int k, const double *b, double *x, co
   // pre-smoothing from zero: x = M^-1 b
   SCHK(launch_single_sweep(dim, true, lv, b, x, flag, st));
   SCHK(launch_single_sweep(dim, false, lv, x, x, flag, st));
-  SCHK(launch_single_residual(dim, A, h->npts[k], lng, lv.lo, lv.m, b, x, lv.r, flag, st));
+  SCHK(launch_single_residual(dim, A, h->npts[k], lng, lv.lo, lv.m, b, x, rk, flag, st));
   SingleLevelDev &cv = bp.lv[k + 1];
   if (cv.n > 0) {
-    SCHK(launch_single_transfer(dim, false, lv.xf, lv.r, cv.b, flag, st));
-    const int rc = vcycle(h, bp, k + 1, cv.b, cv.x, flag, st);
+    double *cb = buf.b[k + 1], *cx = buf.x[k + 1];
+    SCHK(launch_single_transfer(dim, false, lv.xf, rk, cb, flag, st));
+    const int rc = vcycle(h, bp, k + 1, cb, cx, flag, st, buf);
     if (rc != LOR_OK) return rc;
-    SCHK(launch_single_transfer(dim, true, lv.xf, cv.x, x, flag, st));
-    SCHK(launch_single_residual(dim, A, h->npts[k], lng, lv.lo, lv.m, b, x, lv.r, flag, st));
+    SCHK(launch_single_transfer(dim, true, lv.xf, cx, x, flag, st));
+    SCHK(launch_single_residual(dim, A, h->npts[k], lng, lv.lo, lv.m, b, x, rk, flag, st));
   }
   // post-smoothing: x += M^-1 r (in place on r)
-  SCHK(launch_single_sweep(dim, true, lv, lv.r, lv.r, flag, st));
-  SCHK(launch_single_sweep(dim, false, lv, lv.r, lv.r, flag, st));
-  SCHK(launch_axpy1(x, lv.r, lv.n, flag, st));
+  SCHK(launch_single_sweep(dim, true, lv, rk, rk, flag, st));
+  SCHK(launch_single_sweep(dim, false, lv, rk, rk, flag, st));
+  SCHK(launch_axpy1(x, rk, lv.n, flag, st));
   return LOR_OK;
 }
 
@@ -422,16 +469,38 @@ int apply_boxes(lor_handle *h, const double *r, double *z, const double *flag, h
   if (h->opt.patch_mode == LOR_PATCH_SINGLE) {
     // one box, the whole domain: level 0 is the L-vector
     if (h->boxes[0].lv[0].n <= 0) return LOR_OK;
-    return vcycle(h, h->boxes[0], 0, r, z, flag, st);
+    return vcycle(h, h->boxes[0], 0, r, z, flag, st, box_bufs(h, 0));
   }
-  for (BoxPatchDev &bp : h->boxes) {
-    SingleLevelDev &l0 = bp.lv[0];
-    if (l0.n <= 0) continue;
-    double *b0 = h->box_b[0], *x0 = h->box_x[0];
-    SCHK(launch_box_gather(h->dim, h->md, l0.lo, l0.m, r, b0, flag, st));
-    const int rc = vcycle(h, bp, 0, b0, x0, flag, st);
-    if (rc != LOR_OK) return rc;
-    SCHK(launch_box_scatter(h->dim, h->md, l0.lo, l0.m, x0, h->d_box_w, z, flag, st));
+  // colour by colour; within a colour the patches take the streams in turn
+  // (one after another on `st` while a graph is captured or events must not
+  // be recorded), the same additions to z in either case
+  constexpr int NS = lor_handle::kBoxStreams;
+  const bool side = !h->capturing && h->box_st[0] != nullptr;
+  for (int c = 0; c < h->box_ncolor; ++c) {
+    if (side) {
+      SCHK(hipEventRecord(h->box_ev[NS], st));
+      for (hipStream_t t : h->box_st) SCHK(hipStreamWaitEvent(t, h->box_ev[NS], 0));
+    }
+    int turn = 0;
+    for (size_t j = 0; j < h->boxes.size(); ++j) {
+      if (h->box_color[j] != c) continue;
+      BoxPatchDev &bp = h->boxes[j];
+      SingleLevelDev &l0 = bp.lv[0];
+      if (l0.n <= 0) continue;
+      const int set = side ? turn++ % NS : 0;
+      hipStream_t s = side ? h->box_st[set] : st;
+      const BoxBufs buf = box_bufs(h, set);
+      double *b0 = buf.b[0], *x0 = buf.x[0];
+      SCHK(launch_box_gather(h->dim, h->md, l0.lo, l0.m, r, b0, flag, s));
+      const int rc = vcycle(h, bp, 0, b0, x0, flag, s, buf);
+      if (rc != LOR_OK) return rc;
+      SCHK(launch_box_scatter(h->dim, h->md, l0.lo, l0.m, x0, h->d_box_w, z, flag, s));
+    }
+    if (side)
+      for (int t = 0; t < NS; ++t) {
+        SCHK(hipEventRecord(h->box_ev[t], h->box_st[t]));
+        SCHK(hipStreamWaitEvent(st, h->box_ev[t], 0));
+      }
   }
   return LOR_OK;
 }

@@ -1202,6 +1202,11 @@ int lor_bind_workspace(lor_handle_t *h, void *dev_ptr, size_t bytes, void *strea
     for (double *&v : h->box_x) set(v);
     for (double *&v : h->box_b) set(v);
     for (double *&v : h->box_r) set(v);
+    for (int t = 0; t < lor_handle::kBoxStreams - 1; ++t) {
+      for (double *&v : h->box_sx[t]) set(v);
+      for (double *&v : h->box_sb[t]) set(v);
+      for (double *&v : h->box_sr[t]) set(v);
+    }
     set(h->d_box_w);
   };
   apply(false);  // dry run: resolve every pointer before anything changes

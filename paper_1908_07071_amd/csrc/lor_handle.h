@@ -87,6 +87,15 @@ struct lor_handle {
   std::vector<BoxPatchDev> boxes;  // box-patch modes: every patch's levels
   std::vector<double *> box_x, box_b, box_r;  // level vectors shared by the box patches
   double *d_box_w = nullptr;                  // partition-of-unity weights of the box patches
+  // Box patches side by side: the patches of one colour have disjoint level-0
+  // boxes and run on kBoxStreams streams, each with its own level vectors
+  // (set 0: box_x / box_b / box_r); colours one after another.
+  static constexpr int kBoxStreams = 4;
+  std::vector<double *> box_sx[kBoxStreams - 1], box_sb[kBoxStreams - 1], box_sr[kBoxStreams - 1];
+  std::vector<int> box_color;  // colour of every box (in box order)
+  int box_ncolor = 0;
+  hipStream_t box_st[kBoxStreams] = {};
+  hipEvent_t box_ev[kBoxStreams + 1] = {};
   // host copies for parity export
   std::vector<int32_t> order_all, order_off, sched_all, sched_off;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -137,6 +146,10 @@ struct lor_handle {
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : box_ev)
+      if (e) (void)hipEventDestroy(e);
+    for (hipStream_t t : box_st)
+      if (t) (void)hipStreamDestroy(t);
   }
 };
 
