@@ -138,9 +138,15 @@ typedef struct {
                                the boundary is reached); each solved like B(1)
                                on its box, plus the coarse space of eq. as.
                                The box-patch modes (SINGLE, SLABS, VERTEX_ISO)
-                               run in float64 and apply their patches one
-                               after another: meant for the iteration shape
-                               of Sections 4.1 and 4.5, not for speed       */
+                               run in float64.  A box whose dependency levels
+                               have at most sweep_grid_rows rows (and whose
+                               finest level at most 65536) runs its whole
+                               V-cycle in one workgroup, every such box in
+                               one launch; larger boxes take one launch per
+                               sweep segment and transfer, on four streams.
+                               The corrections are added to z one colour of
+                               boxes (disjoint level-0 boxes) at a time, in a
+                               fixed order: B r is bit-reproducible          */
 
 typedef struct {
   int precision;       /* LOR_PREC_*                                        */
@@ -153,7 +159,9 @@ typedef struct {
   int sweep_grid_rows; /* box-patch modes: a dependency level with more rows
                           than this is swept by a launch over the whole
                           device, runs of smaller levels by one workgroup
-                          (a barrier between levels); 0 = 512             */
+                          (a barrier between levels); a box with no such
+                          level runs its whole V-cycle in one workgroup;
+                          0 = 512                                       */
   int nslabs;          /* LOR_PATCH_SLABS: number of subdomains, 1..n[0]    */
   int deterministic;   /* 1: the vertex patches' corrections are added
                           without atomics, one vertex-parity class of

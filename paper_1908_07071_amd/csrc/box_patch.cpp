@@ -7,14 +7,16 @@
 // level-grid points strictly inside it.  Its solver is one V-cycle of the
 // element-structured LOR hierarchy (Section 3.3) restricted to the box: IC(0)
 // smoothing in the chosen elimination order on every level but the last, the
-// exact solve (a dense inverse) on the box's part of T_p.  Patches are applied
-// one after another on the caller's stream; B(1) writes z directly, the
-// others gather the patch residual and add the (optionally weighted)
-// correction back.  Float64.
+// exact solve (a dense inverse) on the box's part of T_p.  Small boxes run
+// their V-cycles one workgroup each, all in one launch; larger ones take
+// per-level launches on four streams.  B(1) writes z directly, the others
+// gather the patch residual and add the (optionally weighted) correction
+// back, one colour of boxes (disjoint level-0 boxes) at a time.  Float64.
 #include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <vector>
 
 #include "lor_handle.h"
@@ -355,7 +357,7 @@ int build_boxes(lor_handle &h, const std::vector<std::vector<double>> &hst, hipS
       }
     }
   }
-  // level vectors shared by the patches (applied one after another)
+  // level vectors of the per-level path (one set per stream)
   h.box_x.assign(L, nullptr);
   h.box_b.assign(L, nullptr);
   h.box_r.assign(L, nullptr);
@@ -394,6 +396,60 @@ int build_boxes(lor_handle &h, const std::vector<std::vector<double>> &hst, hipS
       h.box_color[j] = c;
       h.box_ncolor = std::max(h.box_ncolor, c + 1);
     }
+  }
+  // boxes for one workgroup each: no dependency level over `big` rows, a
+  // finest level of at most kBoxFuseRows rows, level vectors of their own
+  // while they fit kBoxWorkDoubles
+  {
+    const int big = h.opt.sweep_grid_rows > 0 ? h.opt.sweep_grid_rows : kGridLevel;
+    const size_t nb = h.boxes.size();
+    h.box_fused.assign(nb, 0);
+    h.box_vo.assign(nb * L, 0);
+    h.box_vl.assign(nb * L, 0);
+    int64_t total = 0;
+    std::vector<int> list;
+    for (size_t j = 0; j < nb; ++j) {
+      const BoxPatchDev &bp = h.boxes[j];
+      bool ok = bp.lv[0].n > 0 && bp.lv[0].n <= kBoxFuseRows;
+      int64_t need = 0;
+      for (int k = 0; ok && k < L && bp.lv[k].n > 0; ++k) {
+        const std::vector<int> &lp = bp.lv[k].lptr_host;
+        for (size_t l = 0; ok && l + 1 < lp.size(); ++l) ok = lp[l + 1] - lp[l] <= big;
+        need += 3 * ((bp.lv[k].n + 3) / 4 * 4);
+      }
+      if (!ok || total + need > kBoxWorkDoubles) continue;
+      h.box_fused[j] = 1;
+      list.push_back(int(j));
+      for (int k = 0; k < L && bp.lv[k].n > 0; ++k) {
+        const int64_t len = (bp.lv[k].n + 3) / 4 * 4;
+        h.box_vo[j * L + k] = total;
+        h.box_vl[j * L + k] = len;
+        total += 3 * len;
+      }
+    }
+    h.box_nfused = int(list.size());
+    h.box_grid.L = L;
+    h.box_list_off.assign(size_t(h.box_ncolor) + 1, 0);
+    h.box_unfused.assign(size_t(h.box_ncolor), 0);
+    for (int c = 0; c < h.box_ncolor; ++c) {
+      for (size_t j = 0; j < nb; ++j) {
+        if (h.box_color[j] != c || h.boxes[j].lv[0].n <= 0) continue;
+        if (h.box_fused[j]) list.push_back(int(j));
+        else ++h.box_unfused[c];
+      }
+      h.box_list_off[c + 1] = int(list.size()) - h.box_nfused;
+    }
+    if (h.box_nfused > 0) {
+      SCHK(upload(h, &h.d_box_list, list, st));
+      SCHK(h.alloc(&h.d_box_desc, nb));
+      SCHK(h.alloc(&h.d_box_work, size_t(total)));
+      const int rc = refresh_box_descs(h, st);
+      if (rc != LOR_OK) return rc;
+    }
+  }
+  bool unfused = false;
+  for (int c : h.box_unfused) unfused = unfused || c > 0;
+  if (!single && h.boxes.size() > 1 && unfused) {
     // the other streams' level vectors, the streams and their events
     for (int t = 0; t < lor_handle::kBoxStreams - 1; ++t) {
       h.box_sx[t].assign(L, nullptr);
@@ -415,6 +471,47 @@ int build_boxes(lor_handle &h, const std::vector<std::vector<double>> &hst, hipS
     SCHK(upload(h, &h.d_box_w, w, st));
     SCHK(hipStreamSynchronize(st));
   }
+  return LOR_OK;
+}
+
+int refresh_box_descs(lor_handle &h, hipStream_t st) {
+  if (!h.d_box_desc) return LOR_OK;
+  const int dim = h.dim, L = h.L;
+  BoxGrid &g = h.box_grid;
+  g.L = L;
+  for (int k = 0; k < L; ++k) {
+    const int s = int(h.kept[k].size()) - 1;
+    g.stencil[k] = h.d_stencil[k];
+    g.npts[k] = h.npts[k];
+    for (int d = 0; d < 3; ++d) g.lng[k][d] = d < dim ? h.n[d] * s + 1 : 1;
+  }
+  std::vector<BoxDesc> desc(h.boxes.size());
+  for (size_t j = 0; j < h.boxes.size(); ++j) {
+    BoxDesc &bd = desc[j];
+    std::memset(&bd, 0, sizeof(bd));
+    for (int k = 0; k < L; ++k) {
+      const SingleLevelDev &lv = h.boxes[j].lv[k];
+      BoxLevelDesc &o = bd.lv[k];
+      for (int d = 0; d < 3; ++d) {
+        o.lo[d] = lv.lo[d];
+        o.m[d] = lv.m[d];
+      }
+      o.n = int(std::max<int64_t>(lv.n, 0));
+      o.depth = lv.lptr_host.empty() ? 0 : int(lv.lptr_host.size()) - 1;
+      o.sched = lv.sched;
+      o.lptr = lv.lptr;
+      o.Lv = lv.Lv;
+      o.invD = lv.invD;
+      o.emask = lv.emask;
+      o.lmask = lv.lmask;
+      o.xf = lv.xf;
+      o.ainv = lv.ainv;
+      o.vo = h.box_vo[j * L + k];
+      o.vl = h.box_vl[j * L + k];
+    }
+  }
+  SCHK(hipMemcpyAsync(h.d_box_desc, desc.data(), desc.size() * sizeof(BoxDesc), hipMemcpyHostToDevice, st));
+  SCHK(hipStreamSynchronize(st));
   return LOR_OK;
 }
 
@@ -466,37 +563,46 @@ int vcycle(lor_handle *h, BoxPatchDev &bp, int k, const double *b, double *x, co
 
 int apply_boxes(lor_handle *h, const double *r, double *z, const double *flag, hipStream_t st) {
   if (h->boxes.empty()) return LOR_ESTATE;
-  if (h->opt.patch_mode == LOR_PATCH_SINGLE) {
+  const bool single = h->opt.patch_mode == LOR_PATCH_SINGLE;
+  if (single && h->boxes[0].lv[0].n <= 0) return LOR_OK;
+  if (single && !h->box_fused[0]) {
     // one box, the whole domain: level 0 is the L-vector
-    if (h->boxes[0].lv[0].n <= 0) return LOR_OK;
     return vcycle(h, h->boxes[0], 0, r, z, flag, st, box_bufs(h, 0));
   }
-  // colour by colour; within a colour the patches take the streams in turn
-  // (one after another on `st` while a graph is captured or events must not
-  // be recorded), the same additions to z in either case
+  // every one-workgroup box's V-cycle in one launch (B(1): straight into z);
+  // then colour by colour their corrections added to z in one launch, and
+  // the other boxes' V-cycles on the side streams in turn (one after another
+  // on `st` while a graph is captured): the same additions to z either way
+  SCHK(launch_box_vcycles(h->dim, h->d_box_desc, h->d_box_list, h->box_nfused, h->box_grid, h->md, r, z,
+                          single ? 1 : 0, h->d_box_work, flag, st));
+  if (single) return LOR_OK;
   constexpr int NS = lor_handle::kBoxStreams;
   const bool side = !h->capturing && h->box_st[0] != nullptr;
   for (int c = 0; c < h->box_ncolor; ++c) {
-    if (side) {
+    const bool fork = side && h->box_unfused[c] > 0;
+    if (fork) {
       SCHK(hipEventRecord(h->box_ev[NS], st));
       for (hipStream_t t : h->box_st) SCHK(hipStreamWaitEvent(t, h->box_ev[NS], 0));
     }
+    const int l0 = h->box_list_off[c], cnt = h->box_list_off[c + 1] - l0;
+    SCHK(launch_box_add(h->dim, h->d_box_desc, h->d_box_list + h->box_nfused + l0, cnt, h->md, h->d_box_w, z,
+                        h->d_box_work, flag, st));
     int turn = 0;
-    for (size_t j = 0; j < h->boxes.size(); ++j) {
-      if (h->box_color[j] != c) continue;
+    for (size_t j = 0; h->box_unfused[c] > 0 && j < h->boxes.size(); ++j) {
+      if (h->box_color[j] != c || h->box_fused[j]) continue;
       BoxPatchDev &bp = h->boxes[j];
-      SingleLevelDev &l0 = bp.lv[0];
-      if (l0.n <= 0) continue;
-      const int set = side ? turn++ % NS : 0;
-      hipStream_t s = side ? h->box_st[set] : st;
+      SingleLevelDev &lv0 = bp.lv[0];
+      if (lv0.n <= 0) continue;
+      const int set = fork ? turn++ % NS : 0;
+      hipStream_t s = fork ? h->box_st[set] : st;
       const BoxBufs buf = box_bufs(h, set);
       double *b0 = buf.b[0], *x0 = buf.x[0];
-      SCHK(launch_box_gather(h->dim, h->md, l0.lo, l0.m, r, b0, flag, s));
+      SCHK(launch_box_gather(h->dim, h->md, lv0.lo, lv0.m, r, b0, flag, s));
       const int rc = vcycle(h, bp, 0, b0, x0, flag, s, buf);
       if (rc != LOR_OK) return rc;
-      SCHK(launch_box_scatter(h->dim, h->md, l0.lo, l0.m, x0, h->d_box_w, z, flag, s));
+      SCHK(launch_box_scatter(h->dim, h->md, lv0.lo, lv0.m, x0, h->d_box_w, z, flag, s));
     }
-    if (side)
+    if (fork)
       for (int t = 0; t < NS; ++t) {
         SCHK(hipEventRecord(h->box_ev[t], h->box_st[t]));
         SCHK(hipStreamWaitEvent(st, h->box_ev[t], 0));

@@ -1207,7 +1207,7 @@ int lor_bind_workspace(lor_handle_t *h, void *dev_ptr, size_t bytes, void *strea
       for (double *&v : h->box_sb[t]) set(v);
       for (double *&v : h->box_sr[t]) set(v);
     }
-    set(h->d_box_w);
+    set(h->d_box_w), set(h->d_box_desc), set(h->d_box_list), set(h->d_box_work);
   };
   apply(false);  // dry run: resolve every pointer before anything changes
   if (!ok) return LOR_ESTATE;
@@ -1215,6 +1215,9 @@ int lor_bind_workspace(lor_handle_t *h, void *dev_ptr, size_t bytes, void *strea
     HIPCHK(hipMemcpyAsync(base + off[a], h->allocs[a], h->alloc_size[a], hipMemcpyDeviceToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   apply(true);
+  // the box descriptors hold device pointers: rewrite them at the new addresses
+  const int rc = refresh_box_descs(*h, st);
+  if (rc != LOR_OK) return rc;
   for (void *p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
   h->alloc_size.clear();

@@ -8,6 +8,7 @@
 #include <utility>
 #include <vector>
 
+#include "box_vcycle.h"
 #include "lor_internal.h"
 
 using namespace lor;
@@ -96,6 +97,18 @@ struct lor_handle {
   int box_ncolor = 0;
   hipStream_t box_st[kBoxStreams] = {};
   hipEvent_t box_ev[kBoxStreams + 1] = {};
+  // boxes small enough for one workgroup each: all V-cycles in one launch,
+  // then the corrections added to z one colour per launch
+  std::vector<char> box_fused;        // per box
+  std::vector<int64_t> box_vo;        // per box and level: offset of its x, b, r in d_box_work
+  std::vector<int64_t> box_vl;        // per box and level: length of each of them
+  int box_nfused = 0;                 // d_box_list[0 .. box_nfused): every one-workgroup box
+  std::vector<int> box_list_off;      // colour c: d_box_list[box_nfused + box_list_off[c] ..)
+  std::vector<int> box_unfused;       // per colour: boxes on the per-level launches
+  BoxDesc *d_box_desc = nullptr;      // every box's level descriptors (device pointers)
+  int *d_box_list = nullptr;
+  double *d_box_work = nullptr;       // the one-workgroup boxes' level vectors
+  BoxGrid box_grid{};
   // host copies for parity export
   std::vector<int32_t> order_all, order_off, sched_all, sched_off;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -170,6 +183,9 @@ int noalloc_register_device(int device);
 // the patch part of z = B r (B(1): all of it; the others add into z).
 int build_boxes(lor_handle &h, const std::vector<std::vector<double>> &hst, hipStream_t st);
 int apply_boxes(lor_handle *h, const double *r, double *z, const double *flag, hipStream_t st);
+// writes the box descriptors and the shared level layout from the handle's
+// current device pointers (after set-up and after the memory has moved)
+int refresh_box_descs(lor_handle &h, hipStream_t st);
 inline bool box_mode(int m) {
   return m == LOR_PATCH_SINGLE || m == LOR_PATCH_SLABS || m == LOR_PATCH_VERTEX_ISO;
 }

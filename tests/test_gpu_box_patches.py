@@ -122,3 +122,39 @@ def test_float32_patches_on_strip_meshes(dim, p, L, torch_dev):
             L.lor_free(h)
     print("strip", dim, p, its, flush=True)
     assert its["mixed"] <= 1.1 * its["fp64"] + 2, its
+
+
+@pytest.mark.parametrize("case", CASES + [(2, 8, 3, 1.5, "single", 0, "sum"),
+                                          (3, 4, 3, 15.0, "single", 0, "sum")], ids=_ids)
+def test_one_workgroup_boxes_match_level_launches(case, L, torch_dev):
+    """Boxes small enough for one workgroup run their whole V-cycle in it,
+    one launch per colour of boxes; sweep_grid_rows = 1 sends every box to
+    the per-level launches instead.  Same rows, same sums: B r bit for bit,
+    twice in a row (the workgroups' level vectors are reused)."""
+    torch = torch_dev
+    dim, n, p, aspect, mode, nslabs, weights = case
+    print("case", case, flush=True)
+    V = inputs.strip_vertices(n, aspect, dim=dim)
+    codes = {"vertex_iso": L.LOR_PATCH_VERTEX_ISO, "slabs": L.LOR_PATCH_SLABS, "single": L.LOR_PATCH_SINGLE}
+    out = []
+    for grid_rows in (0, 1):
+        opt = L.lor_default_options()
+        opt.patch_mode = codes[mode]
+        opt.nslabs = nslabs
+        opt.prolong_weights = L.LOR_PROLONG_POU if weights == "pou" else L.LOR_PROLONG_SUM
+        opt.sweep_grid_rows = grid_rows
+        h = L.lor_setup(dim, n, V, p, options=opt)
+        try:
+            N = L.lor_ndofs(h)
+            zs = []
+            for seed in (9, 10):
+                r = torch.tensor(inputs.gaussian_rhs(N, seed), device="cuda")
+                z = torch.empty_like(r)
+                L.lor_apply_P(h, r, z)
+                torch.cuda.synchronize()
+                zs.append(z.cpu().numpy())
+            out.append(zs)
+        finally:
+            L.lor_free(h)
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b), np.abs(a - b).max()
