@@ -177,7 +177,8 @@ def batch_measure(L, torch, nprob, nrhs, rtol, precision, seed=7):
         "config": {"workload": (f"batch of {nprob} 3D CG problems, n^3 hexes n~U{{4..24}} perturbed <=10% h, "
                                 f"p~U{{2..8}} (size seed {seed}), {nrhs} Gaussian right-hand sides each, "
                                 f"one lor_pcg_solve_batch call (the right-hand sides of a problem in lockstep, "
-                                f"their patch V-cycles in one launch per iteration; graph-captured "
+                                f"their patch V-cycles in one launch per iteration, small problems "
+                                f"sharing that launch up to 4 at a time; graph-captured "
                                 f"8-iteration chunks on 4 streams), "
                                 f"FCG to {rtol:g}"),
                    "problems": [[n, p] for n, p, _ in probs], "sum_N": sum(Ns), "pairs": len(bs),

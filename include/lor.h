@@ -306,6 +306,18 @@ int lor_apply_A(lor_handle_t *h, const double *x_dev, double *y_dev, void *strea
  * Neumann handle (no preconditioner). */
 int lor_apply_P(lor_handle_t *h, const double *r_dev, double *z_dev, void *stream);
 
+/* z_i = B_i r_i for n problems (eq. as / eq. dg-as for each), the patch
+ * corrections of up to four problems in one launch: consecutive handles
+ * with vertex patches whose corrections use atomics (not deterministic, no
+ * patch network) and of the same dimension and precision share a launch;
+ * any other handle is applied alone, as by lor_apply_P.  hs: n distinct
+ * handles (each holds one workspace); r[i], z[i]: DEVICE, ndofs(hs[i])
+ * float64 each, r[i] != z[i].  Same results as n calls of lor_apply_P up
+ * to the order of the atomic additions.  LOR_EINVAL for a repeated or null
+ * handle or vector, LOR_ESTATE for a handle without a preconditioner. */
+int lor_apply_P_batch(lor_handle_t *const *hs, int n, const double *const *r, double *const *z,
+                      void *stream);
+
 /* z = B r exactly as lor_apply_P computes it, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc): the call allocates, frees and memsets

@@ -20,6 +20,8 @@
 // Corrections of overlapping patches are added with FP64 atomics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "lor_internal.h"
 
 namespace lor {
@@ -517,19 +519,39 @@ constexpr int kSlotTableBytes = 64;
 // with WARM, start from a prediction y_j of the patch solve (patch-grid
 // values wy[block][G^d] times dscale[block], patches jfirst + block) and
 // scatter y_j + V_j(r_j - A_j y_j).
-template <int DIM, typename T, typename ST, int W, bool WARM>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_patch_vcycle(PatchArgs pa, const double *__restrict__ r_in,
+template <bool JOBS>
+struct PatchArg {
+  using type = PatchArgs;
+};
+template <>
+struct PatchArg<true> {
+  using type = PatchJobs;
+};
+__device__ __forceinline__ const PatchArgs &job_args(const PatchArgs &a, int) { return a; }
+__device__ __forceinline__ const PatchArgs &job_args(const PatchJobs &a, int k) { return a.p[k]; }
+
+// With JOBS, the launch carries several problems: the block first finds its
+// problem from the block ranges, then proceeds as in a launch of that
+// problem alone.
+template <int DIM, typename T, typename ST, int W, bool WARM, bool JOBS = false>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_patch_vcycle(typename PatchArg<JOBS>::type arg, const double *__restrict__ r_in,
                                                      double *__restrict__ z_in, const double *flag_in,
                                                      float *__restrict__ dense,
                                                      const double *__restrict__ dscale,
                                                      const float *__restrict__ wy, int jfirst) {
+  int job = 0, blk = int(blockIdx.x);
+  if constexpr (JOBS) {
+    while (job + 1 < arg.njobs && blk >= arg.block0[job + 1]) ++job;
+    blk -= arg.block0[job];
+  }
+  const PatchArgs &pa = job_args(arg, job);
   const double *__restrict__ r = r_in;
   double *__restrict__ z = z_in;
   const double *flag = flag_in;
-  int slot = int(blockIdx.x);  // the block's place in the launch order
+  int slot = blk;  // the block's place in the launch order
   if (!WARM && pa.nrhs > 0) {
     // several right-hand sides: the blocks of one patch sit 8 apart (same XCD)
-    const int b = int(blockIdx.x), t = b >> 3, k = t % pa.nrhs;
+    const int b = blk, t = b >> 3, k = t % pa.nrhs;
     slot = (t / pa.nrhs) * 8 + (b & 7);
     if (slot >= pa.nv[0] * pa.nv[1] * (DIM == 3 ? pa.nv[2] : 1)) return;
     r = pa.rs[k];
@@ -550,7 +572,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       c[d] = (pa.color >> d) & 1;
       nvc[d] = d < DIM ? (pa.nv[d] - c[d] + 1) / 2 : 1;
     }
-    const int i = int(blockIdx.x);
+    const int i = blk;
     const int vx = 2 * (i % nvc[0]) + c[0], vy = 2 * ((i / nvc[0]) % nvc[1]) + c[1],
               vz = DIM == 3 ? 2 * (i / (nvc[0] * nvc[1])) + c[2] : 0;
     j = vx + pa.nv[0] * (vy + pa.nv[1] * vz);
@@ -797,8 +819,26 @@ constexpr int kMaxDynLds = 160 * 1024;
 template <int DIM, typename T, typename ST, bool WARM>
 hipError_t prepare_t() {
   constexpr int W = DIM == 3 ? 26 : 8;
-  return hipFuncSetAttribute((const void *)k_patch_vcycle<DIM, T, ST, W, WARM>,
+  hipError_t e = hipFuncSetAttribute((const void *)k_patch_vcycle<DIM, T, ST, W, WARM>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+  if (e != hipSuccess || WARM) return e;
+  return hipFuncSetAttribute((const void *)k_patch_vcycle<DIM, T, ST, W, false, true>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+}
+
+static_assert(sizeof(PatchJobs) <= 4000, "the jobs travel as a kernel argument (4 KiB at most)");
+
+template <int DIM, typename T, typename ST>
+hipError_t launch_jobs_t(const PatchJobs &pj, int64_t blocks, hipStream_t st) {
+  constexpr int W = DIM == 3 ? 26 : 8;
+  size_t lds = 0;
+  for (int k = 0; k < pj.njobs; ++k)
+    lds = std::max(lds, lds_values<DIM, false>(pj.p[k]) * sizeof(T) + kSlotTableBytes);
+  if (lds > size_t(kMaxDynLds) || blocks > int64_t(INT32_MAX)) return hipErrorInvalidValue;
+  if (blocks <= 0) return hipSuccess;
+  k_patch_vcycle<DIM, T, ST, W, false, true><<<int(blocks), 64, lds, st>>>(pj, nullptr, nullptr, nullptr, nullptr,
+                                                                         nullptr, nullptr, 0);
+  return hipGetLastError();
 }
 
 template <int DIM, typename T, typename ST, bool WARM>
@@ -885,6 +925,33 @@ hipError_t launch_patch_vcycle_multi(const PatchArgs &pa, int npatch, int nrhs,
   if (pa.md.dim == 3)
     return launch_t<3, double, double, false>(pm, int(blocks), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, st);
   return launch_t<2, double, double, false>(pm, int(blocks), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, st);
+}
+
+hipError_t launch_patch_vcycle_jobs(const PatchArgs *jobs, int njobs, hipStream_t st) {
+  if (!jobs || njobs < 1 || njobs > kMaxJobs) return hipErrorInvalidValue;
+  PatchJobs pj{};
+  pj.njobs = njobs;
+  int64_t blocks = 0;
+  for (int k = 0; k < njobs; ++k) {
+    const PatchArgs &a = jobs[k];
+    if (a.md.dim != jobs[0].md.dim || a.fp32 != jobs[0].fp32 || a.plain || a.color >= 0 ||
+        a.nrhs < 1 || a.nrhs > kMaxRhs)
+      return hipErrorInvalidValue;
+    for (int i = 0; i < a.nrhs; ++i)
+      if (!a.rs[i] || !a.zs[i]) return hipErrorInvalidValue;
+    int64_t J = 1;
+    for (int d = 0; d < a.md.dim; ++d) J *= a.nv[d];
+    pj.p[k] = a;
+    pj.block0[k] = int(std::min<int64_t>(blocks, INT32_MAX));
+    blocks += (J + 7) / 8 * 8 * a.nrhs;
+  }
+  if (blocks > int64_t(INT32_MAX)) return hipErrorInvalidValue;
+  pj.block0[njobs] = int(blocks);
+  if (jobs[0].fp32)
+    return jobs[0].md.dim == 3 ? launch_jobs_t<3, float, float>(pj, blocks, st)
+                               : launch_jobs_t<2, float, float>(pj, blocks, st);
+  return jobs[0].md.dim == 3 ? launch_jobs_t<3, double, double>(pj, blocks, st)
+                             : launch_jobs_t<2, double, double>(pj, blocks, st);
 }
 
 hipError_t launch_patch_vcycle_warm(const PatchArgs &pa, int first, int count, const double *r,

@@ -10,6 +10,7 @@
 #include <memory>
 #include <new>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "lor_handle.h"
@@ -706,6 +707,8 @@ int apply_A_impl(lor_handle *h, Work &w, const double *x, double *y, double *par
 
 constexpr int kChunk = 8;         // iterations between host checks / per captured graph
 constexpr int kBatchStreams = 4;  // worker streams of a batched solve (HIP's hardware queues)
+constexpr int64_t kJobBlocks = 2048;  // patch blocks of a shared launch: about 2/3 of one
+                                      // round of resident patches on 256 CUs
 
 // Enqueues x = 0, r = b, z = B r, p = z, rho = r.z and the scalars of a new
 // solve (no memset nodes, so that the sequence can be captured).
@@ -811,6 +814,54 @@ int pcg_iterations_multi(lor_handle *h, Work *const *w, double *const *x, int n,
       int rc = pcg_iter_post(h, *w[k], st);
       if (rc != LOR_OK) return rc;
     }
+  }
+  return LOR_OK;
+}
+
+// Up to kMaxRhs right-hand sides of one handle, as one problem of a
+// multi-problem patch launch.
+struct PatchJob {
+  lor_handle *h = nullptr;
+  Work *w[kMaxRhs] = {};
+  double *x[kMaxRhs] = {};
+  int n = 0;
+};
+
+// The patch launch arguments of a job: the handle's, with the job's patch
+// inputs, outputs and convergence flags (null flags: never stop).
+PatchArgs job_patch_args(const PatchJob &jb, bool flags) {
+  PatchArgs a = jb.h->pa;
+  a.nrhs = jb.n;
+  for (int k = 0; k < kMaxRhs; ++k) {
+    a.rs[k] = nullptr;
+    a.zs[k] = nullptr;
+    a.flags[k] = nullptr;
+  }
+  for (int k = 0; k < jb.n; ++k) {
+    patch_io(jb.h, *jb.w[k], jb.w[k]->r, jb.w[k]->z, &a.rs[k], &a.zs[k]);
+    a.flags[k] = flags ? jb.w[k]->scal : nullptr;
+  }
+  return a;
+}
+
+// Enqueues `count` iterations of the solves of up to kMaxJobs jobs in
+// lockstep: the patch corrections of all of them in one launch.
+int pcg_iterations_jobs(const PatchJob *jobs, int njobs, int count, hipStream_t st) {
+  if (njobs < 1 || njobs > kMaxJobs) return LOR_EINVAL;
+  PatchArgs pa[kMaxJobs];
+  for (int j = 0; j < njobs; ++j) pa[j] = job_patch_args(jobs[j], true);
+  for (int i = 0; i < count; ++i) {
+    for (int j = 0; j < njobs; ++j)
+      for (int k = 0; k < jobs[j].n; ++k) {
+        int rc = pcg_iter_pre(jobs[j].h, *jobs[j].w[k], jobs[j].x[k], st);
+        if (rc != LOR_OK) return rc;
+      }
+    HIPCHK(launch_patch_vcycle_jobs(pa, njobs, st));
+    for (int j = 0; j < njobs; ++j)
+      for (int k = 0; k < jobs[j].n; ++k) {
+        int rc = pcg_iter_post(jobs[j].h, *jobs[j].w[k], st);
+        if (rc != LOR_OK) return rc;
+      }
   }
   return LOR_OK;
 }
@@ -1296,6 +1347,54 @@ int lor_apply_P(lor_handle_t *h, const double *r_dev, double *z_dev, void *strea
   return apply_P_impl(h, h->w, r_dev, z_dev, nullptr, static_cast<hipStream_t>(stream));
 }
 
+int lor_apply_P_batch(lor_handle_t *const *hs, int n, const double *const *r, double *const *z,
+                      void *stream) {
+  if (!hs || !r || !z || n < 1) return LOR_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i] || !r[i] || !z[i] || r[i] == z[i]) return LOR_EINVAL;
+    if (!hs[i]->has_prec) return LOR_ESTATE;
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return LOR_EINVAL;  // one workspace per handle
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int i0 = 0; i0 < n;) {
+    // a run of handles whose patch corrections can share a launch
+    int i1 = i0 + 1;
+    if (multi_rhs_patches(hs[i0]))
+      while (i1 < n && i1 - i0 < kMaxJobs && multi_rhs_patches(hs[i1]) &&
+             hs[i1]->dim == hs[i0]->dim && hs[i1]->pa.fp32 == hs[i0]->pa.fp32)
+        ++i1;
+    if (i1 - i0 == 1) {
+      const int rc = apply_P_impl(hs[i0], hs[i0]->w, r[i0], z[i0], nullptr, st);
+      if (rc != LOR_OK) return rc;
+      i0 = i1;
+      continue;
+    }
+    PatchArgs pa[kMaxJobs];
+    for (int i = i0; i < i1; ++i) {
+      lor_handle *h = hs[i];
+      const int rc = apply_P_pre(h, h->w, r[i], z[i], nullptr, st);
+      if (rc != LOR_OK) return rc;
+      PatchArgs &a = pa[i - i0];
+      a = h->pa;
+      a.nrhs = 1;
+      for (int k = 0; k < kMaxRhs; ++k) {
+        a.rs[k] = nullptr;
+        a.zs[k] = nullptr;
+        a.flags[k] = nullptr;
+      }
+      patch_io(h, h->w, r[i], z[i], &a.rs[0], &a.zs[0]);
+    }
+    HIPCHK(launch_patch_vcycle_jobs(pa, i1 - i0, st));
+    for (int i = i0; i < i1; ++i) {
+      const int rc = apply_P_post(hs[i], hs[i]->w, r[i], z[i], nullptr, st);
+      if (rc != LOR_OK) return rc;
+    }
+    i0 = i1;
+  }
+  return LOR_OK;
+}
+
 int lor_pcg_solve(lor_handle_t *h, const double *b, double *x, double rtol, int maxit,
                   lor_solve_info_t *info, void *stream) {
   if (!h || !b || !x || b == x || !(rtol >= 0.0) || maxit < 0) return LOR_EINVAL;
@@ -1362,11 +1461,20 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
     int nrep = 0;
     double last_true = HUGE_VAL;
   };
-  // The right-hand sides of one problem run in lockstep in groups of up to
-  // kMaxRhs pairs (one captured chunk, the patch corrections of the group in
-  // one launch) where the handle's preconditioner allows it, else alone.
-  struct Group {
+  // The right-hand sides of one problem form parts of up to kMaxRhs pairs
+  // where the handle's preconditioner allows their patch corrections in one
+  // launch, else parts of one pair.  A group is one captured chunk of
+  // iterations of its parts in lockstep; with more parts than streams, small
+  // parts of like dimension and precision share groups of up to kMaxJobs,
+  // their patch corrections in one launch for all of them.
+  struct Part {
     int first = 0, n = 1;
+    bool multi = false;
+    double cost = 0.0;
+  };
+  struct Group {
+    std::vector<Part> parts;
+    double cost = 0.0;
     hipStream_t st = nullptr;
     hipGraphExec_t chunk = nullptr;
   };
@@ -1396,12 +1504,56 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
     hipError_t e_ = (x);                                     \
     if (e_ != hipSuccess) return fail(hip_fail(e_, #x, __LINE__)); \
   } while (0)
-  for (int i = 0; i < nprob; ++i) {
-    const int step = multi_rhs_patches(hs[i]) ? kMaxRhs : 1;
-    for (int j = 0; j < nrhs; j += step) {
+  {
+    std::vector<Part> parts;
+    for (int i = 0; i < nprob; ++i) {
+      const bool multi = multi_rhs_patches(hs[i]);
+      const int step = multi ? kMaxRhs : 1;
+      for (int j = 0; j < nrhs; j += step) {
+        Part pt;
+        pt.first = i * nrhs + j;
+        pt.n = std::min(step, nrhs - j);
+        pt.multi = multi;
+        pt.cost = double(hs[i]->ndofs) * pt.n;
+        parts.push_back(pt);
+      }
+    }
+    // a part whose patch launch alone cannot fill the device shares one:
+    // by dimension and precision, similar patch sizes together (the launch
+    // reserves the largest patch's LDS for every patch), up to kMaxJobs
+    // parts and kJobBlocks patch blocks per group
+    const bool share = int(parts.size()) > kBatchStreams;
+    auto blocks = [&](const Part &pt) { return int64_t(hs[pt.first / nrhs]->J + 7) / 8 * 8 * pt.n; };
+    std::vector<size_t> small;
+    for (size_t a = 0; a < parts.size(); ++a) {
+      if (share && parts[a].multi && blocks(parts[a]) < kJobBlocks) {
+        small.push_back(a);
+        continue;
+      }
       Group g;
-      g.first = i * nrhs + j;
-      g.n = std::min(step, nrhs - j);
+      g.parts.push_back(parts[a]);
+      g.cost = parts[a].cost;
+      groups.push_back(g);
+    }
+    auto key = [&](size_t a) {
+      const lor_handle *h = hs[parts[a].first / nrhs];
+      return std::make_tuple(h->dim, h->pa.fp32, -h->pa.lds_total);
+    };
+    std::stable_sort(small.begin(), small.end(), [&](size_t x, size_t y) { return key(x) < key(y); });
+    for (size_t i = 0; i < small.size();) {
+      Group g;
+      int64_t nb = 0;
+      const lor_handle *h0 = hs[parts[small[i]].first / nrhs];
+      while (i < small.size() && int(g.parts.size()) < kMaxJobs) {
+        const Part &pt = parts[small[i]];
+        const lor_handle *h = hs[pt.first / nrhs];
+        if (!g.parts.empty() && (h->dim != h0->dim || h->pa.fp32 != h0->pa.fp32 || nb + blocks(pt) > kJobBlocks))
+          break;
+        g.parts.push_back(pt);
+        g.cost += pt.cost;
+        nb += blocks(pt);
+        ++i;
+      }
       groups.push_back(g);
     }
   }
@@ -1421,9 +1573,20 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
     // a handle may serve several problems: its pairs take consecutive
     // cached workspaces
     std::vector<std::pair<lor_handle *, int>> used;
-    for (size_t gi = 0; gi < groups.size(); ++gi) {
-      groups[gi].st = streams[gi % ns];
-      for (int k = groups[gi].first; k < groups[gi].first + groups[gi].n; ++k) pairs[k].st = groups[gi].st;
+    // the costliest group first, each to the least loaded stream
+    std::vector<size_t> order(groups.size());
+    for (size_t gi = 0; gi < order.size(); ++gi) order[gi] = gi;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b2) { return groups[a].cost > groups[b2].cost; });
+    std::vector<double> load(ns, 0.0);
+    for (size_t gi : order) {
+      int t = 0;
+      for (int u = 1; u < ns; ++u)
+        if (load[u] < load[t]) t = u;
+      load[t] += groups[gi].cost;
+      groups[gi].st = streams[t];
+      for (const Part &pt : groups[gi].parts)
+        for (int k = pt.first; k < pt.first + pt.n; ++k) pairs[k].st = groups[gi].st;
     }
     for (int k = 0; k < npair; ++k) {
       Pair &q = pairs[k];
@@ -1449,23 +1612,28 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
   // pair has converged, so the chunk is replayed until every pair's flag is
   // set)
   for (Group &gr : groups) {
-    lor_handle *h = pairs[gr.first].h;
-    hipGraph_t g = nullptr;
-    h->capturing = true;
-    BCHK(hipStreamBeginCapture(gr.st, hipStreamCaptureModeThreadLocal));
-    if (gr.n > 1) {
-      Work *ws[kMaxRhs];
-      double *xs[kMaxRhs];
-      for (int k = 0; k < gr.n; ++k) {
-        ws[k] = &pairs[gr.first + k].w;
-        xs[k] = x[gr.first + k];
+    PatchJob jobs[kMaxJobs];
+    const int nj = int(gr.parts.size());
+    for (int j = 0; j < nj; ++j) {
+      const Part &pt = gr.parts[j];
+      jobs[j].h = pairs[pt.first].h;
+      jobs[j].n = pt.n;
+      for (int k = 0; k < pt.n; ++k) {
+        jobs[j].w[k] = &pairs[pt.first + k].w;
+        jobs[j].x[k] = x[pt.first + k];
       }
-      rc = pcg_iterations_multi(h, ws, xs, gr.n, kChunk, gr.st);
-    } else {
-      rc = pcg_iterations(h, pairs[gr.first].w, x[gr.first], kChunk, gr.st);
+      jobs[j].h->capturing = true;
     }
+    hipGraph_t g = nullptr;
+    BCHK(hipStreamBeginCapture(gr.st, hipStreamCaptureModeThreadLocal));
+    if (nj > 1)
+      rc = pcg_iterations_jobs(jobs, nj, kChunk, gr.st);
+    else if (jobs[0].n > 1)
+      rc = pcg_iterations_multi(jobs[0].h, jobs[0].w, jobs[0].x, jobs[0].n, kChunk, gr.st);
+    else
+      rc = pcg_iterations(jobs[0].h, *jobs[0].w[0], jobs[0].x[0], kChunk, gr.st);
     hipError_t e = hipStreamEndCapture(gr.st, &g);
-    h->capturing = false;
+    for (int j = 0; j < nj; ++j) jobs[j].h->capturing = false;
     if (rc != LOR_OK) {
       if (g) (void)hipGraphDestroy(g);
       return fail(rc);
@@ -1494,16 +1662,18 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
       bool any = false;
       for (Group &gr : groups) {
         bool live = false;
-        for (int k = gr.first; k < gr.first + gr.n; ++k) live = live || !pairs[k].done;
+        for (const Part &pt : gr.parts)
+          for (int k = pt.first; k < pt.first + pt.n; ++k) live = live || !pairs[k].done;
         if (!live) continue;
         any = true;
         BCHK(hipGraphLaunch(gr.chunk, gr.st));
-        for (int k = gr.first; k < gr.first + gr.n; ++k) {
-          Pair &q = pairs[k];
-          BCHK(hipMemcpyAsync(q.w.h_scal, q.w.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
-                              q.st));
-          q.it += kChunk;
-        }
+        for (const Part &pt : gr.parts)
+          for (int k = pt.first; k < pt.first + pt.n; ++k) {
+            Pair &q = pairs[k];
+            BCHK(hipMemcpyAsync(q.w.h_scal, q.w.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                                q.st));
+            q.it += kChunk;
+          }
       }
       if (!any) break;
       for (hipStream_t t : streams) BCHK(hipStreamSynchronize(t));

@@ -70,6 +70,16 @@ struct PatchArgs {
   const double *flags[kMaxRhs];
 };
 
+// The patch corrections of several problems in one launch (see
+// launch_patch_vcycle_jobs): problem k's blocks are [block0[k], block0[k+1]),
+// laid out as in a multi-right-hand-side launch of p[k] (p[k].nrhs >= 1).
+constexpr int kMaxJobs = 4;
+struct PatchJobs {
+  PatchArgs p[kMaxJobs];
+  int njobs;
+  int block0[kMaxJobs + 1];
+};
+
 // Sweep block: the data of one ILU(0) triangular sweep (forward or backward)
 // of one (patch, level), laid out for a 64-lane wavefront.
 //   header (kSweepHeader B): int32 nchunks, uint32 hdr0 (header of chunk 0),
@@ -255,6 +265,10 @@ hipError_t launch_patch_vcycle(const PatchArgs &pa, int npatch, const double *r,
 hipError_t launch_patch_vcycle_multi(const PatchArgs &pa, int npatch, int nrhs,
                                      const double *const *r, double *const *z,
                                      const double *const *flags, hipStream_t st);
+// The patch corrections of njobs problems (dimension and precision alike,
+// up to kMaxJobs, each with jobs[k].nrhs right-hand sides in jobs[k].rs,
+// zs, flags) in one launch sized for the largest patch of any of them.
+hipError_t launch_patch_vcycle_jobs(const PatchArgs *jobs, int njobs, hipStream_t st);
 // Warm start of the patch V-cycles for patches first .. first + count - 1
 // (3D): y [count][(2p-1)^3] predictions on the patch grid, scale [count];
 // z += y_j + V_j(r_j - A_j y_j) (scaled) for each.

@@ -38,7 +38,7 @@ EXPORTED = [
     "lor_nn_param_count", "lor_nn_create", "lor_nn_get_params", "lor_nn_shape", "lor_nn_patch_data",
     "lor_nn_forward", "lor_nn_gradients", "lor_nn_train_step", "lor_nn_attach", "lor_nn_free",
     "lor_bf16_gemm", "lor_apply_P_noalloc", "lor_noalloc_scratch_bytes", "lor_workspace_bytes",
-    "lor_bind_workspace", "lor_element_coords", "lor_launch_order", "lor_f64_gemm",
+    "lor_bind_workspace", "lor_element_coords", "lor_launch_order", "lor_f64_gemm", "lor_apply_P_batch",
 ]
 LOR_NN_OFF, LOR_NN_REPLACE, LOR_NN_WARMSTART = 0, 1, 2
 LOR_T_APPLY_A, LOR_T_PATCH, LOR_T_COARSE = 0, 1, 2
@@ -96,6 +96,7 @@ def _load():
         "lor_apply_A": (C.c_int, [vp, vp, vp, vp]),
         "lor_apply_P": (C.c_int, [vp, vp, vp, vp]),
         "lor_apply_P_noalloc": (C.c_int, [vp, vp, vp, vp]),
+        "lor_apply_P_batch": (C.c_int, [C.POINTER(vp), C.c_int, C.POINTER(vp), C.POINTER(vp), vp]),
         "lor_noalloc_scratch_bytes": (C.c_int, [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         "lor_pcg_solve": (C.c_int, [vp, vp, vp, C.c_double, C.c_int, C.POINTER(lor_solve_info_t), vp]),
         "lor_export_maps": (C.c_int, [vp, C.c_int, i32p, i64p]),
@@ -320,6 +321,22 @@ def lor_pcg_solve(h, b, x, rtol: float = 1e-8, maxit: int = 1000, stream=None, c
     if check and rc not in (LOR_OK,):
         raise LorError(rc, "lor_pcg_solve")
     return info
+
+
+def lor_apply_P_batch(handles, r, z, stream=None):
+    """z[i] = B_i r[i] for every handle, patch corrections of like handles in
+    one launch."""
+    n = len(handles)
+    if n == 0 or len(r) != n or len(z) != n:
+        raise ValueError("one r and one z per handle")
+    for i in range(n):
+        m = lor_ndofs(handles[i])
+        if r[i].numel() != m or z[i].numel() != m:
+            raise ValueError(f"problem {i}: vectors must have {m} entries")
+    hs = (C.c_void_p * n)(*[h.value for h in handles])
+    rp = (C.c_void_p * n)(*[_dev(t, "r").value for t in r])
+    zp = (C.c_void_p * n)(*[_dev(t, "z").value for t in z])
+    _check(_lib.lor_apply_P_batch(hs, n, rp, zp, _stream(stream)), "lor_apply_P_batch")
 
 
 def lor_pcg_solve_batch(handles, b, x, rtol: float = 1e-8, maxit: int = 1000, stream=None,

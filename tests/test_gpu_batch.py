@@ -55,7 +55,10 @@ def _setup(L, prob):
 def test_batch_matches_single_solves(nrhs, probs, L, torch_dev):
     """The right-hand sides of a problem run in lockstep groups of up to four
     (one patch launch per group and iteration): three per problem, and five
-    (a group of four and one of one) on two problems."""
+    (a group of four and one of one) on two problems.  Iteration counts
+    within one (CG) or two (DG: near its residual plateau the oracle's own
+    count moves by up to three under 1e-14 relative perturbations of the
+    preconditioner, see test_batch_matches_oracle) of the single solve."""
     torch = torch_dev
     hs = [_setup(L, pr) for pr in probs]
     try:
@@ -72,7 +75,8 @@ def test_batch_matches_single_solves(nrhs, probs, L, torch_dev):
             h = hs[k // nrhs]
             x1 = torch.zeros_like(bs[k])
             ref = L.lor_pcg_solve(h, bs[k], x1, rtol=1e-9, maxit=600)
-            assert info.status == L.LOR_OK and abs(info.iters - ref.iters) <= 1, (k, info.iters, ref.iters)
+            slack = 1 if probs[k // nrhs][5] == "cg" else 2
+            assert info.status == L.LOR_OK and abs(info.iters - ref.iters) <= slack, (k, info.iters, ref.iters)
             err = (xs[k] - x1).abs().max().item() / x1.abs().max().item()
             assert err <= 1e-8, (k, err)
             assert info.rel_res <= 1e-9 and info.rel_res_true <= 1.05e-9
@@ -150,6 +154,95 @@ def test_batch_maxit_and_errors(L, torch_dev):
             assert e.value.code == L.LOR_ESTATE
         finally:
             L.lor_free(hn)
+    finally:
+        for h in hs:
+            L.lor_free(h)
+
+
+MERGED = [
+    # eight 3D float32-patch problems: more parts than streams, so their
+    # patch corrections share launches (two problems per launch)
+    (3, (2, 2, 2), 2, 0.1, 51, "cg", 0.0, "mixed"),
+    (3, (2, 2, 2), 3, 0.1, 52, "cg", 0.0, "mixed"),
+    (3, (3, 2, 2), 4, 0.1, 53, "cg", 0.0, "mixed"),
+    (3, (2, 2, 2), 6, 0.1, 54, "cg", 0.0, "mixed"),
+    (3, (2, 3, 2), 5, 0.1, 55, "cg", 0.0, "mixed"),
+    (3, (2, 2, 1), 3, 0.1, 56, "ip", 1.5 * 16, "mixed"),
+    (3, (1, 2, 2), 7, 0.1, 57, "cg", 0.0, "mixed"),
+    (3, (2, 2, 2), 8, 0.1, 58, "cg", 0.0, "mixed"),
+]
+
+
+def test_batch_shared_patch_launches(L, torch_dev):
+    """More lockstep parts than streams: the parts of like dimension and
+    precision share captured chunks, the patch corrections of a chunk's
+    problems (each with its two right-hand sides) in one launch sized for
+    the largest patch among them.  Every pair against its own single solve."""
+    torch = torch_dev
+    nrhs = 2
+    hs = [_setup(L, pr) for pr in MERGED]
+    try:
+        bs, xs = [], []
+        for i, h in enumerate(hs):
+            N = L.lor_ndofs(h)
+            for j in range(nrhs):
+                bs.append(torch.tensor(inputs.gaussian_rhs(N, 300 * i + j), device="cuda"))
+                xs.append(torch.zeros(N, dtype=torch.float64, device="cuda"))
+        print("batch of", len(bs), "pairs", flush=True)
+        infos = L.lor_pcg_solve_batch(hs, bs, xs, rtol=1e-9, maxit=800)
+        torch.cuda.synchronize()
+        for k, info in enumerate(infos):
+            h = hs[k // nrhs]
+            x1 = torch.zeros_like(bs[k])
+            ref = L.lor_pcg_solve(h, bs[k], x1, rtol=1e-9, maxit=800)
+            slack = 1 if MERGED[k // nrhs][5] == "cg" else 2
+            assert info.status == L.LOR_OK and abs(info.iters - ref.iters) <= slack, (k, info.iters, ref.iters)
+            err = (xs[k] - x1).abs().max().item() / x1.abs().max().item()
+            assert err <= 1e-8, (k, err)
+            assert info.rel_res_true <= 1.05e-9
+    finally:
+        for h in hs:
+            L.lor_free(h)
+
+
+def test_apply_P_batch(L, torch_dev):
+    """lor_apply_P_batch: like handles (3D float32 patches; 2D float64
+    patches) share patch launches, the deterministic handle runs alone; each
+    z_i against lor_apply_P on the same handle (float64 atomics: the order
+    of the additions only), and the float64 2D problems against the oracle's
+    B r."""
+    torch = torch_dev
+    probs = MERGED[:5] + [
+        (2, (4, 3), 4, 0.1, 61, "cg", 0.0, "fp64"),
+        (2, (3, 3), 3, 0.1, 62, "cg", 0.0, "fp64"),
+        (2, (3, 3), 5, 0.0, 63, "br2", 10.0, "fp64"),
+    ]
+    hs = [_setup(L, pr) for pr in probs]
+    opt = L.lor_default_options()
+    opt.deterministic = 1
+    V = inputs.structured_vertices(3, [2, 2, 2], 0.1, seed=64)
+    hs.append(L.lor_setup(3, [2, 2, 2], V, 4, options=opt))
+    try:
+        rs = [torch.tensor(inputs.gaussian_rhs(L.lor_ndofs(h), 500 + i), device="cuda") for i, h in enumerate(hs)]
+        zs = [torch.empty_like(r) for r in rs]
+        for rep in range(2):  # the second call reuses every workspace
+            L.lor_apply_P_batch(hs, rs, zs)
+            torch.cuda.synchronize()
+            for i, h in enumerate(hs):
+                z1 = torch.empty_like(rs[i])
+                L.lor_apply_P(h, rs[i], z1)
+                torch.cuda.synchronize()
+                err = (zs[i] - z1).abs().max().item() / z1.abs().max().item()
+                assert err <= 1e-13, (rep, i, err)
+        for i in (5, 6):
+            dim, n, p, pert, seed, method, eta, prec = probs[i]
+            mesh = M.make_mesh(dim, list(n), inputs.structured_vertices(dim, list(n), pert, seed=seed))
+            zref = S.SchwarzLOR(mesh, p).apply(rs[i].cpu().numpy())
+            err = np.abs(zs[i].cpu().numpy() - zref).max() / np.abs(zref).max()
+            assert err <= 1e-12, (i, err)
+        with pytest.raises(L.LorError) as e:
+            L.lor_apply_P_batch([hs[0], hs[0]], rs[:1] * 2, [zs[0], torch.empty_like(zs[0])])
+        assert e.value.code == L.LOR_EINVAL
     finally:
         for h in hs:
             L.lor_free(h)
