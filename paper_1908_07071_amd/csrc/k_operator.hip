@@ -12,6 +12,8 @@
 // CG gets p^T K p without another pass over the vectors.
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 #include "lor_internal.h"
 
 namespace lor {
@@ -396,44 +398,83 @@ void k_apply_pw3(MeshDims md, const double *__restrict__ G, const double *__rest
 // y on the element skeleton (GLL grid nodes with some coordinate on an
 // element interface): the sum over the elements sharing the node of their
 // element-local results yE, added in a fixed element order.  Nodes inside
-// one element were stored by the element kernel.
+// one element were stored by the element kernel.  One thread per skeleton
+// node only: first the grid planes whose z coordinate is an element
+// interface (every node of them), then, in the other planes, the grid lines
+// whose y coordinate is one (every node), then the rest of those planes'
+// nodes whose x coordinate is one.
+struct SkeletonParts {
+  int64_t nA, nB, nC;  // nodes of the three parts
+  int fx, fy, fz;      // interface coordinates per direction among the unknowns
+};
+
+__host__ __device__ inline SkeletonParts skeleton_parts(const MeshDims &md) {
+  SkeletonParts s;
+  const int f = md.dirichlet ? -1 : 1;
+  s.fx = md.n[0] + f;
+  s.fy = md.n[1] + f;
+  s.fz = md.n[2] + f;
+  s.nA = int64_t(s.fz) * md.nu[0] * md.nu[1];
+  s.nB = int64_t(md.nu[2] - s.fz) * s.fy * md.nu[0];
+  s.nC = int64_t(md.nu[2] - s.fz) * (md.nu[1] - s.fy) * s.fx;
+  return s;
+}
+
 template <int Q>
-__global__ void k_skeleton_gather(MeshDims md, const double *__restrict__ yE,
-                                  double *__restrict__ y, const double *flag) {
+__global__ __launch_bounds__(256) void k_skeleton_gather(MeshDims md, SkeletonParts sp,
+                                                         const double *__restrict__ yE,
+                                                         double *__restrict__ y, const double *flag) {
   if (flag && flag[S_DONE] != 0.0) return;
   constexpr int Q3 = Q * Q * Q;
-  const int p = Q - 1;
+  constexpr int p = Q - 1;
   const int ox = md.dirichlet ? 1 : 0;
-  // one block row per grid line (y, z): the line index is uniform, so the
-  // only division by a run-time extent is done once per block
-  const int line = int(blockIdx.y);
-  const int ly = line % md.nu[1], lz = line / md.nu[1];
-  const int ix = int(blockIdx.x * blockDim.x + threadIdx.x);
-  if (ix < md.nu[0]) {
-    const int64_t i = ix + int64_t(md.nu[0]) * line;
-    const int g[3] = {ix + ox, ly + ox, lz + ox};
-    if (g[0] % p != 0 && g[1] % p != 0 && g[2] % p != 0) return;
-    double acc = 0.0;
-    for (int cb = 0; cb < 8; ++cb) {
-      int e[3], l[3];
-      bool ok = true;
-      for (int d = 0; d < 3; ++d) {
-        if (((cb >> d) & 1) == 0) {
-          e[d] = g[d] / p;
-          l[d] = g[d] - e[d] * p;
-          if (e[d] >= md.n[d]) ok = false;
-        } else {
-          if (g[d] % p != 0 || g[d] == 0) ok = false;
-          e[d] = g[d] / p - 1;
-          l[d] = p;
-        }
-      }
-      if (!ok) continue;
-      const int64_t ei = e[0] + int64_t(md.n[0]) * (e[1] + int64_t(md.n[1]) * e[2]);
-      acc += yE[ei * Q3 + l[0] + Q * (l[1] + Q * l[2])];
-    }
-    y[i] = acc;
+  const int nx = md.nu[0], ny = md.nu[1];
+  // k-th grid coordinate of an interface, and k-th one strictly inside an element
+  auto face = [&](int64_t k) { return int(k + ox) * p; };
+  auto inner = [&](int64_t k) { return int(k + k / (p - 1) + 1); };
+  int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int g[3];
+  if (t < sp.nA) {
+    const int64_t per = int64_t(nx) * ny;
+    const int64_t kz = t / per, rem = t - kz * per, iy = rem / nx;
+    g[0] = int(rem - iy * nx) + ox;
+    g[1] = int(iy) + ox;
+    g[2] = face(kz);
+  } else if ((t -= sp.nA) < sp.nB) {
+    const int64_t per = int64_t(sp.fy) * nx;
+    const int64_t kz = t / per, rem = t - kz * per, ky = rem / nx;
+    g[0] = int(rem - ky * nx) + ox;
+    g[1] = face(ky);
+    g[2] = inner(kz);
+  } else if ((t -= sp.nB) < sp.nC) {
+    const int64_t per = int64_t(ny - sp.fy) * sp.fx;
+    const int64_t kz = t / per, rem = t - kz * per, ky = rem / sp.fx;
+    g[0] = face(rem - ky * sp.fx);
+    g[1] = inner(ky);
+    g[2] = inner(kz);
+  } else {
+    return;
   }
+  double acc = 0.0;
+  for (int cb = 0; cb < 8; ++cb) {
+    int e[3], l[3];
+    bool ok = true;
+    for (int d = 0; d < 3; ++d) {
+      if (((cb >> d) & 1) == 0) {
+        e[d] = g[d] / p;
+        l[d] = g[d] - e[d] * p;
+        if (e[d] >= md.n[d]) ok = false;
+      } else {
+        if (g[d] % p != 0 || g[d] == 0) ok = false;
+        e[d] = g[d] / p - 1;
+        l[d] = p;
+      }
+    }
+    if (!ok) continue;
+    const int64_t ei = e[0] + int64_t(md.n[0]) * (e[1] + int64_t(md.n[1]) * e[2]);
+    acc += yE[ei * Q3 + l[0] + Q * (l[1] + Q * l[2])];
+  }
+  y[(g[0] - ox) + int64_t(nx) * ((g[1] - ox) + int64_t(ny) * (g[2] - ox))] = acc;
 }
 
 // 2D: one thread per element node, Q^2 threads per element.
@@ -588,9 +629,12 @@ hipError_t apply_q(const MeshDims &md, const double *G, const double *D, const d
         else
           k_apply_pw3<Q, false><<<int(nel), Q * 64, 0, st>>>(md, G, D, x, y, partials, flag,
                                                              nullptr, yE);
-        const dim3 grid((md.nu[0] + 127) / 128, unsigned(md.nu[1]) * unsigned(md.nu[2]));
-        if (md.nu[0] > 0 && md.nu[1] > 0 && md.nu[2] > 0)
-          k_skeleton_gather<Q><<<grid, 128, 0, st>>>(md, yE, y, flag);
+        const SkeletonParts sp = skeleton_parts(md);
+        const int64_t nsk = sp.nA + sp.nB + sp.nC;
+        if (md.nu[0] > 0 && md.nu[1] > 0 && md.nu[2] > 0 && nsk > 0) {
+          if ((nsk + 255) / 256 > int64_t(INT32_MAX)) return hipErrorInvalidValue;
+          k_skeleton_gather<Q><<<unsigned((nsk + 255) / 256), 256, 0, st>>>(md, sp, yE, y, flag);
+        }
       }
       return hipGetLastError();
     }
