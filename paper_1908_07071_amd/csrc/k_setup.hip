@@ -9,6 +9,8 @@
 // same order reproduces them bit for bit.
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 #include "lor_internal.h"
 
 #pragma clang fp contract(off)
@@ -430,6 +432,38 @@ __global__ __launch_bounds__(256) void k_coarse_restrict(MeshDims md, const doub
   if (lane == 0) rc[c] = acc;
 }
 
+// The same sum with the degree fixed at compile time: each lane takes every
+// 64th point of the flattened (2p-1)^d support, all of its loads issued
+// together; the 1D hat weights come from LDS.
+template <int DIM, int P>
+__global__ __launch_bounds__(256) void k_coarse_restrict_p(MeshDims md, const double *__restrict__ gllx,
+                                                           const double *__restrict__ r,
+                                                           double *__restrict__ rc, int nc) {
+  constexpr int W1 = 2 * P - 1, W = DIM == 3 ? W1 * W1 * W1 : W1 * W1, NQ = (W + 63) / 64;
+  __shared__ double hw[W1];
+  if (int(threadIdx.x) < W1) hw[threadIdx.x] = hat_weight(gllx, P, int(threadIdx.x));
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= nc) return;  // no barrier follows
+  const int ncx = md.n[0] - 1, ncy = md.n[1] - 1;
+  const int v[3] = {c % ncx + 1, (c / ncx) % ncy + 1, DIM == 3 ? c / (ncx * ncy) + 1 : 0};
+  const int64_t sy = md.nu[0], sz = int64_t(md.nu[0]) * md.nu[1];
+  const double *src = r + (v[0] - 1) * P + sy * ((v[1] - 1) * P) + (DIM == 3 ? sz * ((v[2] - 1) * P) : 0);
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int q = lane + 64 * k;
+    if (q < W) {
+      const int ox = q % W1, oy = (q / W1) % W1, oz = DIM == 3 ? q / (W1 * W1) : 0;
+      const double wq = hw[ox] * hw[oy] * (DIM == 3 ? hw[oz] : 1.0);
+      acc += wq * src[ox + sy * oy + sz * oz];
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) rc[c] = acc;
+}
+
 // z = P_0 xc on the unknowns: a workgroup covers 64 unknowns of each of four
 // x-lines; lines (y, z) from the grid of blocks.
 template <int DIM>
@@ -649,10 +683,28 @@ hipError_t launch_coarse_restrict(const MeshDims &md, const double *gllx, const 
                                   double *rc, hipStream_t st) {
   const int nc = (md.n[0] - 1) * (md.n[1] - 1) * (md.dim == 3 ? md.n[2] - 1 : 1);
   if (nc <= 0) return hipSuccess;
+  const int nb = (nc + 3) / 4;
+#define LOR_RESTRICT_P(PP)                                                              \
+  case PP:                                                                              \
+    if (md.dim == 3) k_coarse_restrict_p<3, PP><<<nb, 256, 0, st>>>(md, gllx, r, rc, nc); \
+    else k_coarse_restrict_p<2, PP><<<nb, 256, 0, st>>>(md, gllx, r, rc, nc);             \
+    return hipGetLastError();
+  switch (md.p) {
+    LOR_RESTRICT_P(1)
+    LOR_RESTRICT_P(2)
+    LOR_RESTRICT_P(3)
+    LOR_RESTRICT_P(4)
+    LOR_RESTRICT_P(5)
+    LOR_RESTRICT_P(6)
+    LOR_RESTRICT_P(7)
+    LOR_RESTRICT_P(8)
+    default: break;
+  }
+#undef LOR_RESTRICT_P
   if (md.dim == 3)
-    k_coarse_restrict<3><<<(nc + 3) / 4, 256, 0, st>>>(md, gllx, r, rc, nc);
+    k_coarse_restrict<3><<<nb, 256, 0, st>>>(md, gllx, r, rc, nc);
   else
-    k_coarse_restrict<2><<<(nc + 3) / 4, 256, 0, st>>>(md, gllx, r, rc, nc);
+    k_coarse_restrict<2><<<nb, 256, 0, st>>>(md, gllx, r, rc, nc);
   return hipGetLastError();
 }
 
