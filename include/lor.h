@@ -354,11 +354,17 @@ int lor_pcg_solve(lor_handle_t *h, const double *b_dev, double *x_dev,
  * order; the patch corrections, and the operator outside 5 <= p+1 <= 8 in 3D,
  * are accumulated with float64 atomics, so the last bits of any two solves
  * may differ).  Every pair gets its own device
- * workspace; each pair's CG iterations are captured once into a HIP graph
- * (8 iterations per graph, kernels turn into no-ops after the device-side
- * convergence flag is set) and the graphs of all pairs are replayed on four
- * worker streams until every pair has converged or reached maxit, so that
- * small problems run concurrently and launch costs are paid once per chunk.
+ * workspace.  The CG iterations are captured once into HIP graphs (8
+ * iterations per graph, kernels turn into no-ops after a pair's device-side
+ * convergence flag is set), replayed on four worker streams until every
+ * pair has converged or reached maxit, so that small problems run
+ * concurrently and launch costs are paid once per chunk.  Where the
+ * preconditioner allows it (vertex patches with atomics, no patch
+ * network), a graph runs up to four right-hand sides of a problem in
+ * lockstep with one patch launch per iteration for all of them; with more
+ * such groups than streams, groups too small to fill the device with their
+ * patch launch share graphs, up to four problems of the same dimension and
+ * precision per patch launch.
  * A handle must not be used by another call during the batch (it may
  * appear several times in hs).
  * b, x: HOST arrays of nprob*nrhs DEVICE pointers (ndofs of the pair's
