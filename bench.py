@@ -640,6 +640,56 @@ def coefficient_measure(L, torch, rtol, n=16, p=4):
             "iters": out}
 
 
+def box_measure(L, torch, rtol):
+    """Box-patch preconditioners of Section 4.5 on strip meshes, float64:
+    milliseconds per application of B with each small box's whole V-cycle
+    in one workgroup (every such box in one launch) and with the per-level
+    launches (sweep_grid_rows = 1), B r compared element by element, and the
+    flexible-CG solve to rtol with the default path."""
+    from paper_1908_07071_amd import inputs
+    cases = [(2, 8, 7, 150.0, "vertex_iso"), (2, 8, 7, 150.0, "slabs3"), (3, 6, 4, 15.0, "vertex_iso")]
+    out = {}
+    for dim, n, p, A, mode in cases:
+        V = inputs.strip_vertices(n, A, dim=dim)
+        rec = {}
+        zs = []
+        for path, rows in (("one_workgroup", 0), ("per_level", 1)):
+            opt = L.lor_default_options()
+            opt.patch_mode = L.LOR_PATCH_VERTEX_ISO if mode == "vertex_iso" else L.LOR_PATCH_SLABS
+            opt.nslabs = 3 if mode == "slabs3" else 0
+            opt.sweep_grid_rows = rows
+            h = L.lor_setup(dim, n, V, p, options=opt)
+            N = L.lor_ndofs(h)
+            r = torch.tensor(inputs.gaussian_rhs(N, 5), device="cuda:0")
+            z = torch.empty_like(r)
+            reps = 20 if rows == 0 else 3
+            for _ in range(2):
+                L.lor_apply_P(h, r, z)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                L.lor_apply_P(h, r, z)
+            e1.record()
+            e1.synchronize()
+            rec[f"{path}_ms_per_apply"] = e0.elapsed_time(e1) / reps
+            zs.append(z.cpu())
+            if rows == 0:
+                x = torch.zeros_like(r)
+                info, ms = solve_timed(L, torch, h, r, x, rtol, 1)
+                rec.update({"N": N, "iters": info.iters, "ms_per_solve": ms,
+                            "status": STATUS_NAMES.get(info.status, str(info.status))})
+            L.lor_free(h)
+        rec["bit_identical"] = bool(torch.equal(zs[0], zs[1]))
+        key = f"{dim}d_n{n}_p{p}_A{A:g}_{mode}"
+        out[key] = rec
+        print(f"[bench] box {key}: {rec['one_workgroup_ms_per_apply']:.3f} ms per apply "
+              f"({rec['per_level_ms_per_apply']:.2f} per-level), {rec['iters']} it, "
+              f"{rec['ms_per_solve']:.1f} ms/solve", file=sys.stderr, flush=True)
+    return {"workload": f"strip meshes (two element rows of aspect A), float64 box-patch preconditioners, "
+                        f"flexible CG to {rtol:g}, Gaussian rhs", "cases": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -668,6 +718,8 @@ def main():
     ap.add_argument("--nn-apply", action="store_true",
                     help="only time one preconditioner application per mode (V-cycles, network, warm start) "
                          "with an untrained 32-channel network at --learned-n^3, p=6 (kernel profiling)")
+    ap.add_argument("--box", action="store_true",
+                    help="only time the box-patch preconditioners (Section 4.5 strip meshes, 2D and 3D)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -712,6 +764,9 @@ def main():
         return
     if args.nn_apply:
         print(json.dumps(nn_apply_measure(L, torch, args.learned_n)))
+        return
+    if args.box:
+        print(json.dumps(box_measure(L, torch, args.rtol)))
         return
 
     dim, n, p = args.dim, args.n, args.p
