@@ -429,6 +429,8 @@ int build_boxes(lor_handle &h, const std::vector<std::vector<double>> &hst, hipS
     }
     h.box_nfused = int(list.size());
     h.box_grid.L = L;
+    h.box_grid.lds_rows = 0;
+    for (int j : list) h.box_grid.lds_rows = std::max<int>(h.box_grid.lds_rows, int(h.boxes[j].lv[0].n));
     h.box_list_off.assign(size_t(h.box_ncolor) + 1, 0);
     h.box_unfused.assign(size_t(h.box_ncolor), 0);
     for (int c = 0; c < h.box_ncolor; ++c) {

@@ -22,6 +22,7 @@ namespace lor {
 constexpr int kBoxThreads = 256;       // threads per box workgroup
 constexpr int kBoxFuseRows = 1 << 16;  // largest finest-level box on the one-workgroup path
 constexpr int64_t kBoxWorkDoubles = int64_t(1) << 28;  // level vectors of those boxes, at most
+constexpr int kBoxLdsRows = 8192;      // sweeps on an LDS copy of the vector up to 64 KiB
 
 // One level of one box (device pointers into the handle's allocations).
 struct BoxLevelDesc {
@@ -47,6 +48,7 @@ struct BoxGrid {
   int64_t npts[kMaxLevels];
   int lng[kMaxLevels][3];
   int L;
+  int lds_rows;  // largest finest level of the boxes in the launch (LDS sweeps when <= kBoxLdsRows)
 };
 
 // V-cycles of `count` boxes, boxes[list[i]] for i < count, one workgroup

@@ -268,7 +268,10 @@ __device__ __forceinline__ void wg_sweep(const BoxLevelDesc &lv, const double *b
 // (pre-smoothing from zero, residual, restriction down to the deepest level
 // the box reaches, the exact solve there if it is T_p, then prolongation,
 // residual and post-smoothing back up), a barrier between steps.
-template <int DIM>
+// LDS: the vector a sweep pair works on sits in LDS (one level's worth,
+// g.lds_rows values), so that the neighbour reads of every dependency level
+// are LDS reads; the arithmetic is the same.
+template <int DIM, bool LDS>
 __global__ __launch_bounds__(kBoxThreads) void k_box_vcycle(const BoxDesc *__restrict__ boxes,
                                                             const int *__restrict__ list, BoxGrid g,
                                                             MeshDims md, const double *__restrict__ r,
@@ -294,15 +297,25 @@ __global__ __launch_bounds__(kBoxThreads) void k_box_vcycle(const BoxDesc *__res
     for (int64_t i = tid; i < l0.n; i += kBoxThreads) move_at<DIM, false>(i, md, lo, bd, r, nullptr, B(0));
     __syncthreads();
   }
+  extern __shared__ double xs[];
   for (int k = 0; k <= top; ++k) {
     const BoxLevelDesc lv = bx.lv[k];
     const BoxDims lo{lv.lo[0], lv.lo[1], lv.lo[2]}, bd{lv.m[0], lv.m[1], lv.m[2]};
     const double *bk = bvec(k);
     double *xk = xvec(k), *rk = R(k);
-    wg_sweep<DIM, true>(lv, bk, xk);
-    wg_sweep<DIM, false>(lv, xk, xk);
-    for (int64_t i = tid; i < lv.n; i += kBoxThreads)
-      residual_at<DIM>(i, g.stencil[k], g.npts[k], g.lng[k][0], g.lng[k][1], lo, bd, bk, xk, rk);
+    if constexpr (LDS) {
+      wg_sweep<DIM, true>(lv, bk, xs);
+      wg_sweep<DIM, false>(lv, xs, xs);
+      for (int64_t i = tid; i < lv.n; i += kBoxThreads) {
+        residual_at<DIM>(i, g.stencil[k], g.npts[k], g.lng[k][0], g.lng[k][1], lo, bd, bk, xs, rk);
+        xk[i] = xs[i];
+      }
+    } else {
+      wg_sweep<DIM, true>(lv, bk, xk);
+      wg_sweep<DIM, false>(lv, xk, xk);
+      for (int64_t i = tid; i < lv.n; i += kBoxThreads)
+        residual_at<DIM>(i, g.stencil[k], g.npts[k], g.lng[k][0], g.lng[k][1], lo, bd, bk, xk, rk);
+    }
     __syncthreads();
     if (k < K) {
       const int64_t nc = int64_t(lv.xf.mc[0]) * lv.xf.mc[1] * lv.xf.mc[2];
@@ -334,9 +347,19 @@ __global__ __launch_bounds__(kBoxThreads) void k_box_vcycle(const BoxDesc *__res
         residual_at<DIM>(i, g.stencil[k], g.npts[k], g.lng[k][0], g.lng[k][1], lo, bd, bk, xk, rk);
       __syncthreads();
     }
-    wg_sweep<DIM, true>(lv, rk, rk);
-    wg_sweep<DIM, false>(lv, rk, rk);
-    for (int64_t i = tid; i < lv.n; i += kBoxThreads) xk[i] += rk[i];
+    if constexpr (LDS) {
+      for (int64_t i = tid; i < lv.n; i += kBoxThreads) xs[i] = rk[i];
+      __syncthreads();
+      wg_sweep<DIM, true>(lv, xs, xs);
+      wg_sweep<DIM, false>(lv, xs, xs);
+      for (int64_t i = tid; i < lv.n; i += kBoxThreads) xk[i] += xs[i];
+    } else {
+      wg_sweep<DIM, true>(lv, rk, rk);
+      wg_sweep<DIM, false>(lv, rk, rk);
+      for (int64_t i = tid; i < lv.n; i += kBoxThreads) xk[i] += rk[i];
+    }
+    // the next level up reads this level's x; in LDS mode the next level's
+    // load into LDS must also wait for this level's last LDS reads
     if (k > 0) __syncthreads();
   }
 }
@@ -448,8 +471,14 @@ hipError_t launch_box_vcycles(int dim, const BoxDesc *boxes, const int *list, in
                               int direct, double *work, const double *flag, hipStream_t st) {
   if (count == 0) return hipSuccess;
   if ((dim != 2 && dim != 3) || count < 0 || g.L < 1 || g.L > kMaxLevels) return hipErrorInvalidValue;
-  if (dim == 3) k_box_vcycle<3><<<count, kBoxThreads, 0, st>>>(boxes, list, g, md, r, z, direct, work, flag);
-  else k_box_vcycle<2><<<count, kBoxThreads, 0, st>>>(boxes, list, g, md, r, z, direct, work, flag);
+  if (g.lds_rows > 0 && g.lds_rows <= kBoxLdsRows) {
+    const size_t lds = size_t(g.lds_rows) * sizeof(double);
+    if (dim == 3) k_box_vcycle<3, true><<<count, kBoxThreads, lds, st>>>(boxes, list, g, md, r, z, direct, work, flag);
+    else k_box_vcycle<2, true><<<count, kBoxThreads, lds, st>>>(boxes, list, g, md, r, z, direct, work, flag);
+  } else {
+    if (dim == 3) k_box_vcycle<3, false><<<count, kBoxThreads, 0, st>>>(boxes, list, g, md, r, z, direct, work, flag);
+    else k_box_vcycle<2, false><<<count, kBoxThreads, 0, st>>>(boxes, list, g, md, r, z, direct, work, flag);
+  }
   return hipGetLastError();
 }
 
