@@ -36,6 +36,7 @@ SOURCES = [
     ("nn_api.cpp", []),
     ("noalloc.hip", []),
     ("box_patch.cpp", ["-ffp-contract=off"]),
+    ("host_plan.cpp", []),
     ("k_single.hip", []),
 ]
 

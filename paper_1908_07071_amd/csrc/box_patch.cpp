@@ -19,6 +19,7 @@
 #include <cstring>
 #include <vector>
 
+#include "host_plan.h"
 #include "lor_handle.h"
 
 namespace {
@@ -378,24 +379,17 @@ int build_boxes(lor_handle &h, const std::vector<std::vector<double>> &hst, hipS
     }
   // colours (greedy, in box order): boxes of one colour have disjoint
   // level-0 point ranges, so their corrections can be added side by side
-  h.box_color.assign(h.boxes.size(), 0);
-  h.box_ncolor = h.boxes.empty() ? 0 : 1;
-  if (!single && h.boxes.size() > 1) {
-    auto overlap = [&](const SingleLevelDev &a, const SingleLevelDev &b) {
-      if (a.n <= 0 || b.n <= 0) return false;
-      for (int d = 0; d < dim; ++d)
-        if (a.lo[d] + a.m[d] <= b.lo[d] || b.lo[d] + b.m[d] <= a.lo[d]) return false;
-      return true;
-    };
+  {
+    std::vector<BoxRange> rg(h.boxes.size());
     for (size_t j = 0; j < h.boxes.size(); ++j) {
-      std::vector<char> used(h.boxes.size() + 1, 0);
-      for (size_t i = 0; i < j; ++i)
-        if (overlap(h.boxes[i].lv[0], h.boxes[j].lv[0])) used[h.box_color[i]] = 1;
-      int c = 0;
-      while (used[c]) ++c;
-      h.box_color[j] = c;
-      h.box_ncolor = std::max(h.box_ncolor, c + 1);
+      const SingleLevelDev &l0 = h.boxes[j].lv[0];
+      for (int d = 0; d < 3; ++d) {
+        rg[j].lo[d] = l0.lo[d];
+        rg[j].m[d] = l0.m[d];
+      }
+      rg[j].n = single ? 0 : l0.n;  // B(1): one box, one colour
     }
+    h.box_color = greedy_box_colours(rg, dim, &h.box_ncolor);
   }
   // boxes for one workgroup each: no dependency level over `big` rows, a
   // finest level of at most kBoxFuseRows rows, level vectors of their own

@@ -13,6 +13,7 @@
 #include <tuple>
 #include <vector>
 
+#include "host_plan.h"
 #include "lor_handle.h"
 
 static_assert(LOR_ORD_MDF == ORD_MDF && LOR_ORD_NATURAL == ORD_NATURAL && LOR_ORD_RCM == ORD_RCM,
@@ -1522,37 +1523,17 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
     // by dimension and precision, similar patch sizes together (the launch
     // reserves the largest patch's LDS for every patch), up to kMaxJobs
     // parts and kJobBlocks patch blocks per group
-    const bool share = int(parts.size()) > kBatchStreams;
-    auto blocks = [&](const Part &pt) { return int64_t(hs[pt.first / nrhs]->J + 7) / 8 * 8 * pt.n; };
-    std::vector<size_t> small;
+    std::vector<BatchPart> bp(parts.size());
     for (size_t a = 0; a < parts.size(); ++a) {
-      if (share && parts[a].multi && blocks(parts[a]) < kJobBlocks) {
-        small.push_back(a);
-        continue;
-      }
-      Group g;
-      g.parts.push_back(parts[a]);
-      g.cost = parts[a].cost;
-      groups.push_back(g);
-    }
-    auto key = [&](size_t a) {
       const lor_handle *h = hs[parts[a].first / nrhs];
-      return std::make_tuple(h->dim, h->pa.fp32, -h->pa.lds_total);
-    };
-    std::stable_sort(small.begin(), small.end(), [&](size_t x, size_t y) { return key(x) < key(y); });
-    for (size_t i = 0; i < small.size();) {
+      bp[a] = BatchPart{parts[a].multi, h->dim, h->pa.fp32, h->pa.lds_total,
+                        int64_t(h->J + 7) / 8 * 8 * parts[a].n, parts[a].cost};
+    }
+    for (const std::vector<int> &pl : plan_batch_groups(bp, kBatchStreams, kMaxJobs, kJobBlocks)) {
       Group g;
-      int64_t nb = 0;
-      const lor_handle *h0 = hs[parts[small[i]].first / nrhs];
-      while (i < small.size() && int(g.parts.size()) < kMaxJobs) {
-        const Part &pt = parts[small[i]];
-        const lor_handle *h = hs[pt.first / nrhs];
-        if (!g.parts.empty() && (h->dim != h0->dim || h->pa.fp32 != h0->pa.fp32 || nb + blocks(pt) > kJobBlocks))
-          break;
-        g.parts.push_back(pt);
-        g.cost += pt.cost;
-        nb += blocks(pt);
-        ++i;
+      for (int a : pl) {
+        g.parts.push_back(parts[a]);
+        g.cost += parts[a].cost;
       }
       groups.push_back(g);
     }
@@ -1574,17 +1555,11 @@ int lor_pcg_solve_batch(lor_handle_t *const *hs, int nprob, int nrhs, const doub
     // cached workspaces
     std::vector<std::pair<lor_handle *, int>> used;
     // the costliest group first, each to the least loaded stream
-    std::vector<size_t> order(groups.size());
-    for (size_t gi = 0; gi < order.size(); ++gi) order[gi] = gi;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t a, size_t b2) { return groups[a].cost > groups[b2].cost; });
-    std::vector<double> load(ns, 0.0);
-    for (size_t gi : order) {
-      int t = 0;
-      for (int u = 1; u < ns; ++u)
-        if (load[u] < load[t]) t = u;
-      load[t] += groups[gi].cost;
-      groups[gi].st = streams[t];
+    std::vector<double> costs(groups.size());
+    for (size_t gi = 0; gi < groups.size(); ++gi) costs[gi] = groups[gi].cost;
+    const std::vector<int> gs = assign_streams(costs, ns);
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      groups[gi].st = streams[gs[gi]];
       for (const Part &pt : groups[gi].parts)
         for (int k = pt.first; k < pt.first + pt.n; ++k) pairs[k].st = groups[gi].st;
     }
