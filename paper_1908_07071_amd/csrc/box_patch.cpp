@@ -581,8 +581,9 @@ int apply_boxes(lor_handle *h, const double *r, double *z, const double *flag, h
       for (hipStream_t t : h->box_st) SCHK(hipStreamWaitEvent(t, h->box_ev[NS], 0));
     }
     const int l0 = h->box_list_off[c], cnt = h->box_list_off[c + 1] - l0;
-    SCHK(launch_box_add(h->dim, h->d_box_desc, h->d_box_list + h->box_nfused + l0, cnt, h->md, h->d_box_w, z,
-                        h->d_box_work, flag, st));
+    if (cnt > 0)
+      SCHK(launch_box_add(h->dim, h->d_box_desc, h->d_box_list + h->box_nfused + l0, cnt, h->md, h->d_box_w,
+                          z, h->d_box_work, flag, st));
     int turn = 0;
     for (size_t j = 0; h->box_unfused[c] > 0 && j < h->boxes.size(); ++j) {
       if (h->box_color[j] != c || h->box_fused[j]) continue;
