@@ -437,6 +437,7 @@ int build_boxes(lor_handle &h, const std::vector<std::vector<double>> &hst, hipS
     }
     if (h.box_nfused > 0) {
       SCHK(upload(h, &h.d_box_list, list, st));
+      SCHK(hipStreamSynchronize(st));  // `list` goes out of scope below
       SCHK(h.alloc(&h.d_box_desc, nb));
       SCHK(h.alloc(&h.d_box_work, size_t(total)));
       const int rc = refresh_box_descs(h, st);
