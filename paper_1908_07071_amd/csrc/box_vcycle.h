@@ -7,8 +7,10 @@
 // then one workgroup walks every sweep level by level (a barrier between
 // levels) and does the residuals, transfers, the exact solve on its part of
 // T_p and the gather from r itself, with the same arithmetic, row for row,
-// as the separate launches of the larger boxes.  Each box keeps its own
-// level vectors, so all of them run at once; the corrections are then added
+// as the separate launches of the larger boxes (each sweep pair on an LDS
+// copy of its vector when the launch's largest box fits kBoxLdsRows).  Each
+// box keeps its own level vectors, so all of them run at once; the
+// corrections are then added
 // to z one colour of boxes per launch (boxes of one colour have disjoint
 // level-0 point ranges), in the order the per-level path adds them.
 #pragma once
