@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "host_plan.h"
@@ -435,6 +436,44 @@ int build_boxes(lor_handle &h, const std::vector<std::vector<double>> &hst, hipS
       }
       h.box_list_off[c + 1] = int(list.size()) - h.box_nfused;
     }
+    // every box on the one-workgroup path: the additions of all colours in
+    // one launch, each point's boxes in colour order
+    h.box_add_npt = 0;
+    bool all = !single && h.box_nfused > 0;
+    for (int c : h.box_unfused) all = all && c == 0;
+    if (all) {
+      std::vector<std::pair<int64_t, int64_t>> ent;  // (point, offset of its x value)
+      for (size_t t = size_t(h.box_nfused); t < list.size(); ++t) {
+        const int j = list[t];
+        const SingleLevelDev &l0 = h.boxes[j].lv[0];
+        const int64_t vo = h.box_vo[size_t(j) * L];
+        for (int64_t i = 0; i < l0.n; ++i) {
+          const int ix = int(i % l0.m[0]), iy = int((i / l0.m[0]) % l0.m[1]),
+                    iz = int(i / (int64_t(l0.m[0]) * l0.m[1]));
+          const int64_t u = (ix + l0.lo[0] - 1) +
+                            int64_t(h.md.nu[0]) * ((iy + l0.lo[1] - 1) + (dim == 3 ? int64_t(h.md.nu[1]) * (iz + l0.lo[2] - 1) : 0));
+          ent.push_back({u, vo + i});
+        }
+      }
+      std::stable_sort(ent.begin(), ent.end(),
+                       [](const std::pair<int64_t, int64_t> &a, const std::pair<int64_t, int64_t> &b) {
+                         return a.first < b.first;
+                       });
+      std::vector<int64_t> ptr(1, 0), pts, src(ent.size());
+      for (size_t e = 0; e < ent.size(); ++e) {
+        if (e == 0 || ent[e].first != ent[e - 1].first) {
+          if (e > 0) ptr.push_back(int64_t(e));
+          pts.push_back(ent[e].first);
+        }
+        src[e] = ent[e].second;
+      }
+      ptr.push_back(int64_t(ent.size()));
+      h.box_add_npt = int64_t(pts.size());
+      SCHK(upload(h, &h.d_add_ptr, ptr, st));
+      SCHK(upload(h, &h.d_add_pts, pts, st));
+      SCHK(upload(h, &h.d_add_src, src, st));
+      SCHK(hipStreamSynchronize(st));
+    }
     if (h.box_nfused > 0) {
       SCHK(upload(h, &h.d_box_list, list, st));
       SCHK(hipStreamSynchronize(st));  // `list` goes out of scope below
@@ -573,6 +612,11 @@ int apply_boxes(lor_handle *h, const double *r, double *z, const double *flag, h
   SCHK(launch_box_vcycles(h->dim, h->d_box_desc, h->d_box_list, h->box_nfused, h->box_grid, h->md, r, z,
                           single ? 1 : 0, h->d_box_work, flag, st));
   if (single) return LOR_OK;
+  if (h->box_add_npt > 0) {  // every box above: all additions in one launch
+    SCHK(launch_box_add_points(h->d_add_ptr, h->d_add_pts, h->d_add_src, h->box_add_npt, h->d_box_w, z,
+                               h->d_box_work, flag, st));
+    return LOR_OK;
+  }
   constexpr int NS = lor_handle::kBoxStreams;
   const bool side = !h->capturing && h->box_st[0] != nullptr;
   for (int c = 0; c < h->box_ncolor; ++c) {

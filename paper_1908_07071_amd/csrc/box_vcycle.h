@@ -68,4 +68,12 @@ hipError_t launch_box_add(int dim, const BoxDesc *boxes, const int *list, int co
                           const MeshDims &md, const double *w, double *z, const double *work,
                           const double *flag, hipStream_t st);
 
+// z_u += w_u x over the boxes holding point u, every point in one launch:
+// points pts[t] (L-vector indices, t < npt), their entries
+// [ptr[t], ptr[t+1]) of src (offsets in `work` of the boxes' level-0 x
+// values, in colour order).
+hipError_t launch_box_add_points(const int64_t *ptr, const int64_t *pts, const int64_t *src, int64_t npt,
+                                 const double *w, double *z, const double *work, const double *flag,
+                                 hipStream_t st);
+
 }  // namespace lor

@@ -199,8 +199,8 @@ __device__ __forceinline__ void move_at(int64_t i, const MeshDims &md, BoxDims l
   const int ix = int(i % bd.m0), iy = int((i / bd.m0) % bd.m1), iz = int(i / (int64_t(bd.m0) * bd.m1));
   const int64_t u = (ix + lo.m0 - 1) +
                     int64_t(md.nu[0]) * ((iy + lo.m1 - 1) + (DIM == 3 ? int64_t(md.nu[1]) * (iz + lo.m2 - 1) : 0));
-  if (SCATTER)
-    dst[u] += w ? w[u] * src[i] : src[i];
+  if (SCATTER)  // one fused multiply-add with a weight, as k_box_add_points does it
+    dst[u] = w ? __builtin_fma(w[u], src[i], dst[u]) : dst[u] + src[i];
   else
     dst[i] = src[u];
 }
@@ -379,6 +379,30 @@ __global__ __launch_bounds__(kBoxThreads) void k_box_add(const BoxDesc *__restri
   for (int64_t i = threadIdx.x; i < l0.n; i += kBoxThreads) move_at<DIM, true>(i, md, lo, bd, x0, w, z);
 }
 
+// z_u += w_u x over every one-workgroup box holding point u, one thread per
+// point, the boxes in colour order (the order of the per-colour launches)
+__global__ __launch_bounds__(256) void k_box_add_points(const int64_t *__restrict__ ptr,
+                                                        const int64_t *__restrict__ pts,
+                                                        const int64_t *__restrict__ src, int64_t npt,
+                                                        const double *__restrict__ w,
+                                                        double *__restrict__ z,
+                                                        const double *__restrict__ work,
+                                                        const double *flag) {
+  if (flag && flag[S_DONE] != 0.0) return;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < npt;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t u = pts[t];
+    double acc = z[u];
+    if (w) {
+      const double wu = w[u];
+      for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) acc = __builtin_fma(wu, work[src[e]], acc);
+    } else {
+      for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) acc = acc + work[src[e]];
+    }
+    z[u] = acc;
+  }
+}
+
 inline int blocks_for(int64_t n, int bs) {
   int64_t g = (n + bs - 1) / bs;
   return int(g > 4096 ? 4096 : (g < 1 ? 1 : g));
@@ -489,6 +513,14 @@ hipError_t launch_box_add(int dim, const BoxDesc *boxes, const int *list, int co
   if ((dim != 2 && dim != 3) || count < 0) return hipErrorInvalidValue;
   if (dim == 3) k_box_add<3><<<count, kBoxThreads, 0, st>>>(boxes, list, md, w, z, work, flag);
   else k_box_add<2><<<count, kBoxThreads, 0, st>>>(boxes, list, md, w, z, work, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_box_add_points(const int64_t *ptr, const int64_t *pts, const int64_t *src, int64_t npt,
+                                 const double *w, double *z, const double *work, const double *flag,
+                                 hipStream_t st) {
+  if (npt <= 0) return hipSuccess;
+  k_box_add_points<<<blocks_for(npt, 256), 256, 0, st>>>(ptr, pts, src, npt, w, z, work, flag);
   return hipGetLastError();
 }
 

@@ -1260,6 +1260,7 @@ int lor_bind_workspace(lor_handle_t *h, void *dev_ptr, size_t bytes, void *strea
       for (double *&v : h->box_sr[t]) set(v);
     }
     set(h->d_box_w), set(h->d_box_desc), set(h->d_box_list), set(h->d_box_work);
+    set(h->d_add_ptr), set(h->d_add_pts), set(h->d_add_src);
   };
   apply(false);  // dry run: resolve every pointer before anything changes
   if (!ok) return LOR_ESTATE;

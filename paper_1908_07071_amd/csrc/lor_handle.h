@@ -109,6 +109,10 @@ struct lor_handle {
   int *d_box_list = nullptr;
   double *d_box_work = nullptr;       // the one-workgroup boxes' level vectors
   BoxGrid box_grid{};
+  // every box on the one-workgroup path: all corrections added in one launch,
+  // per L-vector point its boxes in colour order (launch_box_add_points)
+  int64_t box_add_npt = 0;
+  int64_t *d_add_ptr = nullptr, *d_add_pts = nullptr, *d_add_src = nullptr;
   // host copies for parity export
   std::vector<int32_t> order_all, order_off, sched_all, sched_off;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
